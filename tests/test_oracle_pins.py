@@ -1,0 +1,309 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: textbook
+closed forms, exact conservation, an exact steady solution, analytic decay
+rates, symmetries of the cavity problem and the sense of the buoyancy force.
+"""
+import math
+
+import numpy as np
+import pytest
+
+W15 = np.array([2 / 9] + [1 / 9] * 6 + [1 / 72] * 8)
+EX15 = np.array([0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1])
+EY15 = np.array([0, 0, 0, 1, -1, 0, 0, 1, 1, -1, -1, 1, 1, -1, -1])
+EZ15 = np.array([0, 0, 0, 0, 0, 1, -1, 1, 1, 1, 1, -1, -1, -1, -1])
+E15 = np.stack([EX15, EY15, EZ15], axis=1)
+
+
+# --------------------------------------------------------------------------
+# Single-cell closed forms and conservation
+# --------------------------------------------------------------------------
+
+def test_rest_equilibria_are_the_textbook_weights(oracle):
+    """D3Q15 at rest: (2/9, 1/9 x6, 1/72 x8) scaled by rho; D3Q7 scalar at
+    rest with c_sphi^2 = 1/3: (0, 1/6 x6); with 1/4: (1/4, 1/8 x6)."""
+    f, g = oracle.equilibrium(7, 1.3, [0, 0, 0], 0.7)
+    assert np.allclose(f, 1.3 * W15, rtol=0, atol=1e-15)
+    assert np.allclose(g, 0.7 * np.array([0] + [1 / 6] * 6), rtol=0, atol=1e-15)
+    _, g = oracle.equilibrium(7, 1.0, [0, 0, 0], 1.0, cs2=0.25)
+    assert np.allclose(g, [0.25] + [0.125] * 6, rtol=0, atol=1e-15)
+    _, g15 = oracle.equilibrium(15, 1.0, [0, 0, 0], 1.0)
+    assert np.allclose(g15, W15, rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_flow_equilibrium_moments_are_maxwellian(oracle, seed):
+    """Moments of order 0..2 of the flow equilibrium are rho, rho u and
+    rho (I/3 + u u) (isothermal Maxwellian, c_s^2 = 1/3)."""
+    rng = np.random.default_rng(seed)
+    rho, u = 1 + 0.1 * rng.standard_normal(), 0.1 * rng.standard_normal(3)
+    f, _ = oracle.equilibrium(7, rho, u, 0.0)
+    assert abs(f.sum() - rho) < 1e-14
+    assert np.allclose(E15.T @ f, rho * u, atol=1e-15)
+    P = np.einsum("a,ai,aj->ij", f, E15, E15)
+    assert np.allclose(P, rho * (np.eye(3) / 3 + np.outer(u, u)), atol=1e-14)
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_d3q7_equilibrium_closed_form_and_fixed_point(oracle, seed):
+    """D3Q7 scalar equilibrium with central moments (T; 0; cs2 T I):
+    g_{+-x} = T (cs2 + ux^2 +- ux)/2, g0 = T (1 - 3 cs2 - |u|^2); it is left
+    unchanged by the collision for any rates."""
+    rng = np.random.default_rng(10 + seed)
+    T, u, cs2 = rng.uniform(-0.5, 0.5), 0.1 * rng.standard_normal(3), rng.choice([1 / 3, 0.25])
+    ref = np.empty(7)
+    ref[0] = T * (1 - 3 * cs2 - u @ u)
+    for d in range(3):
+        ref[1 + 2 * d] = T * (cs2 + u[d] ** 2 + u[d]) / 2
+        ref[2 + 2 * d] = T * (cs2 + u[d] ** 2 - u[d]) / 2
+    _, g = oracle.equilibrium(7, 1.0, u, T, cs2=cs2)
+    assert np.allclose(g, ref, rtol=0, atol=1e-15)
+    w = np.concatenate([[0], rng.uniform(0.2, 1.95, 6)])
+    assert np.allclose(oracle.collide_thermal(7, ref, u, cs2, w), ref, rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_collisions_conserve_what_they_must(oracle, seed):
+    """Thermal collision conserves sum g exactly (h0 = 0, R = 0); the flow
+    collision conserves mass and adds exactly F to the momentum (eq. 2a/3)."""
+    rng = np.random.default_rng(100 + seed)
+    g = 0.1 * rng.standard_normal(15)
+    u = 0.1 * rng.standard_normal(3)
+    w = np.concatenate([[0], rng.uniform(0.2, 1.95, 14)])
+    out = oracle.collide_thermal(15, g, u, 1 / 3, w)
+    assert abs(out.sum() - g.sum()) < 1e-15
+    out7 = oracle.collide_thermal(7, g[:7], u, 1 / 3, w[:7])
+    assert abs(out7.sum() - g[:7].sum()) < 1e-15
+
+    f = W15 * (1 + 0.05 * rng.standard_normal(15))
+    F = 1e-3 * rng.standard_normal(3)
+    wf = np.concatenate([np.zeros(4), rng.uniform(0.2, 1.95, 11)])
+    fo, rho, _ = oracle.collide_flow(f, F, wf)
+    assert abs(fo.sum() - f.sum()) < 2e-15
+    assert np.allclose(E15.T @ fo, E15.T @ f + F, rtol=0, atol=1e-15)
+
+
+def test_thermal_first_moment_relaxes_with_omega_T(oracle):
+    """The non-equilibrium heat flux (first central moment) is multiplied by
+    (1 - omega_T) per collision, which is what fixes D = cs2 (1/w - 1/2)."""
+    rng = np.random.default_rng(7)
+    g = 0.1 * rng.standard_normal(7)
+    u = 0.05 * rng.standard_normal(3)
+    wT = 1.37
+    out = oracle.collide_thermal(7, g, u, 1 / 3, [0, wT, wT, wT, 1, 1, 1])
+    E7 = np.array([[0, 0, 0], [1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1]])
+    c_in = E7.T @ g - g.sum() * u
+    c_out = E7.T @ out - out.sum() * u
+    assert np.allclose(c_out, (1 - wT) * c_in, rtol=0, atol=1e-15)
+
+
+# --------------------------------------------------------------------------
+# Whole-cavity pins
+# --------------------------------------------------------------------------
+
+def _linear_T(p):
+    x = np.arange(p.nx) + 0.5
+    T1 = p.T_hot + (p.T_cold - p.T_hot) * x / p.nx
+    return np.broadcast_to(T1, (p.nz, p.ny, p.nx)).copy()
+
+
+def test_pure_conduction_is_exact_on_d3q7(oracle):
+    """Without buoyancy (g beta = 0) the linear profile between the Dirichlet
+    walls is the exact steady state of the D3Q7 scheme with anti-bounce-back
+    and adiabatic bounce-back walls; the wall flux gives Nu = 1."""
+    p = oracle.cavity_params(8, 1e3)
+    p.gbeta = 0.0
+    p.omega_nu = 1.5
+    p.omega_T = 1.0  # alpha = 1/6: fast diffusion
+    p.alpha = (1 / 3) * (1 / p.omega_T - 0.5)
+    F, G = oracle.rest_state(p)
+    F, G, mac = oracle.run(p, 1500, F, G)
+    T = mac[4]
+    assert np.max(np.abs(T - _linear_T(p))) < 1e-12
+    assert np.max(np.abs(mac[1:4])) < 1e-15  # fluid stays at rest
+    nh, nc = oracle.nusselt(p, G)
+    assert np.max(np.abs(nh - 1)) < 1e-10 and np.max(np.abs(nc - 1)) < 1e-10
+
+
+def test_pure_conduction_d3q15_converges_to_nu_1(oracle):
+    """D3Q15 scalar with bounce-back on the adiabatic faces reflects the
+    diagonal links' heat flux, so conduction is exact only away from those
+    faces: the face-mean Nu approaches 1 as the grid is refined."""
+    devs = []
+    for n in (6, 12):
+        p = oracle.cavity_params(n, 1e3, qt=15)
+        p.gbeta = 0.0
+        p.omega_nu = 1.5
+        p.omega_T = 1.0
+        p.alpha = (1 / 3) * (1 / p.omega_T - 0.5)
+        F, G = oracle.rest_state(p)
+        F, G, mac = oracle.run(p, 60 * n * n // 4 + 400, F, G)
+        nh, nc = oracle.nusselt(p, G)
+        assert abs(nh.mean() - nc.mean()) < 1e-8
+        devs.append(abs(nh.mean() - 1))
+        # the centre column (away from the adiabatic faces) is linear
+        T = mac[4][n // 2, n // 2]
+        assert np.max(np.abs(T - _linear_T(p)[0, 0])) < 0.05
+    assert devs[1] < 0.75 * devs[0]
+
+
+def _decay_rate(series, t):
+    return -np.polyfit(t, np.log(np.abs(series)), 1)[0]
+
+
+@pytest.mark.parametrize("qt", [7, 15])
+def test_thermal_mode_decays_at_alpha_k2(oracle, qt):
+    """A sin(pi (i+1/2)/N) temperature mode between two T = 0 walls decays at
+    alpha (pi/N)^2 (eq. 23 fixes alpha from omega_T), up to O((pi/N)^2).
+    y and z are periodic so the mode is one-dimensional."""
+    errs = []
+    for n in (16, 32):
+        p = oracle.cavity_params(n, 1e3, qt=qt, ny=3, nz=3)
+        p.T_hot = p.T_cold = 0.0
+        p.periodic = 6
+        p.gbeta = 0.0
+        p.omega_nu = 1.5
+        p.omega_T = 1.2
+        alpha = p.cs2T * (1 / p.omega_T - 0.5)
+        x = np.arange(n) + 0.5
+        T0 = np.broadcast_to(np.sin(np.pi * x / n), (3, 3, n)).copy()
+        F, G = oracle.init_equilibrium(p, T=T0)
+        amps, ts = [], []
+        t = 0
+        F, G, mac = oracle.run(p, 20, F, G)
+        t += 20
+        for _ in range(6):
+            F, G, mac = oracle.run(p, n * n // 8, F, G)
+            t += n * n // 8
+            amps.append(np.sum(mac[4][1, 1] * np.sin(np.pi * x / n)))
+            ts.append(t)
+        lam = _decay_rate(np.array(amps), np.array(ts))
+        errs.append(abs(lam / (alpha * (np.pi / n) ** 2) - 1))
+    assert errs[0] < 0.02 and errs[1] < 0.006
+    assert errs[1] < errs[0] / 3  # second-order convergence of the rate
+
+
+def test_shear_wave_decays_at_nu_k2(oracle):
+    """Periodic box: u_y = A sin(2 pi x / N) decays at nu k^2 with
+    nu = c_s^2 (1/omega - 1/2), c_s^2 = 1/3 (Appendix A)."""
+    errs = []
+    for n in (16, 32):
+        p = oracle.cavity_params(n, 1e3, ny=2, nz=2)
+        p.periodic = 7
+        p.gbeta = 0.0
+        p.omega_nu = 1.4
+        nu = (1 / p.omega_nu - 0.5) / 3
+        x = np.arange(n)
+        k = 2 * np.pi / n
+        uy = np.broadcast_to(1e-3 * np.sin(k * x), (2, 2, n)).copy()
+        F, G = oracle.init_equilibrium(p, uy=uy, T=np.zeros_like(uy))
+        F, G, mac = oracle.run(p, 20, F, G)
+        t, amps, ts = 20, [], []
+        for _ in range(6):
+            F, G, mac = oracle.run(p, n * n // 10, F, G)
+            t += n * n // 10
+            amps.append(np.sum(mac[2][0, 0] * np.sin(k * x)))
+            ts.append(t)
+        lam = _decay_rate(np.array(amps), np.array(ts))
+        errs.append(abs(lam / (nu * k * k) - 1))
+    assert errs[0] < 0.03 and errs[1] < 0.008
+    assert errs[1] < errs[0] / 3
+
+
+def test_total_mass_is_conserved_in_the_cavity(oracle):
+    """Bounce-back walls and a mass-conserving collision: sum rho is constant."""
+    p = oracle.cavity_params(10, 1e4, ny=8, nz=6)
+    F, G = oracle.rest_state(p)
+    m0 = F.sum()
+    F, G, mac = oracle.run(p, 300, F, G)
+    assert abs(F.sum() - m0) < 1e-11 * m0
+    assert abs(mac[0].sum() - m0) < 1e-11 * m0
+
+
+@pytest.mark.parametrize("qt", [7, 15])
+def test_cavity_symmetries(oracle, qt):
+    """The differentially heated cavity is invariant under the rotation
+    (x, z) -> (L - x, L - z), which maps T -> -T, (ux, uy, uz) ->
+    (-ux, uy, -uz), and under the mirror y -> L - y, which maps uy -> -uy."""
+    p = oracle.cavity_params(10, 1e4, u0=0.1, qt=qt, ny=7, nz=9, omega_bulk=1.0)
+    F, G = oracle.rest_state(p)
+    F, G, mac = oracle.run(p, 150, F, G)
+    rho, ux, uy, uz, T = mac
+    rot = lambda a: a[::-1, :, ::-1]
+    mir = lambda a: a[:, ::-1, :]
+    sc = max(np.max(np.abs(uz)), 1e-30)
+    assert np.max(np.abs(T + rot(T))) < 1e-13
+    assert np.max(np.abs(rho - rot(rho))) < 1e-13
+    assert np.max(np.abs(ux + rot(ux))) < 1e-12 * sc
+    assert np.max(np.abs(uz + rot(uz))) < 1e-12 * sc
+    assert np.max(np.abs(uy - rot(uy))) < 1e-12 * sc
+    assert np.max(np.abs(uy + mir(uy))) < 1e-12 * sc
+    assert np.max(np.abs(T - mir(T))) < 1e-13
+
+
+def test_hot_fluid_rises(oracle):
+    """F = g beta (T - T0) z-hat (Sec. 3): fluid next to the hot wall moves up
+    and next to the cold wall moves down."""
+    p = oracle.cavity_params(12, 1e4, u0=0.1, omega_bulk=1.0)
+    F, G = oracle.rest_state(p)
+    F, G, mac = oracle.run(p, 200, F, G)
+    uz = mac[3]
+    mid = p.nz // 2
+    assert uz[mid, :, 0].mean() > 0
+    assert uz[mid, :, -1].mean() < 0
+    # and it turns toward the cold wall at the top
+    assert mac[1][-1, :, :].mean() > 0
+
+
+def test_steady_cavity_energy_balance(oracle):
+    """At steady state the heat entering at the hot wall leaves at the cold
+    wall (Nu_hot = Nu_cold) and convection makes Nu > 1."""
+    p = oracle.cavity_params(10, 3e3, u0=0.15)
+    assert p.omega_nu < 1.76
+    F, G = oracle.rest_state(p)
+    F, G, mac = oracle.run(p, 6000, F, G)
+    F2, G2, mac2 = oracle.run(p, 200, F, G)
+    assert np.max(np.abs(mac2[4] - mac[4])) < 1e-8  # steady
+    nh, nc = oracle.nusselt(p, G2)
+    assert abs(nh.mean() - nc.mean()) < 1e-6
+    assert nh.mean() > 1.1
+
+
+def test_fp64_oracle_rounding_is_small(oracle):
+    """The FP64 oracle and its extended-precision twin agree after 400 steps
+    of the 16^3 Ra = 1e3 cavity to well under the 1e-12 normalised tolerance
+    used for the GPU's FP64 mode (u is a small difference of O(0.1)
+    populations, so its normalised noise is the largest)."""
+    p = oracle.cavity_params(16, 1e3)
+    F, G = oracle.rest_state(p)
+    _, _, m64 = oracle.run(p, 400, F, G)
+    _, _, mld = oracle.run(p, 400, F, G, long_double=True)
+    umax = np.max(np.abs(mld[1:4]))
+    for k in range(5):
+        scale = umax if 1 <= k <= 3 else np.max(np.abs(mld[k]))
+        err = np.max(np.abs(m64[k] - mld[k])) / scale
+        assert err < 5e-13, (k, err)
+
+
+def _periodic_noise_growth(oracle, omega_nu, steps, **kw):
+    p = oracle.cavity_params(8, 1e3, **kw)
+    p.periodic = 7
+    p.gbeta = 0.0
+    p.omega_nu = omega_nu
+    F, G = oracle.rest_state(p)
+    F = F + 1e-10 * np.random.default_rng(5).standard_normal(F.shape)
+    _, _, m1 = oracle.run(p, 40, F, G)
+    _, _, m2 = oracle.run(p, steps, F, G)
+    return np.max(np.abs(m2[1:4])) / np.max(np.abs(m1[1:4]))
+
+
+def test_linear_stability_envelope_of_the_flow_kernel(oracle):
+    """Records the stability facts behind two relaxation readings.  With the
+    bulk rate equal to the shear rate and the factorised 4th-order
+    equilibrium, noise on a fluid at rest decays for omega_nu = 1.75 but grows
+    for 1.88 (linear analysis: threshold near 1.78).  With the bulk rate 1 and
+    the Maxwellian 4th-order equilibrium rho/9 it decays even at 1.96."""
+    assert _periodic_noise_growth(oracle, 1.75, 400) < 1.0
+    assert _periodic_noise_growth(oracle, 1.88, 400) > 1e3
+    assert _periodic_noise_growth(oracle, 1.96, 400, omega_bulk=1.0, fourth_maxwell=1) < 1.0
