@@ -1,0 +1,186 @@
+"""Throughput of the fused cascaded double-distribution LBM step on one MI355X.
+
+Workload: the differentially heated 512^3 cavity at Ra = 1e6, Pr = 0.71,
+u0 = 0.05, D3Q15 flow + D3Q7 scalar, FP32 arithmetic, distributions stored in
+FP32 (headline) and in shifted FP16 (second line of the same record),
+started from rest.  One step = one launch of the fused stream-collide kernel
+over all cells (pull streaming, walls, Boussinesq coupling, both cascaded
+collisions, store).
+
+Prints one JSON line.  `value` is whole-job MLUPS (million lattice-cell
+updates per second) with the state resident in HBM; `roofline` relates the
+step kernel's algorithmic bytes per launch ((15 + 7) values read and written
+per cell) to its average launch time measured with HIP events on the stream
+the kernel runs on; `cpu_baseline` times the CPU oracle on a bounded sample
+of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "coupled flow+thermal MLUPS & % HBM roofline; steps-to-steady learned vs plain"
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes_per_cell(precision, qt=7):
+    vb = {"fp32": 4, "fp16": 2, "fp64": 8}[precision]
+    return 2 * (15 + qt) * vb
+
+
+def time_variant(n, ra, precision, steps, warmup, block=None, log=print):
+    import torch
+    from paper_1710_04751_amd import solver as S
+
+    stream = torch.cuda.Stream()
+    params = S.make_params(n, ra, precision=precision)
+    params.block_x, params.block_y = block or (256, 1)
+    cav = S.Cavity(params, stream=stream)
+    kname = cav.kernel_name()
+    cav.step(warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    done = 0
+    chunk = max(1, min(steps, 2000))
+    while done < steps:
+        k = min(chunk, steps - done)
+        cav.step(k)
+        done += k
+        if done < steps:
+            stream.synchronize()  # progress line; the gap is one launch latency
+            log(f"  {precision}: {done}/{steps} steps")
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    # sanity of the state after the timed region
+    status, _ = cav.residual()
+    s2, dT = cav.residual()
+    nu = cav.nusselt()
+    ncell = n ** 3
+    launch_ms = ms / steps
+    mlups = ncell * steps / (ms * 1e-3) / 1e6
+    bpc = algorithmic_bytes_per_cell(precision)
+    achieved = bpc * ncell / (launch_ms * 1e-3) / 1e9
+    out = {
+        "precision": precision, "kernel": kname, "steps": steps, "warmup": warmup,
+        "ms_per_step": launch_ms, "wall_s": wall, "mlups": mlups,
+        "bytes_per_cell_update": bpc, "achieved_GBs": achieved,
+        "frac_hbm_peak": achieved / HBM_PEAK_GBS, "finite": status == 0,
+        "nu_hot_wall": nu.nu_hot_wall, "block": [cav.p.block_x, cav.p.block_y],
+    }
+    cav.close()
+    del cav
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline(n_full, ra, seconds_hint=15.0, log=print):
+    """The oracle on a bounded sample of the workload: a 64^3 block of cells
+    with the 512^3 case's lattice parameters, a few steps, all host threads."""
+    import numpy as np
+    from oracle import oracle as O
+
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
+    used = O.set_threads(threads)
+    p = O.cavity_params(n_full, ra)
+    side = 64
+    p.nx = p.ny = p.nz = side
+    F, G = O.rest_state(p)
+    O.run(p, 1, F, G)  # warm
+    t0 = time.perf_counter()
+    steps = 0
+    while time.perf_counter() - t0 < seconds_hint:
+        F, G, _ = O.run(p, 2, F, G)
+        steps += 2
+    dt = time.perf_counter() - t0
+    mlups = side ** 3 * steps / dt / 1e6
+    log(f"cpu oracle: {side}^3 x {steps} steps in {dt:.1f}s on {used} threads -> {mlups:.3f} MLUPS")
+    return {"value": mlups, "unit": "MLUPS", "cores": used, "kind": "oracle",
+            "sample": f"{side}^3 cells with the {n_full}^3 Ra={ra:g} lattice parameters, "
+                      f"{steps} steps from rest ({dt:.1f} s), FP64 oracle"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--Ra", type=float, default=1e6)
+    ap.add_argument("--fp16-steps", type=int, default=None,
+                    help="timed steps of the FP16-storage line (default: --steps)")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--block", type=str, default=None, help="bx,by of the step kernel")
+    args = ap.parse_args()
+
+    def log(*a):
+        print(*a, file=sys.stderr, flush=True)
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "
+              "z-slab decomposition is a design, not part of this build.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+
+    block = tuple(int(v) for v in args.block.split(",")) if args.block else None
+    log(f"bench: {args.n}^3 Ra={args.Ra:g} D3Q7, {args.steps} timed steps, warmup {args.warmup}")
+    main_line = time_variant(args.n, args.Ra, "fp32", args.steps, args.warmup, block, log)
+    log(json.dumps(main_line))
+    f16_steps = args.fp16_steps if args.fp16_steps is not None else args.steps
+    f16 = time_variant(args.n, args.Ra, "fp16", f16_steps, args.warmup, block, log)
+    log(json.dumps(f16))
+    cpu = None if args.no_cpu else cpu_baseline(args.n, args.Ra, log=log)
+
+    rec = {
+        "metric": METRIC,
+        "value": round(main_line["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_line["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"cavity{args.n}_ra{args.Ra:g}_d3q7",
+            "cells": args.n ** 3, "Ra": args.Ra, "Pr": 0.71, "u0": 0.05,
+            "flow_lattice": "D3Q15", "thermal_lattice": "D3Q7", "storage": "fp32",
+            "start": "rest", "kernel": main_line["kernel"], "block": main_line["block"],
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(main_line["achieved_GBs"], 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(main_line["frac_hbm_peak"], 4),
+            "traffic": None,
+        },
+        "fp16_storage": {
+            "value": round(f16["mlups"], 1), "unit": "MLUPS", "steps": f16_steps,
+            "ms_per_step": f16["ms_per_step"], "kernel": f16["kernel"],
+            "roofline": {"bound": "hbm", "achieved": round(f16["achieved_GBs"], 1),
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(f16["frac_hbm_peak"], 4), "traffic": None},
+        },
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

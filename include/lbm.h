@@ -1,0 +1,215 @@
+/*
+ * lbm.h - C ABI of the MI355X (gfx950) library for the double-distribution
+ * cascaded (central-moment, multiple-relaxation-time) lattice Boltzmann
+ * method for 3D thermal convection of Hajabdollahi & Premnath,
+ * arXiv:1710.04751.
+ *
+ * Problem (Sec. 3 of the paper): a box of nx * ny * nz fluid cells with
+ * walls half a link outside the first and last cells (L = nx).  The wall
+ * x = -1/2 is held at T_hot, the wall x = nx - 1/2 at T_cold, the other four
+ * faces are adiabatic, the fluid sticks to every wall, and buoyancy
+ * F = g beta (T - T0) acts along +z with T0 = (T_hot + T_cold)/2.
+ *
+ * Method per time step and cell (the fused update this library launches):
+ *   pull streaming, eq. (2b) and (13b), with half-way bounce-back for the
+ *   flow, anti-bounce-back on the two Dirichlet walls and bounce-back on the
+ *   adiabatic faces for the scalar;
+ *   macroscopic fields: T = sum g (eq. 25, no heat source),
+ *   F = g beta (T - T0) z-hat, rho = sum f, rho u = sum f e + F/2 (eq. 3);
+ *   flow collision: the D3Q15 cascaded central-moment kernel of Appendix A
+ *   with the body-force source, eq. (2a);
+ *   scalar collision: the D3Q15 kernel of Sec. 2.2 or the D3Q7 kernel of
+ *   Appendix C, eq. (13a), with the flow velocity of the same step.
+ *
+ * Conventions for every function:
+ *   - Return an lbm_status; nothing throws across this ABI.
+ *   - lbm_last_error() returns a thread-local message for the last failure.
+ *   - "device pointer" means memory on the HIP device the handle was created
+ *     on; the caller allocates and owns it.  "host pointer" means ordinary
+ *     host memory.
+ *   - Work is enqueued on the stream given at creation (hipStream_t passed
+ *     as void*; NULL is the default stream).  Only functions documented as
+ *     synchronising wait for the device.
+ *   - Field layout: one value per cell, x fastest: index (z*ny + y)*nx + x.
+ *   - Population arrays: population a of cell c at [a*ncell + c].
+ */
+#ifndef LBM_H_
+#define LBM_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LBM_OK = 0,
+    LBM_ERR_ARG = -1,      /* invalid argument or parameter set */
+    LBM_ERR_HIP = -2,      /* a HIP runtime call failed */
+    LBM_ERR_UNSTABLE = -3, /* NaN or Inf found in the solution */
+    LBM_ERR_STATE = -4     /* call not valid in the handle's current state */
+} lbm_status;
+
+/* Storage and arithmetic of the distributions.
+ * LBM_FP64: FP64 arithmetic, FP64 storage.
+ * LBM_FP32: FP32 arithmetic, FP32 storage.
+ * LBM_FP32_S16: FP32 arithmetic, FP16 storage (round to nearest even).
+ * In every mode the flow populations are stored as deviations f - w_a from
+ * the rest state (rho = 1, u = 0) and the scalar populations as g (T_ref =
+ * 0), so storage rounding acts on small numbers. */
+typedef enum { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP32_S16 = 2 } lbm_precision;
+
+/* Problem and method parameters.  Fill with lbm_params_init, then adjust. */
+typedef struct lbm_params {
+    int32_t nx, ny, nz;     /* fluid cells per axis (each >= 4) */
+    int32_t thermal_q;      /* scalar lattice: 7 (Appendix C) or 15 (Sec. 2.2) */
+    int32_t precision;      /* lbm_precision */
+    int32_t fourth_maxwell; /* flow 4th-order equilibrium: 0 = kxx~ kyy~ / rho
+                               (post-collision second-order central moments,
+                               Appendix A), 1 = c_s^4 rho */
+    double Ra, Pr;          /* Rayleigh and Prandtl numbers (Sec. 3) */
+    double u0;              /* velocity scale sqrt(g beta dT L) in lattice units */
+    double T_hot, T_cold;   /* wall temperatures at x = -1/2 and x = nx - 1/2 */
+    double cs2_T;           /* c_sphi^2 of the scalar equilibrium (eq. 6); 1/3 */
+    double omega_bulk;      /* flow trace rate omega_9; <= 0 means the shear rate */
+    double omega_hi;        /* flow rates omega_10..omega_14 (third/fourth order); 1 */
+    double omega_hi_T;      /* scalar rates of orders >= 2; 1 */
+    double R;               /* scalar source; must be 0 */
+    int32_t lattice_units;  /* 0: derive nu, alpha, gbeta from Ra, Pr, u0 and
+                               L = nx; 1: take nu, alpha, gbeta below as given */
+    int32_t block_x;        /* threads per block along x (0 = default) */
+    int32_t block_y;        /* threads per block along y (0 = default) */
+    int32_t reserved0;
+    double nu, alpha, gbeta; /* used only when lattice_units == 1 */
+} lbm_params;
+
+/* Lattice-unit values a handle runs with. */
+typedef struct lbm_lattice {
+    double nu, alpha, gbeta; /* viscosity, diffusivity, g beta */
+    double omega_nu;         /* shear rate: nu = (1/omega - 1/2)/3 (Appendix A) */
+    double omega_bulk;       /* trace rate actually used */
+    double omega_T;          /* alpha = c_sphi^2 (1/omega_T - 1/2) (eq. 23) */
+    double T_ref;            /* T0 of the buoyancy force */
+} lbm_lattice;
+
+/* Wall heat transfer (FP64).  Local Nu is the heat crossing a wall per unit
+ * area and step times L / (alpha dT), taken from the links that cross the
+ * wall (anti-bounce-back returns 2 (w_a T_wall - g_out) per link), so pure
+ * conduction gives exactly 1. */
+typedef struct lbm_nu {
+    double nu_hot_wall, nu_cold_wall; /* means over the two Dirichlet faces */
+    double nu_hot_mid, nu_cold_mid;   /* means along z on the mid-plane y = L/2 */
+    double nu_max, z_max;             /* max of hot-wall local Nu on that line, at z/L */
+    double nu_min, z_min;             /* min, at z/L */
+} lbm_nu;
+
+typedef struct lbm_handle lbm_handle;
+
+/* Thread-local text of the last error (never NULL). */
+const char* lbm_last_error(void);
+
+/* Defaults: n^3 cavity at Rayleigh number Ra, Pr = 0.71, u0 = 0.05,
+ * T_hot = +0.5, T_cold = -0.5, D3Q7 scalar, FP32, c_sphi^2 = 1/3, bulk rate
+ * equal to the shear rate, higher-order rates 1, factorised 4th-order
+ * equilibrium. */
+lbm_status lbm_params_init(lbm_params* p, int32_t n, double Ra);
+
+/* Derived lattice values of a parameter set (host pointers). */
+lbm_status lbm_params_lattice(const lbm_params* p, lbm_lattice* out);
+
+/* Bytes of device workspace lbm_create needs for p; 0 if p is invalid. */
+size_t lbm_workspace_bytes(const lbm_params* p);
+
+/* Create a solver.  Validates p (LBM_ERR_ARG: a size < 4, thermal_q not 7 or
+ * 15, R != 0, Ra, Pr or u0 <= 0, u0 / c_s > 0.3, a relaxation rate outside
+ * (0, 2), block sizes not a multiple of 64 threads or above 1024).
+ * workspace: device pointer of at least lbm_workspace_bytes(p) bytes, 256-byte
+ * aligned, borrowed until lbm_destroy.  stream: hipStream_t or NULL.
+ * The state is the fluid at rest with T = 0 (lbm_init_rest is enqueued). */
+lbm_status lbm_create(const lbm_params* p, void* workspace, size_t workspace_bytes, void* stream,
+                      lbm_handle** out);
+
+/* Release the host-side state; the workspace is not freed (caller owns it). */
+lbm_status lbm_destroy(lbm_handle* h);
+
+/* Lattice values the handle runs with (host pointer). */
+lbm_status lbm_get_lattice(const lbm_handle* h, lbm_lattice* out);
+
+/* Number of steps taken since the last initialisation. */
+int64_t lbm_steps_done(const lbm_handle* h);
+
+/* Rest state: rho = 1, u = 0, T = 0 (f = w_a, g = 0).  Asynchronous. */
+lbm_status lbm_init_rest(lbm_handle* h);
+
+/* Equilibrium state from fields (device pointers, float, ncell each; NULL
+ * means 0): rho = 1, velocity (ux, uy, uz), temperature T.  Used to start
+ * from a prediction.  Asynchronous. */
+lbm_status lbm_init_macros(lbm_handle* h, const float* ux, const float* uy, const float* uz,
+                           const float* T);
+
+/* Advance nsteps >= 0 time steps.  Asynchronous. */
+lbm_status lbm_step(lbm_handle* h, int64_t nsteps);
+
+/* Macroscopic fields of the current step: rho, ux, uy, uz, T (device
+ * pointers, ncell values each, double if fp64 != 0 else float; NULL skips a
+ * field).  They equal the pre-collision moments of the last step (eq. 3, 25),
+ * recovered from the stored post-collision populations (collision conserves
+ * rho and T and adds F to the momentum).  Asynchronous. */
+lbm_status lbm_macros(lbm_handle* h, void* rho, void* ux, void* uy, void* uz, void* T, int fp64);
+
+/* Wall Nusselt numbers of the current state (FP64 reduction on the device).
+ * out: host pointer.  Synchronises the stream.  Optional profiles (device
+ * pointers, double, may be NULL): local Nu of the hot and cold walls,
+ * [nz][ny] each. */
+lbm_status lbm_nusselt(lbm_handle* h, lbm_nu* out, double* local_hot, double* local_cold);
+
+/* Steady-state residual: max over cells of |T_now - T_snapshot| (host
+ * pointer), then T_now becomes the snapshot.  The first call after an
+ * initialisation only takes the snapshot and reports +inf.  Returns
+ * LBM_ERR_UNSTABLE if any T is NaN or Inf.  Synchronises the stream. */
+lbm_status lbm_residual(lbm_handle* h, double* max_dT);
+
+/* Full populations as FP64 (device pointers): F [15][ncell], G [q][ncell]
+ * (f itself, not the stored deviation).  Either may be NULL.  Asynchronous. */
+lbm_status lbm_get_populations(lbm_handle* h, double* F, double* G);
+
+/* Overwrite the state with full FP64 populations (device pointers, same
+ * layout; rounded to the storage precision).  Resets the step counter.
+ * Asynchronous. */
+lbm_status lbm_set_populations(lbm_handle* h, const double* F, const double* G);
+
+/* Full FP64 populations of n listed cells (device pointers): cells [n]
+ * (linear cell indices, each in [0, ncell)), F [n][15], G [n][q].  Indices
+ * out of range are reported as LBM_ERR_ARG before any launch only when
+ * check != 0 (the check copies cells to the host and synchronises).
+ * Asynchronous otherwise. */
+lbm_status lbm_gather_cells(lbm_handle* h, const int64_t* cells, int64_t n, double* F, double* G,
+                            int check);
+
+/* Device buffers of the current state, for inspection: F and G base
+ * pointers, elements between two populations, bytes per stored value. */
+lbm_status lbm_state_info(const lbm_handle* h, const void** F, const void** G,
+                          int64_t* pop_stride, int32_t* value_bytes);
+
+/* Name of the step kernel the handle launches (for profiler summaries). */
+const char* lbm_step_kernel_name(const lbm_handle* h);
+
+/* Threads per block of the step kernel: set (each a multiple of 64 total,
+ * at most 1024) or time candidates with HIP events on the handle's stream
+ * and keep the fastest.  lbm_autotune advances the state by the steps it
+ * times (it is meant for warm-up); results: the chosen block_x, block_y. */
+lbm_status lbm_set_block(lbm_handle* h, int32_t block_x, int32_t block_y);
+lbm_status lbm_autotune(lbm_handle* h, int32_t steps_per_trial, int32_t* block_x,
+                        int32_t* block_y);
+
+/* Plain device copy of bytes (device pointers, 16-byte aligned, bytes a
+ * multiple of 16) on stream: the reference kernel for bandwidth and
+ * memory-counter calibration.  Asynchronous. */
+lbm_status lbm_copy_probe(void* dst, const void* src, size_t bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H_ */

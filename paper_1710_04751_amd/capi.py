@@ -1,0 +1,218 @@
+"""ctypes binding of liblbm.so: the C ABI of include/lbm.h under the same
+names.  Argument marshalling only; every step of the method runs in the
+library's HIP kernels.  Device pointers are passed as Python ints (for
+example torch_tensor.data_ptr()); NULL is 0 or None.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblbm.so")
+
+LBM_OK, LBM_ERR_ARG, LBM_ERR_HIP, LBM_ERR_UNSTABLE, LBM_ERR_STATE = 0, -1, -2, -3, -4
+LBM_FP64, LBM_FP32, LBM_FP32_S16 = 0, 1, 2
+
+
+class lbm_params(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("thermal_q", ctypes.c_int32), ("precision", ctypes.c_int32),
+        ("fourth_maxwell", ctypes.c_int32),
+        ("Ra", ctypes.c_double), ("Pr", ctypes.c_double), ("u0", ctypes.c_double),
+        ("T_hot", ctypes.c_double), ("T_cold", ctypes.c_double), ("cs2_T", ctypes.c_double),
+        ("omega_bulk", ctypes.c_double), ("omega_hi", ctypes.c_double),
+        ("omega_hi_T", ctypes.c_double), ("R", ctypes.c_double),
+        ("lattice_units", ctypes.c_int32), ("block_x", ctypes.c_int32),
+        ("block_y", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+        ("nu", ctypes.c_double), ("alpha", ctypes.c_double), ("gbeta", ctypes.c_double),
+    ]
+
+
+class lbm_lattice(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in
+                ("nu", "alpha", "gbeta", "omega_nu", "omega_bulk", "omega_T", "T_ref")]
+
+
+class lbm_nu(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in
+                ("nu_hot_wall", "nu_cold_wall", "nu_hot_mid", "nu_cold_mid",
+                 "nu_max", "z_max", "nu_min", "z_min")]
+
+
+class LbmError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"lbm status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+vp = ctypes.c_void_p
+H = ctypes.c_void_p  # lbm_handle*
+
+# name -> (restype, argtypes); mirrors include/lbm.h
+_SIGS = {
+    "lbm_last_error": (ctypes.c_char_p, []),
+    "lbm_params_init": (ctypes.c_int, [ctypes.POINTER(lbm_params), ctypes.c_int32, ctypes.c_double]),
+    "lbm_params_lattice": (ctypes.c_int, [ctypes.POINTER(lbm_params), ctypes.POINTER(lbm_lattice)]),
+    "lbm_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(lbm_params)]),
+    "lbm_create": (ctypes.c_int, [ctypes.POINTER(lbm_params), vp, ctypes.c_size_t, vp,
+                                  ctypes.POINTER(H)]),
+    "lbm_destroy": (ctypes.c_int, [H]),
+    "lbm_get_lattice": (ctypes.c_int, [H, ctypes.POINTER(lbm_lattice)]),
+    "lbm_steps_done": (ctypes.c_int64, [H]),
+    "lbm_init_rest": (ctypes.c_int, [H]),
+    "lbm_init_macros": (ctypes.c_int, [H, vp, vp, vp, vp]),
+    "lbm_step": (ctypes.c_int, [H, ctypes.c_int64]),
+    "lbm_macros": (ctypes.c_int, [H, vp, vp, vp, vp, vp, ctypes.c_int]),
+    "lbm_nusselt": (ctypes.c_int, [H, ctypes.POINTER(lbm_nu), vp, vp]),
+    "lbm_residual": (ctypes.c_int, [H, ctypes.POINTER(ctypes.c_double)]),
+    "lbm_get_populations": (ctypes.c_int, [H, vp, vp]),
+    "lbm_set_populations": (ctypes.c_int, [H, vp, vp]),
+    "lbm_gather_cells": (ctypes.c_int, [H, vp, ctypes.c_int64, vp, vp, ctypes.c_int]),
+    "lbm_state_info": (ctypes.c_int, [H, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                      ctypes.POINTER(ctypes.c_int64),
+                                      ctypes.POINTER(ctypes.c_int32)]),
+    "lbm_step_kernel_name": (ctypes.c_char_p, [H]),
+    "lbm_set_block": (ctypes.c_int, [H, ctypes.c_int32, ctypes.c_int32]),
+    "lbm_autotune": (ctypes.c_int, [H, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                    ctypes.POINTER(ctypes.c_int32)]),
+    "lbm_copy_probe": (ctypes.c_int, [vp, vp, ctypes.c_size_t, vp]),
+}
+
+
+def lib():
+    """The loaded liblbm.so; raises if the HIP library has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build the HIP library first "
+                               "(python -c 'import __graft_entry__ as g; g.build()')")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_names():
+    return list(_SIGS)
+
+
+def check(status):
+    if status != LBM_OK:
+        raise LbmError(status, lbm_last_error())
+    return status
+
+
+def lbm_last_error():
+    return lib().lbm_last_error().decode()
+
+
+def lbm_params_init(n, Ra):
+    p = lbm_params()
+    check(lib().lbm_params_init(ctypes.byref(p), int(n), float(Ra)))
+    return p
+
+
+def lbm_params_lattice(p):
+    L = lbm_lattice()
+    check(lib().lbm_params_lattice(ctypes.byref(p), ctypes.byref(L)))
+    return L
+
+
+def lbm_workspace_bytes(p):
+    n = lib().lbm_workspace_bytes(ctypes.byref(p))
+    if n == 0:
+        raise LbmError(LBM_ERR_ARG, lbm_last_error())
+    return n
+
+
+def lbm_create(p, workspace_ptr, workspace_bytes, stream_ptr=None):
+    h = H()
+    check(lib().lbm_create(ctypes.byref(p), workspace_ptr, workspace_bytes, stream_ptr or None,
+                           ctypes.byref(h)))
+    return h
+
+
+def lbm_destroy(h):
+    return check(lib().lbm_destroy(h))
+
+
+def lbm_get_lattice(h):
+    L = lbm_lattice()
+    check(lib().lbm_get_lattice(h, ctypes.byref(L)))
+    return L
+
+
+def lbm_steps_done(h):
+    return lib().lbm_steps_done(h)
+
+
+def lbm_init_rest(h):
+    return check(lib().lbm_init_rest(h))
+
+
+def lbm_init_macros(h, ux=None, uy=None, uz=None, T=None):
+    return check(lib().lbm_init_macros(h, ux, uy, uz, T))
+
+
+def lbm_step(h, nsteps):
+    return check(lib().lbm_step(h, int(nsteps)))
+
+
+def lbm_macros(h, rho=None, ux=None, uy=None, uz=None, T=None, fp64=False):
+    return check(lib().lbm_macros(h, rho, ux, uy, uz, T, 1 if fp64 else 0))
+
+
+def lbm_nusselt(h, local_hot=None, local_cold=None):
+    out = lbm_nu()
+    check(lib().lbm_nusselt(h, ctypes.byref(out), local_hot, local_cold))
+    return out
+
+
+def lbm_residual(h):
+    """Returns (status, max_dT); status LBM_ERR_UNSTABLE is returned, not raised."""
+    v = ctypes.c_double()
+    s = lib().lbm_residual(h, ctypes.byref(v))
+    if s not in (LBM_OK, LBM_ERR_UNSTABLE):
+        check(s)
+    return s, v.value
+
+
+def lbm_get_populations(h, F=None, G=None):
+    return check(lib().lbm_get_populations(h, F, G))
+
+
+def lbm_set_populations(h, F, G):
+    return check(lib().lbm_set_populations(h, F, G))
+
+
+def lbm_gather_cells(h, cells, n, F=None, G=None, check_range=True):
+    return check(lib().lbm_gather_cells(h, cells, int(n), F, G, 1 if check_range else 0))
+
+
+def lbm_state_info(h):
+    F, G, ps, vb = vp(), vp(), ctypes.c_int64(), ctypes.c_int32()
+    check(lib().lbm_state_info(h, ctypes.byref(F), ctypes.byref(G), ctypes.byref(ps),
+                               ctypes.byref(vb)))
+    return F.value, G.value, ps.value, vb.value
+
+
+def lbm_step_kernel_name(h):
+    return lib().lbm_step_kernel_name(h).decode()
+
+
+def lbm_set_block(h, bx, by):
+    return check(lib().lbm_set_block(h, int(bx), int(by)))
+
+
+def lbm_autotune(h, steps_per_trial):
+    bx, by = ctypes.c_int32(), ctypes.c_int32()
+    check(lib().lbm_autotune(h, int(steps_per_trial), ctypes.byref(bx), ctypes.byref(by)))
+    return bx.value, by.value
+
+
+def lbm_copy_probe(dst, src, nbytes, stream_ptr=None):
+    return check(lib().lbm_copy_probe(dst, src, int(nbytes), stream_ptr or None))

@@ -1,0 +1,62 @@
+// Host-side declarations shared by the C ABI (lbm_api.cpp) and the kernel
+// launchers (lbm_kernels.hip).  Not part of the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+// Geometry of one cavity and the tiling of its step launch.
+struct Geom {
+    int32_t nx, ny, nz;
+    int32_t bx, by;           // threads per block along x, y
+    int32_t tiles_x, tiles_y; // blocks per row / per plane
+};
+
+// Lattice-unit coefficients, in double; launchers convert to the arithmetic
+// type of the kernel.
+struct Coefs {
+    double omega, omega_bulk, omega_hi;  // flow
+    double omega_T, omega_hiT, cs2;      // scalar
+    double gbeta, T_ref, T_hot, T_cold;
+    double alpha;                        // for the Nusselt number
+    int32_t fourth_maxwell;
+};
+
+// One stored state (A or B): populations a of cell c at base[a*ps + c].
+struct StateBuf {
+    void* F;
+    void* G;
+};
+
+enum class Prec : int32_t { FP64 = 0, FP32 = 1, FP32_S16 = 2 };
+
+int value_bytes(Prec p);
+
+hipError_t launch_step(Prec p, int qt, bool general, const Geom& g, int64_t ps, StateBuf in,
+                       StateBuf out, const Coefs& c, hipStream_t s);
+hipError_t launch_fill_zero(void* ptr, size_t bytes, hipStream_t s);
+hipError_t launch_init_macros(Prec p, int qt, const Geom& g, int64_t ps, StateBuf st,
+                              const float* ux, const float* uy, const float* uz, const float* T,
+                              const Coefs& c, hipStream_t s);
+hipError_t launch_macros(Prec p, int qt, const Geom& g, int64_t ps, StateBuf st, void* rho,
+                         void* ux, void* uy, void* uz, void* T, bool fp64, const Coefs& c,
+                         hipStream_t s);
+hipError_t launch_nusselt(Prec p, int qt, const Geom& g, int64_t ps, StateBuf st,
+                          double* local_hot, double* local_cold, double* result,
+                          const Coefs& c, hipStream_t s);
+hipError_t launch_residual(Prec p, int qt, const Geom& g, int64_t ps, StateBuf st, void* snapshot,
+                           bool compare, unsigned long long* max_bits, unsigned int* bad_flag,
+                           hipStream_t s);
+hipError_t launch_get_pops(Prec p, int qt, const Geom& g, int64_t ps, StateBuf st, double* F,
+                           double* G, hipStream_t s);
+hipError_t launch_set_pops(Prec p, int qt, const Geom& g, int64_t ps, StateBuf st,
+                           const double* F, const double* G, hipStream_t s);
+hipError_t launch_gather_cells(Prec p, int qt, int64_t ncell, int64_t ps, StateBuf st,
+                               const int64_t* cells, int64_t n, double* F, double* G,
+                               hipStream_t s);
+hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
+const char* step_kernel_name(Prec p, int qt, bool general);
+
+}  // namespace lbm

@@ -1,0 +1,104 @@
+"""GPU observables against the oracle: the FP64 Nusselt reduction, the
+steady-state residual, NaN detection and the macroscopic-field output."""
+import math
+
+import numpy as np
+import pytest
+
+from gpu_helpers import log, to_np
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def solver():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1710_04751_amd import solver as S
+    return S
+
+
+def _summary(nh, nc):
+    """Face means, mid-line (y = L/2) means and hot-line extremes."""
+    nz, ny = nh.shape
+    y0, y1 = (ny // 2, ny // 2) if ny % 2 else (ny // 2 - 1, ny // 2)
+    lh = 0.5 * (nh[:, y0] + nh[:, y1])
+    lc = 0.5 * (nc[:, y0] + nc[:, y1])
+    return {"nu_hot_wall": nh.mean(), "nu_cold_wall": nc.mean(), "nu_hot_mid": lh.mean(),
+            "nu_cold_mid": lc.mean(), "nu_max": lh.max(), "z_max": (np.argmax(lh) + 0.5) / nz,
+            "nu_min": lh.min(), "z_min": (np.argmin(lh) + 0.5) / nz}
+
+
+@pytest.mark.parametrize("qt,n", [(7, 16), (15, 13)])
+def test_nusselt_matches_oracle(solver, oracle, qt, n):
+    log(f"case: nusselt {n}^3 q{qt} fp64")
+    p = oracle.cavity_params(n, 1e3, qt=qt)
+    F, G = oracle.rest_state(p)
+    F, G, _ = oracle.run(p, 600, F, G)
+    nh, nc = oracle.nusselt(p, G)
+    ref = _summary(nh, nc)
+    cav = solver.Cavity(solver.make_params(n, 1e3, precision="fp64", thermal_q=qt))
+    cav.step(600)
+    r, lh, lc = cav.nusselt(local=True)
+    lh, lc = to_np(lh), to_np(lc)
+    assert np.max(np.abs(lh - nh)) < 1e-11 * np.max(np.abs(nh))
+    assert np.max(np.abs(lc - nc)) < 1e-11 * np.max(np.abs(nc))
+    for k, v in ref.items():
+        assert abs(getattr(r, k) - v) <= 1e-11 * max(1.0, abs(v)), (k, getattr(r, k), v)
+    log("nusselt", {k: getattr(r, k) for k in ref})
+    cav.close()
+
+
+def test_residual_matches_oracle(solver, oracle):
+    log("case: residual 16^3 fp64")
+    p = oracle.cavity_params(16, 1e3)
+    F, G = oracle.rest_state(p)
+    F, G, m1 = oracle.run(p, 500, F, G)
+    F, G, m2 = oracle.run(p, 300, F, G)
+    ref = np.max(np.abs(m2[4] - m1[4]))
+    cav = solver.Cavity(solver.make_params(16, 1e3, precision="fp64"))
+    cav.step(500)
+    s, v = cav.residual()
+    assert s == 0 and math.isinf(v)
+    cav.step(300)
+    s, v = cav.residual()
+    assert s == 0
+    assert abs(v - ref) <= 1e-12 * max(ref, 1e-30) + 1e-15, (v, ref)
+    cav.close()
+
+
+def test_nan_is_reported_unstable(solver):
+    """A NaN forced into the initial temperature (from the host) surfaces as
+    LBM_ERR_UNSTABLE at the next residual; the kernels just carry the NaN."""
+    from paper_1710_04751_amd import capi
+    log("case: NaN detection")
+    cav = solver.Cavity(solver.make_params(16, 1e3, precision="fp32"))
+    T = torch.zeros(cav.shape)
+    T[5, 6, 7] = float("nan")
+    cav.init_macros(T=T)
+    cav.step(2)
+    s, v = cav.residual()
+    assert s == capi.LBM_ERR_UNSTABLE and math.isnan(v)
+    cav.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_macros_single_and_double(solver, oracle, prec):
+    """lbm_macros in both output types agree with the oracle's pre-collision
+    moments of the same step."""
+    p = oracle.cavity_params(12, 5e3, qt=15, ny=10, nz=14)
+    F, G = oracle.rest_state(p)
+    F, G, mac = oracle.run(p, 300, F, G)
+    cav = solver.Cavity(solver.make_params(nx=12, ny=10, nz=14, Ra=5e3, precision=prec,
+                                           thermal_q=15))
+    cav.step(300)
+    tol = 1e-12 if prec == "fp64" else 1e-5
+    for fp64 in (True, False):
+        m = cav.macros(fp64=fp64)
+        for i, k in enumerate(("rho", "ux", "uy", "uz", "T")):
+            sc = np.max(np.abs(mac[1:4])) if k.startswith("u") else np.max(np.abs(mac[i]))
+            err = np.max(np.abs(to_np(m[k]).astype(np.float64) - mac[i])) / sc
+            lim = tol if fp64 else max(tol, 1e-6)
+            assert err <= lim, (k, fp64, err)
+    cav.close()

@@ -1,0 +1,185 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Tolerances (normalised max error, see gpu_helpers.field_errors):
+  FP64 mode: 1e-12; FP32 mode: 1e-5; FP16 storage: the bound derived from
+  the storage rounding (below).  Full populations are compared too.
+"""
+import numpy as np
+import pytest
+
+from gpu_helpers import cell_index, field_errors, gather_neighbourhoods, log, to_np
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def solver():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1710_04751_amd import solver as S
+    return S
+
+
+@pytest.fixture(scope="module")
+def small_case_oracle(oracle):
+    """16^3, Ra = 1e3, D3Q7, fluid at rest with T = 0, 2000 steps."""
+    from paper_1710_04751_amd import workloads as W
+    c = W.SMALL_PARITY
+    p = oracle.cavity_params(c.n, c.Ra, Pr=c.Pr, u0=c.u0)
+    F, G = oracle.rest_state(p)
+    F, G, mac = oracle.run(p, c.steps, F, G)
+    return p, F, G, mac
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_small_cavity_2000_steps(solver, small_case_oracle, prec, tol):
+    p, F, G, mac = small_case_oracle
+    log(f"case: 16^3 Ra=1e3 D3Q7 2000 steps {prec}")
+    cav = solver.Cavity(solver.make_params(16, 1e3, precision=prec))
+    cav.step(2000)
+    m = {k: to_np(v) for k, v in cav.macros(fp64=True).items()}
+    err = field_errors(m, mac)
+    log(prec, err)
+    assert err["rho"] <= tol and err["u"] <= tol and err["T"] <= tol
+    Fg, Gg = (to_np(t) for t in cav.populations())
+    ef = np.max(np.abs(Fg - F)) / np.max(np.abs(F))
+    eg = np.max(np.abs(Gg - G)) / np.max(np.abs(G))
+    log(prec, "populations", ef, eg)
+    assert ef <= tol and eg <= tol
+    cav.close()
+
+
+def test_small_cavity_fp16_storage(solver, small_case_oracle):
+    """FP16 storage rounds each stored deviation to 11 significant bits
+    (relative 2^-11 = 4.9e-4 per store).  The scalar populations are O(0.1),
+    so each store moves T by up to ~1e-4 / 0.5; damping by the collision and
+    diffusion keeps the accumulated error within a few such units.  Bound:
+    T and rho within 2e-3, u (normalised by its peak) within 2e-2."""
+    p, F, G, mac = small_case_oracle
+    log("case: 16^3 Ra=1e3 D3Q7 2000 steps fp16 storage")
+    cav = solver.Cavity(solver.make_params(16, 1e3, precision="fp16"))
+    cav.step(2000)
+    m = {k: to_np(v) for k, v in cav.macros(fp64=True).items()}
+    err = field_errors(m, mac)
+    log("fp16", err)
+    assert err["T"] <= 2e-3 and err["rho"] <= 2e-3 and err["u"] <= 2e-2
+    cav.close()
+
+
+def _lattice_params(solver, oracle_p, prec, qt, **extra):
+    """GPU parameters with the oracle's lattice values (lattice units)."""
+    nu = (1 / oracle_p.omega_nu - 0.5) / 3
+    alpha = oracle_p.cs2T * (1 / oracle_p.omega_T - 0.5)
+    return solver.make_params(nx=oracle_p.nx, ny=oracle_p.ny, nz=oracle_p.nz, precision=prec,
+                              thermal_q=qt, lattice_units=1, nu=nu, alpha=alpha,
+                              gbeta=oracle_p.gbeta, T_hot=oracle_p.T_hot, T_cold=oracle_p.T_cold,
+                              cs2_T=oracle_p.cs2T,
+                              omega_bulk=oracle_p.omega_bulk, omega_hi=oracle_p.omega_hi,
+                              omega_hi_T=oracle_p.omega_hiT,
+                              fourth_maxwell=oracle_p.fourth_maxwell, **extra)
+
+
+VARIANTS = [
+    # (name, qt, overrides of the oracle parameters)
+    ("q7_default", 7, {}),
+    ("q15_default", 15, {}),
+    ("q15_general_rates", 15, {"omega_hi": 0.8, "omega_hiT": 1.3}),
+    ("q7_general_rates", 7, {"omega_hi": 1.2, "omega_hiT": 0.7}),
+    ("q15_bulk1_maxwell", 15, {"omega_bulk": 1.0, "fourth_maxwell": 1}),
+    ("q7_cs2_quarter", 7, {"cs2T": 0.25}),
+]
+
+
+@pytest.mark.parametrize("name,qt,over", VARIANTS, ids=[v[0] for v in VARIANTS])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 2e-6)])
+def test_ragged_random_state(solver, oracle, name, qt, over, prec, tol):
+    """A ragged grid (not a multiple of the block in any direction) started
+    from a seeded random non-equilibrium state, so every moment order, wall
+    and edge rule is active from the first step."""
+    from paper_1710_04751_amd import workloads as W
+    shape = (19, 23, 37)  # nz, ny, nx
+    p = oracle.cavity_params(37, 2e4, u0=0.1, qt=qt, ny=23, nz=19)
+    p.omega_nu = 1.6
+    p.omega_T = 1.45
+    for k, v in over.items():
+        setattr(p, k, v)
+    log(f"case: ragged 37x23x19 {name} {prec}")
+    F0, G0 = oracle.init_equilibrium(
+        p, ux=W.smooth_field(shape, 1, 0.02), uy=W.smooth_field(shape, 2, 0.02),
+        uz=W.smooth_field(shape, 3, 0.02), T=W.smooth_field(shape, 4, 0.5))
+    F0 = F0 + W.perturbation(shape, 15, 5, 2e-4)
+    G0 = G0 + W.perturbation(shape, qt, 6, 2e-3)
+    F1, G1, mac = oracle.run(p, 40, F0, G0)
+    cav = solver.Cavity(_lattice_params(solver, p, prec, qt))
+    cav.set_populations(F0, G0)
+    cav.step(40)
+    Fg, Gg = (to_np(t) for t in cav.populations())
+    m = {k: to_np(v) for k, v in cav.macros(fp64=True).items()}
+    ef = np.max(np.abs(Fg - F1)) / np.max(np.abs(F1))
+    eg = np.max(np.abs(Gg - G1)) / np.max(np.abs(G1))
+    err = field_errors(m, mac)
+    log(name, prec, "F", ef, "G", eg, err)
+    assert ef <= tol and eg <= tol
+    assert err["rho"] <= tol and err["u"] <= 10 * tol and err["T"] <= tol
+    cav.close()
+
+
+def test_init_macros_matches_oracle_equilibrium(solver, oracle):
+    """Equilibrium initialisation from (u, T) fields (float32 inputs)."""
+    from paper_1710_04751_amd import workloads as W
+    shape = (9, 10, 11)
+    p = oracle.cavity_params(11, 1e4, qt=15, ny=10, nz=9)
+    fields = [W.smooth_field(shape, s, a).astype(np.float32).astype(np.float64)
+              for s, a in ((11, 0.03), (12, 0.03), (13, 0.03), (14, 0.5))]
+    F, G = oracle.init_equilibrium(p, ux=fields[0], uy=fields[1], uz=fields[2], T=fields[3])
+    cav = solver.Cavity(solver.make_params(nx=11, ny=10, nz=9, Ra=1e4, precision="fp64",
+                                           thermal_q=15))
+    cav.init_macros(*[torch.tensor(f, dtype=torch.float32) for f in fields])
+    Fg, Gg = (to_np(t) for t in cav.populations())
+    assert np.max(np.abs(Fg - F)) < 1e-15 and np.max(np.abs(Gg - G)) < 1e-15
+    cav.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+def test_full_size_sampled_one_step(solver, oracle, prec):
+    """512^3, Ra = 1e6, D3Q7, in the launch configuration the benchmark
+    times: one step from a non-trivial state, checked on 3000 sampled cells
+    (all corners, edges and faces included) that the oracle updates one by
+    one from the same neighbourhood values."""
+    from paper_1710_04751_amd import workloads as W
+    n = 512
+    log(f"case: 512^3 sampled one-step {prec}")
+    p = oracle.cavity_params(n, 1e6)
+    cav = solver.Cavity(solver.make_params(n, 1e6, precision=prec))
+    g = torch.Generator(device="cuda").manual_seed(7)
+    shape = cav.shape
+    zz, yy, xx = torch.meshgrid(*[(torch.arange(s, device="cuda", dtype=torch.float32) + 0.5) / s
+                                  for s in shape], indexing="ij")
+    amp = torch.rand(4, generator=g, device="cuda")
+    ux = 0.02 * amp[0] * torch.sin(3.1 * xx) * torch.cos(2.2 * yy) * torch.sin(1.7 * zz)
+    uy = 0.02 * amp[1] * torch.cos(1.3 * xx) * torch.sin(2.9 * zz)
+    uz = 0.02 * amp[2] * torch.sin(2.3 * yy) * torch.cos(3.7 * xx)
+    T = 0.5 * torch.sin(4.1 * xx + 1.0) * torch.cos(3.3 * zz)
+    cav.init_macros(ux, uy, uz, T)
+    del ux, uy, uz, T, xx, yy, zz
+    cav.step(3)
+    pos = W.sample_cells(shape, 3000, seed=3)
+    nb = gather_neighbourhoods(cav, pos)
+    cav.step(1)
+    Fg, Gg = (to_np(t) for t in cav.gather_cells(cell_index(pos, shape)))
+    fo, go, _ = oracle.step_cells(p, nb, pos)
+    if prec == "fp32":
+        assert np.max(np.abs(Fg - fo)) < 1e-7 and np.max(np.abs(Gg - go)) < 1e-7
+    else:
+        # storage rounding of the deviation: at most one FP16 unit in the last place
+        w, _ = oracle.equilibrium(7, 1.0, [0, 0, 0], 0.0)
+        ulp_f = np.spacing(np.abs(fo - w).astype(np.float16)).astype(np.float64)
+        ulp_g = np.spacing(np.abs(go).astype(np.float16)).astype(np.float64)
+        assert np.all(np.abs(Fg - fo) <= ulp_f + 1e-7)
+        assert np.all(np.abs(Gg - go) <= ulp_g + 1e-7)
+    log(prec, "max |dF|", np.max(np.abs(Fg - fo)), "max |dG|", np.max(np.abs(Gg - go)))
+    cav.close()
+    del cav
+    torch.cuda.empty_cache()
