@@ -52,11 +52,14 @@ def test_small_cavity_2000_steps(solver, small_case_oracle, prec, tol):
 
 
 def test_small_cavity_fp16_storage(solver, small_case_oracle):
-    """FP16 storage rounds each stored deviation to 11 significant bits
-    (relative 2^-11 = 4.9e-4 per store).  The scalar populations are O(0.1),
-    so each store moves T by up to ~1e-4 / 0.5; damping by the collision and
-    diffusion keeps the accumulated error within a few such units.  Bound:
-    T and rho within 2e-3, u (normalised by its peak) within 2e-2."""
+    """FP16 storage rounds every stored population to 11 significant bits
+    each step.  The scalar populations are stored directly (reference
+    temperature 0) and are up to |T|/6 ~ 0.08, so each store errs by up to
+    2^-11 * 0.08 = 4e-5; T sums 7 of them and the error does a damped random
+    walk over the diffusion time L^2/(pi^2 alpha) ~ 860 steps of this case:
+    7 * 4e-5 * sqrt(860) ~ 8e-3 absolute, i.e. ~1.6e-2 of max |T| = 0.5.
+    Flow populations are stored as deviations (~1e-3), so u and rho err far
+    less.  Bound (twice the estimate): T 3e-2, u 1e-2, rho 1e-4."""
     p, F, G, mac = small_case_oracle
     log("case: 16^3 Ra=1e3 D3Q7 2000 steps fp16 storage")
     cav = solver.Cavity(solver.make_params(16, 1e3, precision="fp16"))
@@ -64,7 +67,7 @@ def test_small_cavity_fp16_storage(solver, small_case_oracle):
     m = {k: to_np(v) for k, v in cav.macros(fp64=True).items()}
     err = field_errors(m, mac)
     log("fp16", err)
-    assert err["T"] <= 2e-3 and err["rho"] <= 2e-3 and err["u"] <= 2e-2
+    assert err["T"] <= 3e-2 and err["rho"] <= 1e-4 and err["u"] <= 1e-2
     cav.close()
 
 
