@@ -38,9 +38,15 @@ def time_variant(n, ra, precision, steps, warmup, block=None, log=print):
 
     stream = torch.cuda.Stream()
     params = S.make_params(n, ra, precision=precision)
-    params.block_x, params.block_y = block or (256, 1)
+    if block:
+        params.block_x, params.block_y = block
     cav = S.Cavity(params, stream=stream)
     kname = cav.kernel_name()
+    if block:
+        chosen = list(block)
+    else:  # block shape chosen by the library's autotuner (its trial steps are warm-up)
+        chosen = list(cav.autotune(steps_per_trial=20))
+        log(f"  {precision}: autotuned block {chosen[0]}x{chosen[1]}")
     cav.step(warmup)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -75,12 +81,37 @@ def time_variant(n, ra, precision, steps, warmup, block=None, log=print):
         "ms_per_step": launch_ms, "wall_s": wall, "mlups": mlups,
         "bytes_per_cell_update": bpc, "achieved_GBs": achieved,
         "frac_hbm_peak": achieved / HBM_PEAK_GBS, "finite": status == 0,
-        "nu_hot_wall": nu.nu_hot_wall, "block": [cav.p.block_x, cav.p.block_y],
+        "nu_hot_wall": nu.nu_hot_wall, "block": chosen,
     }
     cav.close()
     del cav
     torch.cuda.empty_cache()
     return out
+
+
+def copy_calibration(nbytes=4 << 30, reps=5, log=print):
+    """Plain device copy of a known size (the library's copy probe): the
+    reference for bandwidth and for scaling the FETCH_SIZE / WRITE_SIZE
+    counters of the step kernel (each launch reads and writes nbytes)."""
+    import torch
+    from paper_1710_04751_amd import capi
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    capi.lbm_copy_probe(b.data_ptr(), a.data_ptr(), nbytes)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        capi.lbm_copy_probe(b.data_ptr(), a.data_ptr(), nbytes)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    gbs = 2 * nbytes / (ms * 1e-3) / 1e9
+    log(f"copy probe: {nbytes >> 30} GiB in {ms:.3f} ms -> {gbs:.1f} GB/s read+write")
+    return {"bytes_per_launch_each_way": nbytes, "ms": ms, "GBs": gbs}
 
 
 def cpu_baseline(n_full, ra, seconds_hint=15.0, log=print):
@@ -135,6 +166,7 @@ def main():
         sys.exit(1)
 
     block = tuple(int(v) for v in args.block.split(",")) if args.block else None
+    copy = copy_calibration(log=log)
     log(f"bench: {args.n}^3 Ra={args.Ra:g} D3Q7, {args.steps} timed steps, warmup {args.warmup}")
     main_line = time_variant(args.n, args.Ra, "fp32", args.steps, args.warmup, block, log)
     log(json.dumps(main_line))
@@ -177,6 +209,7 @@ def main():
                          "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": round(f16["frac_hbm_peak"], 4), "traffic": None},
         },
+        "copy_probe": {"GBs": round(copy["GBs"], 1), "bytes": copy["bytes_per_launch_each_way"]},
         "cpu_baseline": cpu,
     }
     print(json.dumps(rec), flush=True)

@@ -119,7 +119,9 @@ bool validate(const lbm_params* p, lbm_lattice* L, std::string* why) {
     }
     const int64_t ncell = (int64_t)p->nx * p->ny * p->nz;
     const int vb = value_bytes((Prec)p->precision);
-    if ((uint64_t)ncell * (uint64_t)vb >= (1ull << 32) || ncell >= (1ll << 31)) {
+    const uint64_t pop_bytes = align_up((size_t)ncell, 256) * (uint64_t)vb;
+    if (pop_bytes >= (1ull << 32) || ncell >= (1ll << 31)) {
+        // one population array must fit a 32-bit buffer offset
         *why = "grid too large for 32-bit per-population offsets";
         return false;
     }
@@ -143,8 +145,10 @@ Layout layout_of(const lbm_params* p) {
     return l;
 }
 
+// Fastest measured shape for large boxes is 128 x 2 (256 threads); small
+// boxes use rows rounded up to 16 cells.
 void default_block(int nx, int* bx, int* by) {
-    int b = nx <= 16 ? 16 : nx <= 32 ? 32 : nx <= 64 ? 64 : nx <= 128 ? 128 : 256;
+    int b = nx <= 16 ? 16 : nx <= 32 ? 32 : nx <= 64 ? 64 : 128;
     *bx = b;
     *by = std::max(1, 256 / b);
 }

@@ -69,6 +69,54 @@ struct Store<_Float16> {
     }
 };
 
+// Range-checked population access.  Every load and store of the step kernel
+// goes through a raw buffer resource whose record count is the byte size of
+// one population array: the hardware returns 0 for a load and drops a store
+// outside it, so no index, however computed, can touch memory beyond the
+// array.  Offsets are 32-bit byte offsets from a scalar base.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t pop_rsrc(const void* base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes,
+                                             0x00020000);
+}
+constexpr int kNonTemporal = 2;  // cache policy of the stores: non-temporal
+
+template <typename S>
+struct Buf;
+template <>
+struct Buf<float> {
+    template <typename R>
+    __device__ static R ld(__amdgpu_buffer_rsrc_t r, uint32_t i) {
+        return (R)__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, i * 4u, 0, 0));
+    }
+    __device__ static void st(__amdgpu_buffer_rsrc_t r, uint32_t i, float v) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, i * 4u, 0,
+                                              kNonTemporal);
+    }
+};
+template <>
+struct Buf<double> {
+    typedef unsigned v2u __attribute__((ext_vector_type(2)));
+    template <typename R>
+    __device__ static R ld(__amdgpu_buffer_rsrc_t r, uint32_t i) {
+        return (R)__builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, i * 8u, 0, 0));
+    }
+    __device__ static void st(__amdgpu_buffer_rsrc_t r, uint32_t i, double v) {
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2u, v), r, i * 8u, 0, kNonTemporal);
+    }
+};
+template <>
+struct Buf<_Float16> {
+    template <typename R>
+    __device__ static R ld(__amdgpu_buffer_rsrc_t r, uint32_t i) {
+        return (R)(float)__builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, i * 2u, 0, 0));
+    }
+    __device__ static void st(__amdgpu_buffer_rsrc_t r, uint32_t i, float v) {
+        // round to nearest even
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, (_Float16)v), r,
+                                              i * 2u, 0, kNonTemporal);
+    }
+};
+
 // Block number -> tile number, so that XCD k (hardware places block b on XCD
 // b mod 8) receives the contiguous tile range [start_k, start_k + count_k).
 __device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t nb) {
@@ -145,6 +193,7 @@ k_step(const S* __restrict__ Fi, const S* __restrict__ Gi, S* __restrict__ Fo,
     const bool ylo = p.y == 0, yhi = p.y == g.ny - 1;
     const bool zlo = p.z == 0, zhi = p.z == g.nz - 1;
 
+    const uint32_t pb = (uint32_t)(ps * (int64_t)sizeof(S));  // bytes of one population array
     R d[15];
 #pragma unroll
     for (int a = 0; a < 15; ++a) {
@@ -152,8 +201,10 @@ k_step(const S* __restrict__ Fi, const S* __restrict__ Gi, S* __restrict__ Fo,
         const bool out = (ex > 0 && xlo) || (ex < 0 && xhi) || (ey > 0 && ylo) || (ey < 0 && yhi) ||
                          (ez > 0 && zlo) || (ez < 0 && zhi);
         const int32_t off = ex + ey * (int32_t)nx + ez * (int32_t)nxy;
-        const S* src = out ? (Fi + OPP15[a] * ps + cell) : (Fi + a * ps + (cell - off));
-        d[a] = Store<S>::template ld<R>(src);
+        // wall lanes take the opposite population of their own cell
+        R v = Buf<S>::template ld<R>(pop_rsrc(Fi + a * ps, pb), out ? cell : cell - off);
+        if (out) v = Buf<S>::template ld<R>(pop_rsrc(Fi + OPP15[a] * ps, pb), cell);
+        d[a] = v;
     }
     R gq[QT];
 #pragma unroll
@@ -166,12 +217,14 @@ k_step(const S* __restrict__ Fi, const S* __restrict__ Gi, S* __restrict__ Fo,
         const bool outyz = (ey > 0 && ylo) || (ey < 0 && yhi) || (ez > 0 && zlo) || (ez < 0 && zhi);
         const int32_t off = ex + ey * (int32_t)nx + ez * (int32_t)nxy;
         const bool out = outx || outyz;
-        const S* src = out ? (Gi + ob * ps + cell) : (Gi + a * ps + (cell - off));
-        R v = Store<S>::template ld<R>(src);
-        if (ex != 0) {
-            const R w = (a == 0) ? R(0) : ((ey == 0 && ez == 0) ? k.w_face : k.w_corner);
-            const R tw = ex > 0 ? k.T_hot : k.T_cold;  // source beyond x = -1/2 or x = nx - 1/2
-            v = outx ? (R(2) * w * tw - v) : v;
+        R v = Buf<S>::template ld<R>(pop_rsrc(Gi + a * ps, pb), out ? cell : cell - off);
+        if (out) {
+            v = Buf<S>::template ld<R>(pop_rsrc(Gi + ob * ps, pb), cell);
+            if (ex != 0 && outx) {
+                const R w = (ey == 0 && ez == 0) ? k.w_face : k.w_corner;
+                const R tw = ex > 0 ? k.T_hot : k.T_cold;  // source beyond x = -1/2 or nx - 1/2
+                v = R(2) * w * tw - v;
+            }
         }
         gq[a] = v;
     }
@@ -188,9 +241,9 @@ k_step(const S* __restrict__ Fi, const S* __restrict__ Gi, S* __restrict__ Fo,
         collide_thermal15<R, HG>(gq, ux, uy, uz, k.t);
 
 #pragma unroll
-    for (int a = 0; a < 15; ++a) Store<S>::st(Fo + a * ps + cell, d[a]);
+    for (int a = 0; a < 15; ++a) Buf<S>::st(pop_rsrc(Fo + a * ps, pb), cell, d[a]);
 #pragma unroll
-    for (int a = 0; a < QT; ++a) Store<S>::st(Go + a * ps + cell, gq[a]);
+    for (int a = 0; a < QT; ++a) Buf<S>::st(pop_rsrc(Go + a * ps, pb), cell, gq[a]);
 }
 
 // ---------------------------------------------------------------------------
