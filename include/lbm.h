@@ -105,6 +105,7 @@ typedef struct lbm_nu {
 } lbm_nu;
 
 typedef struct lbm_handle lbm_handle;
+typedef struct lbm_batch lbm_batch;
 
 /* Thread-local text of the last error (never NULL). */
 const char* lbm_last_error(void);
@@ -207,6 +208,78 @@ lbm_status lbm_autotune(lbm_handle* h, int32_t steps_per_trial, int32_t* block_x
  * multiple of 16) on stream: the reference kernel for bandwidth and
  * memory-counter calibration.  Asynchronous. */
 lbm_status lbm_copy_probe(void* dst, const void* src, size_t bytes, void* stream);
+
+
+/* ------------------------------------------------------------------------
+ * Batched form: many independent cavities (any sizes and parameters, one
+ * precision, scalar lattice and rate set) advanced together.  One step is
+ * one persistent launch over a device list of tiles (a tile is a few whole
+ * x-rows of one z-plane of one cavity); each member is updated exactly as
+ * by lbm_step.  Steps are replayed from a captured hipGraph.  Converged
+ * members leave the tile list (compacted on the device), so the graph is
+ * never re-captured for that.
+ * ---------------------------------------------------------------------- */
+
+/* Bytes of device workspace for n cavities p[0..n-1] (host array); 0 if any
+ * is invalid, if they differ in precision, thermal_q or in whether the
+ * higher-order rates are 1, or if n is not in [1, 255]. */
+size_t lbm_batch_workspace_bytes(const lbm_params* p, int32_t n);
+
+/* Create a batch over caller device memory (256-byte aligned, borrowed
+ * until lbm_batch_destroy) on stream; every member starts at rest and is
+ * active.  Launch shape: 256 threads per block, 8 blocks per compute unit,
+ * graphs of 100 steps (change with lbm_batch_set_launch or
+ * lbm_batch_autotune). */
+lbm_status lbm_batch_create(const lbm_params* p, int32_t n, void* workspace, size_t bytes,
+                            void* stream, lbm_batch** out);
+lbm_status lbm_batch_destroy(lbm_batch* b);
+
+/* Member i as a solver handle, for the observables (lbm_macros,
+ * lbm_nusselt, lbm_get_populations, lbm_init_macros, ...).  lbm_step and
+ * lbm_destroy refuse members.  Members may be re-initialised only while the
+ * batch has taken an even number of steps. NULL if i is out of range. */
+lbm_handle* lbm_batch_member(lbm_batch* b, int32_t i);
+
+/* Advance every active member nsteps steps.  Asynchronous. */
+lbm_status lbm_batch_step(lbm_batch* b, int64_t nsteps);
+
+/* Residual of every member (host arrays of n): max |T - T_snapshot| over its
+ * cells, then the snapshot is renewed (+inf on a member's first call;
+ * inactive members report their last value).  status[i] = LBM_OK or
+ * LBM_ERR_UNSTABLE (NaN/Inf).  Synchronises the stream. */
+lbm_status lbm_batch_residuals(lbm_batch* b, double* max_dT, int32_t* status);
+
+/* Set which members take part in later steps (host array of n, 0/1).
+ * Rebuilds the device tile list; asynchronous. */
+lbm_status lbm_batch_set_active(lbm_batch* b, const int32_t* active);
+
+/* Run every active member until its residual over check_every steps is
+ * below tol (or it becomes unstable, or max_steps is reached): steps in
+ * chunks of check_every (even), checks all residuals, retires converged
+ * members.  Outputs (host arrays of n, may be NULL): steps each member took
+ * to meet tol (-1 if it did not), final status (LBM_OK, LBM_ERR_UNSTABLE,
+ * or LBM_ERR_STATE if max_steps was reached first), last residual.
+ * Synchronises. */
+lbm_status lbm_batch_run_to_steady(lbm_batch* b, double tol, int64_t check_every,
+                                   int64_t max_steps, int64_t* steps, int32_t* status,
+                                   double* last_residual);
+
+/* Launch shape: threads per block (a multiple of 64, >= the largest nx, at
+ * most 1024), blocks per compute unit (1..32), steps per captured graph
+ * (even, 0 disables graphs). */
+lbm_status lbm_batch_set_launch(lbm_batch* b, int32_t threads, int32_t blocks_per_cu,
+                                int32_t graph_steps);
+
+/* Time candidate (threads, blocks per CU) shapes with HIP events over
+ * steps_per_trial steps each and keep the fastest; the trial steps advance
+ * the members.  Returns the chosen shape. */
+lbm_status lbm_batch_autotune(lbm_batch* b, int32_t steps_per_trial, int32_t* threads,
+                              int32_t* blocks_per_cu);
+
+/* Current launch: threads per block, grid blocks, active tiles (synchronises
+ * to read the device count), steps per graph, batch steps taken. */
+lbm_status lbm_batch_launch_info(lbm_batch* b, int32_t* threads, int32_t* grid_blocks,
+                                 int32_t* active_tiles, int32_t* graph_steps, int64_t* steps);
 
 #ifdef __cplusplus
 }

@@ -77,6 +77,27 @@ _SIGS = {
     "lbm_autotune": (ctypes.c_int, [H, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                     ctypes.POINTER(ctypes.c_int32)]),
     "lbm_copy_probe": (ctypes.c_int, [vp, vp, ctypes.c_size_t, vp]),
+    "lbm_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(lbm_params), ctypes.c_int32]),
+    "lbm_batch_create": (ctypes.c_int, [ctypes.POINTER(lbm_params), ctypes.c_int32, vp,
+                                        ctypes.c_size_t, vp, ctypes.POINTER(vp)]),
+    "lbm_batch_destroy": (ctypes.c_int, [vp]),
+    "lbm_batch_member": (vp, [vp, ctypes.c_int32]),
+    "lbm_batch_step": (ctypes.c_int, [vp, ctypes.c_int64]),
+    "lbm_batch_residuals": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_double),
+                                           ctypes.POINTER(ctypes.c_int32)]),
+    "lbm_batch_set_active": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_int32)]),
+    "lbm_batch_run_to_steady": (ctypes.c_int, [vp, ctypes.c_double, ctypes.c_int64,
+                                               ctypes.c_int64, ctypes.POINTER(ctypes.c_int64),
+                                               ctypes.POINTER(ctypes.c_int32),
+                                               ctypes.POINTER(ctypes.c_double)]),
+    "lbm_batch_set_launch": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "lbm_batch_autotune": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                          ctypes.POINTER(ctypes.c_int32)]),
+    "lbm_batch_launch_info": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_int32),
+                                             ctypes.POINTER(ctypes.c_int32),
+                                             ctypes.POINTER(ctypes.c_int32),
+                                             ctypes.POINTER(ctypes.c_int32),
+                                             ctypes.POINTER(ctypes.c_int64)]),
 }
 
 
@@ -216,3 +237,80 @@ def lbm_autotune(h, steps_per_trial):
 
 def lbm_copy_probe(dst, src, nbytes, stream_ptr=None):
     return check(lib().lbm_copy_probe(dst, src, int(nbytes), stream_ptr or None))
+
+
+# -- batched form ----------------------------------------------------------
+
+def _params_array(params):
+    arr = (lbm_params * len(params))(*params)
+    return arr
+
+
+def lbm_batch_workspace_bytes(params):
+    n = lib().lbm_batch_workspace_bytes(_params_array(params), len(params))
+    if n == 0:
+        raise LbmError(LBM_ERR_ARG, lbm_last_error())
+    return n
+
+
+def lbm_batch_create(params, workspace_ptr, workspace_bytes, stream_ptr=None):
+    b = vp()
+    check(lib().lbm_batch_create(_params_array(params), len(params), workspace_ptr,
+                                 workspace_bytes, stream_ptr or None, ctypes.byref(b)))
+    return b
+
+
+def lbm_batch_destroy(b):
+    return check(lib().lbm_batch_destroy(b))
+
+
+def lbm_batch_member(b, i):
+    h = lib().lbm_batch_member(b, int(i))
+    if not h:
+        raise LbmError(LBM_ERR_ARG, "member index out of range")
+    return vp(h)
+
+
+def lbm_batch_step(b, nsteps):
+    return check(lib().lbm_batch_step(b, int(nsteps)))
+
+
+def lbm_batch_residuals(b, n):
+    r = (ctypes.c_double * n)()
+    st = (ctypes.c_int32 * n)()
+    check(lib().lbm_batch_residuals(b, r, st))
+    return list(r), list(st)
+
+
+def lbm_batch_set_active(b, active):
+    a = (ctypes.c_int32 * len(active))(*[1 if v else 0 for v in active])
+    return check(lib().lbm_batch_set_active(b, a))
+
+
+def lbm_batch_run_to_steady(b, n, tol, check_every, max_steps):
+    steps = (ctypes.c_int64 * n)()
+    st = (ctypes.c_int32 * n)()
+    res = (ctypes.c_double * n)()
+    check(lib().lbm_batch_run_to_steady(b, float(tol), int(check_every), int(max_steps),
+                                        steps, st, res))
+    return list(steps), list(st), list(res)
+
+
+def lbm_batch_set_launch(b, threads, blocks_per_cu, graph_steps):
+    return check(lib().lbm_batch_set_launch(b, int(threads), int(blocks_per_cu),
+                                            int(graph_steps)))
+
+
+def lbm_batch_autotune(b, steps_per_trial):
+    t, bp = ctypes.c_int32(), ctypes.c_int32()
+    check(lib().lbm_batch_autotune(b, int(steps_per_trial), ctypes.byref(t), ctypes.byref(bp)))
+    return t.value, bp.value
+
+
+def lbm_batch_launch_info(b):
+    t, g, at, gs = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    st = ctypes.c_int64()
+    check(lib().lbm_batch_launch_info(b, ctypes.byref(t), ctypes.byref(g), ctypes.byref(at),
+                                      ctypes.byref(gs), ctypes.byref(st)))
+    return {"threads": t.value, "grid_blocks": g.value, "active_tiles": at.value,
+            "graph_steps": gs.value, "steps": st.value}

@@ -12,13 +12,19 @@
 #include <string>
 #include <vector>
 
-#include "lbm_internal.hpp"
+#include "lbm_handle.hpp"
 
 using namespace lbm;
 
-namespace {
-
 thread_local std::string g_err;
+
+namespace {
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+}  // namespace
+
+namespace lbm {
+
 
 lbm_status fail(lbm_status s, const std::string& msg) {
     g_err = msg;
@@ -30,14 +36,7 @@ lbm_status hip_fail(hipError_t e, const char* what) {
     return LBM_ERR_HIP;
 }
 
-constexpr size_t kAlign = 256;
-size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-struct Layout {
-    int64_t ncell, ps;
-    size_t state_bytes;   // one of A, B
-    size_t off_A, off_B, off_snap, off_nu, off_red, total;
-};
 
 // Lattice values from parameters (reading of Sec. 3: the buoyancy velocity
 // scale sqrt(g beta dT L) is u0, L = nx; Ra = g beta dT L^3/(nu alpha),
@@ -153,32 +152,8 @@ void default_block(int nx, int* bx, int* by) {
     *by = std::max(1, 256 / b);
 }
 
-}  // namespace
 
-struct lbm_handle {
-    lbm_params p;
-    lbm_lattice L;
-    Coefs c;
-    Layout lay;
-    char* ws;
-    hipStream_t stream;
-    int cur;  // 0: state in A, 1: state in B
-    int64_t steps;
-    bool snap_valid;
-    bool general;
-    Geom geom;
-
-    StateBuf buf(int which) const {
-        char* base = ws + (which ? lay.off_B : lay.off_A);
-        const int vb = value_bytes((Prec)p.precision);
-        return StateBuf{base, base + (size_t)15 * lay.ps * vb};
-    }
-    double* nu_hot() const { return (double*)(ws + lay.off_nu); }
-    double* nu_cold() const { return nu_hot() + (size_t)p.ny * p.nz; }
-    double* red() const { return (double*)(ws + lay.off_red); }
-};
-
-static void set_geom(lbm_handle* h, int bx, int by) {
+void set_geom(lbm_handle* h, int bx, int by) {
     h->geom.nx = h->p.nx;
     h->geom.ny = h->p.ny;
     h->geom.nz = h->p.nz;
@@ -187,6 +162,51 @@ static void set_geom(lbm_handle* h, int bx, int by) {
     h->geom.tiles_x = (h->p.nx + bx - 1) / bx;
     h->geom.tiles_y = (h->p.ny + by - 1) / by;
 }
+
+lbm_status make_handle(const lbm_params* p, void* workspace, size_t bytes, void* stream,
+                       lbm_handle** out) {
+    std::string why;
+    lbm_lattice L;
+    if (!out) return fail(LBM_ERR_ARG, "null output handle");
+    *out = nullptr;
+    if (!validate(p, &L, &why)) return fail(LBM_ERR_ARG, why);
+    const Layout lay = layout_of(p);
+    if (!workspace || bytes < lay.total)
+        return fail(LBM_ERR_ARG, "workspace missing or smaller than lbm_workspace_bytes()");
+    if (((uintptr_t)workspace) % kAlign)
+        return fail(LBM_ERR_ARG, "workspace must be 256-byte aligned");
+    lbm_handle* h = new (std::nothrow) lbm_handle();
+    if (!h) return fail(LBM_ERR_STATE, "out of host memory");
+    h->p = *p;
+    h->L = L;
+    h->lay = lay;
+    h->ws = (char*)workspace;
+    h->stream = (hipStream_t)stream;
+    h->cur = 0;
+    h->steps = 0;
+    h->snap_valid = false;
+    h->general = p->omega_hi != 1.0 || p->omega_hi_T != 1.0;
+    h->c.omega = L.omega_nu;
+    h->c.omega_bulk = L.omega_bulk;
+    h->c.omega_hi = p->omega_hi;
+    h->c.omega_T = L.omega_T;
+    h->c.omega_hiT = p->omega_hi_T;
+    h->c.cs2 = p->cs2_T;
+    h->c.gbeta = L.gbeta;
+    h->c.T_ref = L.T_ref;
+    h->c.T_hot = p->T_hot;
+    h->c.T_cold = p->T_cold;
+    h->c.alpha = L.alpha;
+    h->c.fourth_maxwell = p->fourth_maxwell;
+    int bx = p->block_x, by = p->block_y;
+    if (!bx || !by) default_block(p->nx, &bx, &by);
+    set_geom(h, bx, by);
+    h->owner = nullptr;
+    *out = h;
+    return LBM_OK;
+}
+
+}  // namespace lbm
 
 extern "C" {
 
@@ -233,45 +253,16 @@ size_t lbm_workspace_bytes(const lbm_params* p) {
 
 lbm_status lbm_create(const lbm_params* p, void* workspace, size_t bytes, void* stream,
                       lbm_handle** out) {
-    std::string why;
-    lbm_lattice L;
-    if (!out) return fail(LBM_ERR_ARG, "null output handle");
-    *out = nullptr;
-    if (!validate(p, &L, &why)) return fail(LBM_ERR_ARG, why);
-    const Layout lay = layout_of(p);
-    if (!workspace || bytes < lay.total)
-        return fail(LBM_ERR_ARG, "workspace missing or smaller than lbm_workspace_bytes()");
-    if (((uintptr_t)workspace) % kAlign)
-        return fail(LBM_ERR_ARG, "workspace must be 256-byte aligned");
-    lbm_handle* h = new (std::nothrow) lbm_handle();
-    if (!h) return fail(LBM_ERR_STATE, "out of host memory");
-    h->p = *p;
-    h->L = L;
-    h->lay = lay;
-    h->ws = (char*)workspace;
-    h->stream = (hipStream_t)stream;
-    h->cur = 0;
-    h->steps = 0;
-    h->snap_valid = false;
-    h->general = p->omega_hi != 1.0 || p->omega_hi_T != 1.0;
-    h->c.omega = L.omega_nu;
-    h->c.omega_bulk = L.omega_bulk;
-    h->c.omega_hi = p->omega_hi;
-    h->c.omega_T = L.omega_T;
-    h->c.omega_hiT = p->omega_hi_T;
-    h->c.cs2 = p->cs2_T;
-    h->c.gbeta = L.gbeta;
-    h->c.T_ref = L.T_ref;
-    h->c.T_hot = p->T_hot;
-    h->c.T_cold = p->T_cold;
-    h->c.alpha = L.alpha;
-    h->c.fourth_maxwell = p->fourth_maxwell;
-    int bx = p->block_x, by = p->block_y;
-    if (!bx || !by) default_block(p->nx, &bx, &by);
-    set_geom(h, bx, by);
-    lbm_status s = lbm_init_rest(h);
+    lbm_handle* h = nullptr;
+    lbm_status s = make_handle(p, workspace, bytes, stream, &h);
+    if (s != LBM_OK) {
+        if (out) *out = nullptr;
+        return s;
+    }
+    s = lbm_init_rest(h);
     if (s != LBM_OK) {
         delete h;
+        *out = nullptr;
         return s;
     }
     *out = h;
@@ -279,6 +270,7 @@ lbm_status lbm_create(const lbm_params* p, void* workspace, size_t bytes, void* 
 }
 
 lbm_status lbm_destroy(lbm_handle* h) {
+    if (h && h->owner) return fail(LBM_ERR_STATE, "a batch member is released with its batch");
     delete h;
     return LBM_OK;
 }
@@ -293,6 +285,8 @@ int64_t lbm_steps_done(const lbm_handle* h) { return h ? h->steps : -1; }
 
 lbm_status lbm_init_rest(lbm_handle* h) {
     if (!h) return fail(LBM_ERR_ARG, "null handle");
+    if (h->owner && !batch_allows_reinit(h->owner))
+        return fail(LBM_ERR_STATE, "batch member re-initialised at an odd batch step");
     hipError_t e = launch_fill_zero(h->ws + h->lay.off_A, h->lay.state_bytes, h->stream);
     if (e != hipSuccess) return hip_fail(e, "init_rest");
     h->cur = 0;
@@ -304,6 +298,8 @@ lbm_status lbm_init_rest(lbm_handle* h) {
 lbm_status lbm_init_macros(lbm_handle* h, const float* ux, const float* uy, const float* uz,
                            const float* T) {
     if (!h) return fail(LBM_ERR_ARG, "null handle");
+    if (h->owner && !batch_allows_reinit(h->owner))
+        return fail(LBM_ERR_STATE, "batch member re-initialised at an odd batch step");
     hipError_t e = launch_init_macros((Prec)h->p.precision, h->p.thermal_q, h->geom, h->lay.ps,
                                       h->buf(0), ux, uy, uz, T, h->c, h->stream);
     if (e != hipSuccess) return hip_fail(e, "init_macros");
@@ -315,6 +311,7 @@ lbm_status lbm_init_macros(lbm_handle* h, const float* ux, const float* uy, cons
 
 lbm_status lbm_step(lbm_handle* h, int64_t nsteps) {
     if (!h) return fail(LBM_ERR_ARG, "null handle");
+    if (h->owner) return fail(LBM_ERR_STATE, "batch members are stepped by lbm_batch_step");
     if (nsteps < 0) return fail(LBM_ERR_ARG, "nsteps must be >= 0");
     const Prec pr = (Prec)h->p.precision;
     for (int64_t i = 0; i < nsteps; ++i) {
@@ -406,6 +403,8 @@ lbm_status lbm_get_populations(lbm_handle* h, double* F, double* G) {
 
 lbm_status lbm_set_populations(lbm_handle* h, const double* F, const double* G) {
     if (!h || !F || !G) return fail(LBM_ERR_ARG, "null argument");
+    if (h->owner && !batch_allows_reinit(h->owner))
+        return fail(LBM_ERR_STATE, "batch member re-initialised at an odd batch step");
     hipError_t e = launch_set_pops((Prec)h->p.precision, h->p.thermal_q, h->geom, h->lay.ps,
                                    h->buf(0), F, G, h->stream);
     if (e != hipSuccess) return hip_fail(e, "set_populations");

@@ -1,0 +1,59 @@
+// Host-side state of a solver handle and the helpers the C ABI and the
+// batched driver share.  Internal to the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "../../include/lbm.h"
+#include "lbm_internal.hpp"
+
+namespace lbm {
+
+struct Layout {
+    int64_t ncell, ps;
+    size_t state_bytes;   // one of A, B
+    size_t off_A, off_B, off_snap, off_nu, off_red, total;
+};
+
+lbm_status fail(lbm_status s, const std::string& msg);
+lbm_status hip_fail(hipError_t e, const char* what);
+bool validate(const lbm_params* p, lbm_lattice* L, std::string* why);
+Layout layout_of(const lbm_params* p);
+void default_block(int nx, int* bx, int* by);
+// Create a handle over caller memory without touching the device.
+lbm_status make_handle(const lbm_params* p, void* workspace, size_t bytes, void* stream,
+                       lbm_handle** out);
+
+}  // namespace lbm
+
+struct lbm_handle {
+    lbm_params p;
+    lbm_lattice L;
+    lbm::Coefs c;
+    lbm::Layout lay;
+    char* ws;
+    hipStream_t stream;
+    int cur;  // 0: state in A, 1: state in B
+    int64_t steps;
+    bool snap_valid;
+    bool general;
+    lbm::Geom geom;
+    lbm_batch* owner;  // set for members of a batch (the batch steps them)
+
+    lbm::StateBuf buf(int which) const {
+        char* base = ws + (which ? lay.off_B : lay.off_A);
+        const int vb = lbm::value_bytes((lbm::Prec)p.precision);
+        return lbm::StateBuf{base, base + (size_t)15 * lay.ps * vb};
+    }
+    double* nu_hot() const { return (double*)(ws + lay.off_nu); }
+    double* nu_cold() const { return nu_hot() + (size_t)p.ny * p.nz; }
+    double* red() const { return (double*)(ws + lay.off_red); }
+};
+
+namespace lbm {
+void set_geom(lbm_handle* h, int bx, int by);
+// A member of a batch may be re-initialised only at an even batch step.
+bool batch_allows_reinit(const lbm_batch* b);
+}

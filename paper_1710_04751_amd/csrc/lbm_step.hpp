@@ -1,0 +1,201 @@
+// Shared device code of the fused step: lattice tables, range-checked
+// population access and the per-cell stream-collide update.  Included by
+// the single-cavity kernels (lbm_kernels.hip) and the batched kernels
+// (lbm_batch.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lbm_device.hpp"
+#include "lbm_internal.hpp"
+
+namespace lbm {
+namespace kern {
+
+
+constexpr int EX15[15] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1};
+constexpr int EY15[15] = {0, 0, 0, 1, -1, 0, 0, 1, 1, -1, -1, 1, 1, -1, -1};
+constexpr int EZ15[15] = {0, 0, 0, 0, 0, 1, -1, 1, 1, 1, 1, -1, -1, -1, -1};
+constexpr int OPP15[15] = {0, 2, 1, 4, 3, 6, 5, 14, 13, 12, 11, 10, 9, 8, 7};
+constexpr int EX7[7] = {0, 1, -1, 0, 0, 0, 0};
+constexpr int EY7[7] = {0, 0, 0, 1, -1, 0, 0};
+constexpr int EZ7[7] = {0, 0, 0, 0, 0, 1, -1};
+constexpr int OPP7[7] = {0, 2, 1, 4, 3, 6, 5};
+
+// Rest-state flow weights (D3Q15, c_s^2 = 1/3).
+__device__ __forceinline__ double flow_weight(int a) {
+    return a == 0 ? 2.0 / 9.0 : (a <= 6 ? 1.0 / 9.0 : 1.0 / 72.0);
+}
+
+template <typename S>
+struct Store;
+template <>
+struct Store<double> {
+    template <typename R>
+    __device__ static R ld(const double* p) { return (R)*p; }
+    __device__ static void st(double* p, double v) { __builtin_nontemporal_store(v, p); }
+};
+template <>
+struct Store<float> {
+    template <typename R>
+    __device__ static R ld(const float* p) { return (R)*p; }
+    __device__ static void st(float* p, float v) { __builtin_nontemporal_store(v, p); }
+};
+template <>
+struct Store<_Float16> {
+    template <typename R>
+    __device__ static R ld(const _Float16* p) { return (R)(float)*p; }
+    __device__ static void st(_Float16* p, float v) {
+        __builtin_nontemporal_store((_Float16)v, p);  // round to nearest even
+    }
+};
+
+// Range-checked population access.  Every load and store of the step kernel
+// goes through a raw buffer resource whose record count is the byte size of
+// one population array: the hardware returns 0 for a load and drops a store
+// outside it, so no index, however computed, can touch memory beyond the
+// array.  Offsets are 32-bit byte offsets from a scalar base.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t pop_rsrc(const void* base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes,
+                                             0x00020000);
+}
+constexpr int kNonTemporal = 2;  // cache policy of the stores: non-temporal
+
+template <typename S>
+struct Buf;
+template <>
+struct Buf<float> {
+    template <typename R>
+    __device__ static R ld(__amdgpu_buffer_rsrc_t r, uint32_t i) {
+        return (R)__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, i * 4u, 0, 0));
+    }
+    __device__ static void st(__amdgpu_buffer_rsrc_t r, uint32_t i, float v) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, i * 4u, 0,
+                                              kNonTemporal);
+    }
+};
+template <>
+struct Buf<double> {
+    typedef unsigned v2u __attribute__((ext_vector_type(2)));
+    template <typename R>
+    __device__ static R ld(__amdgpu_buffer_rsrc_t r, uint32_t i) {
+        return (R)__builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, i * 8u, 0, 0));
+    }
+    __device__ static void st(__amdgpu_buffer_rsrc_t r, uint32_t i, double v) {
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2u, v), r, i * 8u, 0, kNonTemporal);
+    }
+};
+template <>
+struct Buf<_Float16> {
+    template <typename R>
+    __device__ static R ld(__amdgpu_buffer_rsrc_t r, uint32_t i) {
+        return (R)(float)__builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, i * 2u, 0, 0));
+    }
+    __device__ static void st(__amdgpu_buffer_rsrc_t r, uint32_t i, float v) {
+        // round to nearest even
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, (_Float16)v), r,
+                                              i * 2u, 0, kNonTemporal);
+    }
+};
+
+template <typename R>
+struct KCoef {
+    FlowCoef<R> f;
+    ThermCoef<R> t;
+    R T_hot, T_cold;
+    R w_face, w_corner;  // rest weights of the scalar (anti-bounce-back)
+};
+
+template <typename R>
+KCoef<R> make_kcoef(const Coefs& c, int qt) {
+    KCoef<R> k;
+    k.f.omega = (R)c.omega;
+    k.f.omega_bulk = (R)c.omega_bulk;
+    k.f.omega_hi = (R)c.omega_hi;
+    k.f.gbeta = (R)c.gbeta;
+    k.f.T_ref = (R)c.T_ref;
+    k.f.fourth_maxwell = c.fourth_maxwell;
+    k.t.omega_T = (R)c.omega_T;
+    k.t.omega_hiT = (R)c.omega_hiT;
+    k.t.cs2 = (R)c.cs2;
+    k.T_hot = (R)c.T_hot;
+    k.T_cold = (R)c.T_cold;
+    if (qt == 7) {
+        k.w_face = (R)(c.cs2 / 2);
+        k.w_corner = 0;
+    } else {
+        k.w_face = (R)((c.cs2 - c.cs2 * c.cs2) / 2);
+        k.w_corner = (R)(c.cs2 * c.cs2 / 8);
+    }
+    return k;
+}
+
+// ---------------------------------------------------------------------------
+// Fused stream-collide update of one cell (shared by the single-cavity and
+// the batched kernels, so both compute bit-identical results)
+// ---------------------------------------------------------------------------
+template <typename R, typename S, int QT, bool HG>
+__device__ __forceinline__ void update_cell(const S* __restrict__ Fi, const S* __restrict__ Gi,
+                                            S* __restrict__ Fo, S* __restrict__ Go, int64_t ps,
+                                            uint32_t cell, int x, int y, int z, int nxi, int nyi,
+                                            int nzi, const KCoef<R>& k) {
+    const uint32_t nx = (uint32_t)nxi, nxy = (uint32_t)nxi * (uint32_t)nyi;
+    const bool xlo = x == 0, xhi = x == nxi - 1;
+    const bool ylo = y == 0, yhi = y == nyi - 1;
+    const bool zlo = z == 0, zhi = z == nzi - 1;
+    const uint32_t pb = (uint32_t)(ps * (int64_t)sizeof(S));  // bytes of one population array
+    R d[15];
+#pragma unroll
+    for (int a = 0; a < 15; ++a) {
+        const int ex = EX15[a], ey = EY15[a], ez = EZ15[a];
+        const bool out = (ex > 0 && xlo) || (ex < 0 && xhi) || (ey > 0 && ylo) || (ey < 0 && yhi) ||
+                         (ez > 0 && zlo) || (ez < 0 && zhi);
+        const int32_t off = ex + ey * (int32_t)nx + ez * (int32_t)nxy;
+        // wall lanes take the opposite population of their own cell
+        R v = Buf<S>::template ld<R>(pop_rsrc(Fi + a * ps, pb), out ? cell : cell - off);
+        if (out) v = Buf<S>::template ld<R>(pop_rsrc(Fi + OPP15[a] * ps, pb), cell);
+        d[a] = v;
+    }
+    R gq[QT];
+#pragma unroll
+    for (int a = 0; a < QT; ++a) {
+        const int ex = QT == 7 ? EX7[a] : EX15[a];
+        const int ey = QT == 7 ? EY7[a] : EY15[a];
+        const int ez = QT == 7 ? EZ7[a] : EZ15[a];
+        const int ob = QT == 7 ? OPP7[a] : OPP15[a];
+        const bool outx = (ex > 0 && xlo) || (ex < 0 && xhi);
+        const bool outyz = (ey > 0 && ylo) || (ey < 0 && yhi) || (ez > 0 && zlo) || (ez < 0 && zhi);
+        const int32_t off = ex + ey * (int32_t)nx + ez * (int32_t)nxy;
+        const bool out = outx || outyz;
+        R v = Buf<S>::template ld<R>(pop_rsrc(Gi + a * ps, pb), out ? cell : cell - off);
+        if (out) {
+            v = Buf<S>::template ld<R>(pop_rsrc(Gi + ob * ps, pb), cell);
+            if (ex != 0 && outx) {
+                const R w = (ey == 0 && ez == 0) ? k.w_face : k.w_corner;
+                const R tw = ex > 0 ? k.T_hot : k.T_cold;  // source beyond x = -1/2 or nx - 1/2
+                v = R(2) * w * tw - v;
+            }
+        }
+        gq[a] = v;
+    }
+
+    R T = 0;
+#pragma unroll
+    for (int a = 0; a < QT; ++a) T += gq[a];
+    const R Fz = k.f.gbeta * (T - k.f.T_ref);
+    R ux, uy, uz;
+    collide_flow<R, HG>(d, Fz, k.f, ux, uy, uz);
+    if constexpr (QT == 7)
+        collide_thermal7<R, HG>(gq, ux, uy, uz, k.t);
+    else
+        collide_thermal15<R, HG>(gq, ux, uy, uz, k.t);
+
+#pragma unroll
+    for (int a = 0; a < 15; ++a) Buf<S>::st(pop_rsrc(Fo + a * ps, pb), cell, d[a]);
+#pragma unroll
+    for (int a = 0; a < QT; ++a) Buf<S>::st(pop_rsrc(Go + a * ps, pb), cell, gq[a]);
+}
+
+}  // namespace kern
+}  // namespace lbm

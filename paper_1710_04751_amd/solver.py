@@ -73,6 +73,7 @@ class Cavity:
     def macros(self, fp64=True):
         dt = torch.float64 if fp64 else torch.float32
         out = self._empty(5, dtype=dt)
+        self._inputs_ready()
         capi.lbm_macros(self.h, *[out[i].data_ptr() for i in range(5)], fp64=fp64)
         self._sync_if_needed()
         return {"rho": out[0], "ux": out[1], "uy": out[2], "uz": out[3], "T": out[4]}
@@ -81,7 +82,9 @@ class Cavity:
         if local:
             lh = torch.empty(self.p.nz, self.p.ny, dtype=torch.float64, device=self.device)
             lc = torch.empty_like(lh)
+            self._inputs_ready()
             r = capi.lbm_nusselt(self.h, lh.data_ptr(), lc.data_ptr())
+            self._sync_if_needed()
             return r, lh, lc
         return capi.lbm_nusselt(self.h)
 
@@ -91,6 +94,7 @@ class Cavity:
     def populations(self):
         F = self._empty(15)
         G = self._empty(self.p.thermal_q)
+        self._inputs_ready()
         capi.lbm_get_populations(self.h, F.data_ptr(), G.data_ptr())
         self._sync_if_needed()
         return F, G
@@ -130,7 +134,8 @@ class Cavity:
         capi.lbm_set_block(self.h, bx, by)
 
     def _inputs_ready(self):
-        # inputs were produced on torch's current stream
+        # inputs were produced, and output buffers allocated, on torch's
+        # current stream: the library's stream must not run ahead of them
         if self.stream is not None:
             self.stream.wait_stream(torch.cuda.current_stream(self.device))
 
@@ -144,6 +149,78 @@ class Cavity:
         if getattr(self, "h", None):
             capi.lbm_destroy(self.h)
             self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class _Member(Cavity):
+    """A batch member viewed as a cavity (observables only)."""
+
+    def __init__(self, batch, i, params):
+        self.p = params
+        self.device = batch.device
+        self.stream = batch.stream
+        self.h = capi.lbm_batch_member(batch.b, i)
+        self.lattice = capi.lbm_get_lattice(self.h)
+        self._batch = batch
+
+    def close(self):  # released with the batch
+        self.h = None
+
+
+class Batch:
+    """Many cavities advanced together (persistent launch, hipGraph)."""
+
+    def __init__(self, params_list, device="cuda", stream=None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("a HIP device is required")
+        self.params = list(params_list)
+        self.n = len(self.params)
+        self.device = torch.device(device)
+        # graphs need a stream of their own
+        self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+        self.nbytes = capi.lbm_batch_workspace_bytes(self.params)
+        self._raw = torch.empty(self.nbytes + 256, dtype=torch.uint8, device=self.device)
+        ptr = (self._raw.data_ptr() + 255) // 256 * 256
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        self.b = capi.lbm_batch_create(self.params, ptr, self.nbytes, self.stream.cuda_stream)
+        self.members = [_Member(self, i, self.params[i]) for i in range(self.n)]
+
+    @property
+    def cells(self):
+        return sum(p.nx * p.ny * p.nz for p in self.params)
+
+    def step(self, nsteps):
+        capi.lbm_batch_step(self.b, nsteps)
+
+    def residuals(self):
+        return capi.lbm_batch_residuals(self.b, self.n)
+
+    def set_active(self, active):
+        capi.lbm_batch_set_active(self.b, active)
+
+    def run_to_steady(self, tol, check_every=1000, max_steps=10 ** 6):
+        return capi.lbm_batch_run_to_steady(self.b, self.n, tol, check_every, max_steps)
+
+    def set_launch(self, threads, blocks_per_cu, graph_steps):
+        capi.lbm_batch_set_launch(self.b, threads, blocks_per_cu, graph_steps)
+
+    def autotune(self, steps_per_trial=10):
+        return capi.lbm_batch_autotune(self.b, steps_per_trial)
+
+    def launch_info(self):
+        return capi.lbm_batch_launch_info(self.b)
+
+    def close(self):
+        if getattr(self, "b", None):
+            for m in self.members:
+                m.close()
+            capi.lbm_batch_destroy(self.b)
+            self.b = None
 
     def __del__(self):
         try:

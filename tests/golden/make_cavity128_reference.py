@@ -1,0 +1,46 @@
+"""Write tests/golden/cavity128_ra1e6_d3q7_2500.npz with the CPU oracle.
+
+The 128^3 cavity at Ra = 1e6, Pr = 0.71, u0 = 0.05, D3Q7 scalar, started
+from rest, advanced 2500 steps: the same physical time (t u0 / L) as 10,000
+steps of the 512^3 cavity.  Stored: the macroscopic fields (rho, ux, uy, uz,
+T, float32) on the mid-planes y = 64 and z = 64 (0-based cell indices), the
+points the 512^3 fields are compared at after averaging each 4x4x4 block.
+
+Only the oracle is called.  Runtime: several CPU hours (OpenMP threads from
+ORACLE_THREADS, default all cores).
+"""
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+from oracle import oracle as O  # noqa: E402
+
+N, RA, STEPS = 128, 1e6, 2500
+OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "cavity128_ra1e6_d3q7_2500.npz")
+
+
+def main():
+    threads = O.set_threads(int(os.environ.get("ORACLE_THREADS", "0")) or (os.cpu_count() or 1))
+    p = O.cavity_params(N, RA)
+    F, G = O.rest_state(p)
+    t0 = time.time()
+    done, chunk = 0, 100
+    while done < STEPS:
+        k = min(chunk, STEPS - done)
+        F, G, mac = O.run(p, k, F, G)
+        done += k
+        print(f"{done}/{STEPS} steps, {time.time() - t0:.0f} s, {threads} threads", flush=True)
+    np.savez_compressed(
+        OUT, steps=STEPS, n=N, Ra=RA, plane_y=64, plane_z=64,
+        y64=mac[:, :, 64, :].astype(np.float32), z64=mac[:, 64, :, :].astype(np.float32),
+        fields=np.array(["rho", "ux", "uy", "uz", "T"]))
+    print("wrote", OUT, flush=True)
+
+
+if __name__ == "__main__":
+    main()

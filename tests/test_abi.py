@@ -80,3 +80,19 @@ def test_workspace_checks_before_any_device_work(capi):
         capi.lbm_create(p, 0x1001, nbytes)  # misaligned
     with pytest.raises(capi.LbmError):
         capi.lbm_copy_probe(0x1000, 0x2000, 17)
+
+
+def test_batch_validation_on_host(capi):
+    a = capi.lbm_params_init(32, 1e4)
+    b = capi.lbm_params_init(48, 1e5)
+    n2 = capi.lbm_batch_workspace_bytes([a, b])
+    assert n2 >= capi.lbm_workspace_bytes(a) + capi.lbm_workspace_bytes(b)
+    b.precision = capi.LBM_FP64
+    with pytest.raises(capi.LbmError, match="share precision"):
+        capi.lbm_batch_workspace_bytes([a, b])
+    b.precision = a.precision
+    b.nx = 3
+    with pytest.raises(capi.LbmError, match="member 1"):
+        capi.lbm_batch_workspace_bytes([a, b])
+    with pytest.raises(capi.LbmError, match="1 to 255"):
+        capi.lbm_batch_workspace_bytes([a] * 256)
