@@ -104,6 +104,28 @@ typedef struct lbm_nu {
     double nu_min, z_min;             /* min, at z/L */
 } lbm_nu;
 
+/* Peak velocities on the symmetry plane y = L/2, the quantities Table 1 of
+ * the paper reports, in units of u0.  Positions follow the paper's axes
+ * (heated axis from the cold wall, height from the bottom), in units of L. */
+typedef struct lbm_peaks {
+    double u_max; /* max over height of the velocity along the heated axis
+                     pointing from the cold to the hot wall (-u_x), on the
+                     vertical centreline x = L/2 */
+    double u_pos; /* its height z/L */
+    double w_max; /* max of the vertical velocity u_z on the horizontal
+                     centreline z = L/2 */
+    double w_pos; /* its distance from the cold wall, over L */
+} lbm_peaks;
+
+/* How a run to steady state ended. */
+typedef enum {
+    LBM_STEADY_TOL = 0,       /* residual below the tolerance */
+    LBM_STEADY_PLATEAU = 1,   /* residual stopped falling above the tolerance
+                                 (the precision's floor) */
+    LBM_STEADY_MAX_STEPS = 2, /* step limit reached first */
+    LBM_STEADY_UNSTABLE = 3   /* NaN or Inf appeared */
+} lbm_steady;
+
 typedef struct lbm_handle lbm_handle;
 typedef struct lbm_batch lbm_batch;
 
@@ -170,6 +192,31 @@ lbm_status lbm_nusselt(lbm_handle* h, lbm_nu* out, double* local_hot, double* lo
  * initialisation only takes the snapshot and reports +inf.  Returns
  * LBM_ERR_UNSTABLE if any T is NaN or Inf.  Synchronises the stream. */
 lbm_status lbm_residual(lbm_handle* h, double* max_dT);
+
+/* Velocity profiles on the symmetry plane y = L/2 (FP64, device kernel):
+ * u_line[nz] = -u_x / u0 along the vertical centreline x = L/2, w_line[nx]
+ * = u_z / u0 along the horizontal centreline z = L/2, pre-collision moments
+ * of the current step as in lbm_macros.  An even number of cells across a
+ * centreline averages the two middle cells.  u_line, w_line: device
+ * pointers, may be NULL.  peaks (host pointer, may be NULL): maxima of the
+ * two profiles, each refined by the parabola through the largest sample and
+ * its two neighbours (cell centres sit at (i + 1/2)/N).  Synchronises the
+ * stream when peaks is given. */
+lbm_status lbm_centerlines(lbm_handle* h, double* u_line, double* w_line, lbm_peaks* peaks);
+
+/* Step until steady: every check_every steps (even, > 0) take lbm_residual;
+ * stop when it is below tol (LBM_STEADY_TOL), or when plateau_checks > 0
+ * and it has not reached a new minimum for plateau_checks checks in a row
+ * (LBM_STEADY_PLATEAU: the steady state is the precision's floor; *steps
+ * is then the step at which the minimum was first seen), or after
+ * max_steps (LBM_STEADY_MAX_STEPS).  The first check only takes the
+ * snapshot.  Outputs (host pointers, may be NULL): steps taken to the
+ * stopping criterion, how it ended (lbm_steady), the last residual.
+ * Returns LBM_ERR_UNSTABLE (with *how = LBM_STEADY_UNSTABLE) on NaN/Inf.
+ * Synchronises. */
+lbm_status lbm_run_to_steady(lbm_handle* h, double tol, int64_t check_every, int64_t max_steps,
+                             int32_t plateau_checks, int64_t* steps, int32_t* how,
+                             double* last_residual);
 
 /* Full populations as FP64 (device pointers): F [15][ncell], G [q][ncell]
  * (f itself, not the stored deviation).  Either may be NULL.  Asynchronous. */
@@ -253,16 +300,15 @@ lbm_status lbm_batch_residuals(lbm_batch* b, double* max_dT, int32_t* status);
  * Rebuilds the device tile list; asynchronous. */
 lbm_status lbm_batch_set_active(lbm_batch* b, const int32_t* active);
 
-/* Run every active member until its residual over check_every steps is
- * below tol (or it becomes unstable, or max_steps is reached): steps in
- * chunks of check_every (even), checks all residuals, retires converged
- * members.  Outputs (host arrays of n, may be NULL): steps each member took
- * to meet tol (-1 if it did not), final status (LBM_OK, LBM_ERR_UNSTABLE,
- * or LBM_ERR_STATE if max_steps was reached first), last residual.
- * Synchronises. */
+/* Run every active member to steady state with the rule of
+ * lbm_run_to_steady (tolerance, plateau, step limit), checking all members
+ * every check_every steps (even) and retiring each as it stops.  Outputs
+ * (host arrays of n, may be NULL): steps each member took to its stopping
+ * criterion (-1 if it hit max_steps or became unstable), how it ended
+ * (lbm_steady), last residual.  Synchronises. */
 lbm_status lbm_batch_run_to_steady(lbm_batch* b, double tol, int64_t check_every,
-                                   int64_t max_steps, int64_t* steps, int32_t* status,
-                                   double* last_residual);
+                                   int64_t max_steps, int32_t plateau_checks, int64_t* steps,
+                                   int32_t* how, double* last_residual);
 
 /* Launch shape: threads per block (a multiple of 64, >= the largest nx, at
  * most 1024), blocks per compute unit (1..32), steps per captured graph

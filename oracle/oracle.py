@@ -234,3 +234,46 @@ def midline_profile(local_nu):
     if ny % 2:
         return local_nu[:, ny // 2].copy()
     return 0.5 * (local_nu[:, ny // 2 - 1] + local_nu[:, ny // 2])
+
+
+def _middle(n):
+    """Indices of the cells across the centre of n cells: one for odd n, the
+    two middle ones for even n."""
+    return list(range((n - 1) // 2, n // 2 + 1))
+
+
+def centerline_profiles(mac, u0):
+    """Velocity profiles on the symmetry plane y = L/2 (Table 1 quantities),
+    in units of u0, from the macroscopic fields mac[5][nz][ny][nx]:
+    u_line[z] = -u_x on the vertical centreline x = L/2 (the velocity along
+    the heated axis pointing from the cold to the hot wall), and
+    w_line[x] = u_z on the horizontal centreline z = L/2."""
+    _, nz, ny, nx = mac.shape
+    ys, xs, zs = _middle(ny), _middle(nx), _middle(nz)
+    u_line = np.array([-np.mean([mac[1, z, y, x] for y in ys for x in xs]) for z in range(nz)])
+    w_line = np.array([np.mean([mac[3, z, y, x] for z in zs for y in ys]) for x in range(nx)])
+    return u_line / u0, w_line / u0
+
+
+def parabola_peak(v):
+    """Maximum of samples v[i] taken at (i + 1/2)/n, refined by the parabola
+    through the largest sample and its two neighbours; (value, position)."""
+    n = len(v)
+    k = int(np.argmax(v))
+    if 0 < k < n - 1:
+        a, b, c = v[k - 1], v[k], v[k + 1]
+        curv = a - 2 * b + c
+        if curv < 0:
+            off = 0.5 * (a - c) / curv
+            return b - 0.25 * (a - c) * off, (k + 0.5 + off) / n
+    return float(v[k]), (k + 0.5) / n
+
+
+def table1_peaks(mac, u0):
+    """u_max with its height z/L, and w_max with its distance from the cold
+    wall over L (the paper's heated axis runs from the cold to the hot wall),
+    each from centerline_profiles."""
+    u_line, w_line = centerline_profiles(mac, u0)
+    u_max, u_pos = parabola_peak(u_line)
+    w_max, w_pos = parabola_peak(w_line[::-1])
+    return {"u_max": u_max, "u_pos": u_pos, "w_max": w_max, "w_pos": w_pos}

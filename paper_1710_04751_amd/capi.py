@@ -39,6 +39,13 @@ class lbm_nu(ctypes.Structure):
                  "nu_max", "z_max", "nu_min", "z_min")]
 
 
+class lbm_peaks(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in ("u_max", "u_pos", "w_max", "w_pos")]
+
+
+LBM_STEADY_TOL, LBM_STEADY_PLATEAU, LBM_STEADY_MAX_STEPS, LBM_STEADY_UNSTABLE = 0, 1, 2, 3
+
+
 class LbmError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"lbm status {status}: {msg}")
@@ -66,6 +73,11 @@ _SIGS = {
     "lbm_macros": (ctypes.c_int, [H, vp, vp, vp, vp, vp, ctypes.c_int]),
     "lbm_nusselt": (ctypes.c_int, [H, ctypes.POINTER(lbm_nu), vp, vp]),
     "lbm_residual": (ctypes.c_int, [H, ctypes.POINTER(ctypes.c_double)]),
+    "lbm_centerlines": (ctypes.c_int, [H, vp, vp, ctypes.POINTER(lbm_peaks)]),
+    "lbm_run_to_steady": (ctypes.c_int, [H, ctypes.c_double, ctypes.c_int64, ctypes.c_int64,
+                                         ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
+                                         ctypes.POINTER(ctypes.c_int32),
+                                         ctypes.POINTER(ctypes.c_double)]),
     "lbm_get_populations": (ctypes.c_int, [H, vp, vp]),
     "lbm_set_populations": (ctypes.c_int, [H, vp, vp]),
     "lbm_gather_cells": (ctypes.c_int, [H, vp, ctypes.c_int64, vp, vp, ctypes.c_int]),
@@ -87,7 +99,8 @@ _SIGS = {
                                            ctypes.POINTER(ctypes.c_int32)]),
     "lbm_batch_set_active": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_int32)]),
     "lbm_batch_run_to_steady": (ctypes.c_int, [vp, ctypes.c_double, ctypes.c_int64,
-                                               ctypes.c_int64, ctypes.POINTER(ctypes.c_int64),
+                                               ctypes.c_int64, ctypes.c_int32,
+                                               ctypes.POINTER(ctypes.c_int64),
                                                ctypes.POINTER(ctypes.c_int32),
                                                ctypes.POINTER(ctypes.c_double)]),
     "lbm_batch_set_launch": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
@@ -202,6 +215,23 @@ def lbm_residual(h):
     return s, v.value
 
 
+def lbm_centerlines(h, u_line=None, w_line=None, peaks=True):
+    """Returns an lbm_peaks (synchronising) when peaks is true, else None."""
+    pk = lbm_peaks() if peaks else None
+    check(lib().lbm_centerlines(h, u_line, w_line, ctypes.byref(pk) if peaks else None))
+    return pk
+
+
+def lbm_run_to_steady(h, tol, check_every, max_steps, plateau_checks=0):
+    """Returns (steps, how, last residual); how is an LBM_STEADY_* value.  An
+    unstable run raises LbmError(LBM_ERR_UNSTABLE)."""
+    steps, how, res = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_double()
+    check(lib().lbm_run_to_steady(h, float(tol), int(check_every), int(max_steps),
+                                  int(plateau_checks), ctypes.byref(steps), ctypes.byref(how),
+                                  ctypes.byref(res)))
+    return steps.value, how.value, res.value
+
+
 def lbm_get_populations(h, F=None, G=None):
     return check(lib().lbm_get_populations(h, F, G))
 
@@ -287,12 +317,13 @@ def lbm_batch_set_active(b, active):
     return check(lib().lbm_batch_set_active(b, a))
 
 
-def lbm_batch_run_to_steady(b, n, tol, check_every, max_steps):
+def lbm_batch_run_to_steady(b, n, tol, check_every, max_steps, plateau_checks=0):
+    """Returns (steps, how, last residual) per member; how is an LBM_STEADY_* value."""
     steps = (ctypes.c_int64 * n)()
     st = (ctypes.c_int32 * n)()
     res = (ctypes.c_double * n)()
     check(lib().lbm_batch_run_to_steady(b, float(tol), int(check_every), int(max_steps),
-                                        steps, st, res))
+                                        int(plateau_checks), steps, st, res))
     return list(steps), list(st), list(res)
 
 

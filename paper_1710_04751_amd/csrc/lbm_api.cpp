@@ -138,7 +138,9 @@ Layout layout_of(const lbm_params* p) {
     l.off_snap = 2 * l.state_bytes;
     const size_t snap_bytes = align_up((size_t)l.ncell * (p->precision == LBM_FP64 ? 8 : 4), kAlign);
     l.off_nu = l.off_snap + snap_bytes;
-    const size_t nu_bytes = align_up((size_t)2 * p->ny * p->nz * sizeof(double), kAlign);
+    // Nusselt profiles (2 ny nz) or centreline profiles (nx + nz) share it
+    const size_t nu_vals = std::max((size_t)2 * p->ny * p->nz, (size_t)p->nx + p->nz);
+    const size_t nu_bytes = align_up(nu_vals * sizeof(double), kAlign);
     l.off_red = l.off_nu + nu_bytes;
     l.total = l.off_red + kAlign;
     return l;
@@ -393,6 +395,92 @@ lbm_status lbm_residual(lbm_handle* h, double* max_dT) {
     return LBM_OK;
 }
 
+namespace {
+// Maximum of v[0..n) at positions (i + 1/2)/n, refined by the parabola
+// through the largest sample and its neighbours.
+void parabola_peak(const double* v, int n, double* vmax, double* pos) {
+    int k = 0;
+    for (int i = 1; i < n; ++i)
+        if (v[i] > v[k]) k = i;
+    double off = 0, val = v[k];
+    if (k > 0 && k < n - 1) {
+        const double a = v[k - 1], b = v[k], c = v[k + 1];
+        const double curv = a - 2 * b + c;
+        if (curv < 0) {
+            off = 0.5 * (a - c) / curv;
+            val = b - 0.25 * (a - c) * off;
+        }
+    }
+    *vmax = val;
+    *pos = (k + 0.5 + off) / n;
+}
+}  // namespace
+
+lbm_status lbm_centerlines(lbm_handle* h, double* u_line, double* w_line, lbm_peaks* peaks) {
+    if (!h) return fail(LBM_ERR_ARG, "null handle");
+    double* uu = h->nu_hot();  // scratch for the profiles
+    double* ww = uu + h->p.nz;
+    hipError_t e = launch_centerlines((Prec)h->p.precision, h->p.thermal_q, h->geom, h->lay.ps,
+                                      h->buf(h->cur), uu, ww, h->c, h->p.u0, h->stream);
+    if (e != hipSuccess) return hip_fail(e, "centerlines");
+    if (u_line) {
+        e = hipMemcpyAsync(u_line, uu, sizeof(double) * h->p.nz, hipMemcpyDeviceToDevice,
+                           h->stream);
+        if (e != hipSuccess) return hip_fail(e, "centerlines copy");
+    }
+    if (w_line) {
+        e = hipMemcpyAsync(w_line, ww, sizeof(double) * h->p.nx, hipMemcpyDeviceToDevice,
+                           h->stream);
+        if (e != hipSuccess) return hip_fail(e, "centerlines copy");
+    }
+    if (!peaks) return LBM_OK;
+    std::vector<double> hv((size_t)h->p.nz + h->p.nx);
+    e = hipMemcpyAsync(hv.data(), uu, sizeof(double) * hv.size(), hipMemcpyDeviceToHost,
+                       h->stream);
+    if (e != hipSuccess) return hip_fail(e, "centerlines copy");
+    e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(e, "centerlines sync");
+    for (double v : hv)
+        if (!std::isfinite(v)) return fail(LBM_ERR_UNSTABLE, "non-finite velocity");
+    parabola_peak(hv.data(), h->p.nz, &peaks->u_max, &peaks->u_pos);
+    // distance from the cold wall: reverse the x profile
+    std::vector<double> wr(hv.rbegin(), hv.rbegin() + h->p.nx);
+    parabola_peak(wr.data(), h->p.nx, &peaks->w_max, &peaks->w_pos);
+    return LBM_OK;
+}
+
+lbm_status lbm_run_to_steady(lbm_handle* h, double tol, int64_t check_every, int64_t max_steps,
+                             int32_t plateau_checks, int64_t* steps, int32_t* how,
+                             double* last_residual) {
+    if (!h) return fail(LBM_ERR_ARG, "null handle");
+    if (h->owner) return fail(LBM_ERR_STATE, "batch members are run by lbm_batch_run_to_steady");
+    if (check_every <= 0 || (check_every & 1) || max_steps < 0 || plateau_checks < 0)
+        return fail(LBM_ERR_ARG, "check_every must be positive and even");
+    double res = INFINITY;
+    lbm_status s = lbm_residual(h, &res);  // snapshot
+    SteadyTracker tr;
+    int result = LBM_STEADY_MAX_STEPS;
+    int64_t done = 0;
+    while (s == LBM_OK && done < max_steps) {
+        s = lbm_step(h, check_every);
+        if (s != LBM_OK) return s;
+        done += check_every;
+        s = lbm_residual(h, &res);
+        if (s != LBM_OK) break;
+        const int r = tr.update(res, h->steps, tol, plateau_checks);
+        if (r >= 0) {
+            result = r;
+            break;
+        }
+    }
+    if (s == LBM_ERR_UNSTABLE) result = LBM_STEADY_UNSTABLE;
+    if (steps)
+        *steps = (result == LBM_STEADY_TOL || result == LBM_STEADY_PLATEAU) ? tr.best_step : -1;
+    if (how) *how = result;
+    if (last_residual) *last_residual = res;
+    return s;
+}
+
 lbm_status lbm_get_populations(lbm_handle* h, double* F, double* G) {
     if (!h) return fail(LBM_ERR_ARG, "null handle");
     hipError_t e = launch_get_pops((Prec)h->p.precision, h->p.thermal_q, h->geom, h->lay.ps,
@@ -466,24 +554,26 @@ lbm_status lbm_autotune(lbm_handle* h, int32_t steps_per_trial, int32_t* out_bx,
     if (e != hipSuccess) return hip_fail(e, "autotune events");
     float best = 1e30f;
     int bbx = h->geom.bx, bby = h->geom.by;
+    lbm_status s = LBM_OK;
     for (auto& cnd : cand) {
         const int bx = cnd[0], by = cnd[1];
         if (bx > 2 * std::max(64, h->p.nx)) continue;  // mostly idle lanes
         set_geom(h, bx, by);
-        lbm_status s = lbm_step(h, 1);  // warm the instruction cache
+        s = lbm_step(h, 1);  // warm the instruction cache
         if (s != LBM_OK) break;
-        hipEventRecord(e0, h->stream);
-        s = lbm_step(h, steps_per_trial);
-        hipEventRecord(e1, h->stream);
-        e = hipEventSynchronize(e1);
-        if (s != LBM_OK || e != hipSuccess) break;
+        e = hipEventRecord(e0, h->stream);
+        if (e == hipSuccess) s = lbm_step(h, steps_per_trial);
+        if (e == hipSuccess && s == LBM_OK) e = hipEventRecord(e1, h->stream);
+        if (e == hipSuccess && s == LBM_OK) e = hipEventSynchronize(e1);
         float ms = 0;
-        hipEventElapsedTime(&ms, e0, e1);
+        if (e == hipSuccess && s == LBM_OK) e = hipEventElapsedTime(&ms, e0, e1);
+        if (s != LBM_OK || e != hipSuccess) break;
         if (ms < best) best = ms, bbx = bx, bby = by;
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     set_geom(h, bbx, bby);
+    if (s != LBM_OK) return s;
     if (e != hipSuccess) return hip_fail(e, "autotune");
     if (out_bx) *out_bx = bbx;
     if (out_by) *out_by = bby;

@@ -566,12 +566,12 @@ lbm_status lbm_batch_set_active(lbm_batch* b, const int32_t* active) {
 }
 
 lbm_status lbm_batch_run_to_steady(lbm_batch* b, double tol, int64_t check_every,
-                                   int64_t max_steps, int64_t* steps, int32_t* status,
-                                   double* last_residual) {
-    if (!b || check_every <= 0 || (check_every & 1) || max_steps < 0)
+                                   int64_t max_steps, int32_t plateau_checks, int64_t* steps,
+                                   int32_t* how, double* last_residual) {
+    if (!b || check_every <= 0 || (check_every & 1) || max_steps < 0 || plateau_checks < 0)
         return fail(LBM_ERR_ARG, "check_every must be positive and even");
-    std::vector<int64_t> reached(b->n, -1);
-    std::vector<int32_t> st(b->n, LBM_ERR_STATE);
+    std::vector<SteadyTracker> tr(b->n);
+    std::vector<int32_t> end(b->n, LBM_STEADY_MAX_STEPS);
     std::vector<double> res(b->n);
     std::vector<int32_t> rs(b->n);
     // snapshot at the start
@@ -591,13 +591,11 @@ lbm_status lbm_batch_run_to_steady(lbm_batch* b, double tol, int64_t check_every
         bool changed = false;
         for (int i = 0; i < b->n; ++i) {
             if (!b->active[i]) continue;
-            if (rs[i] != LBM_OK) {
-                st[i] = LBM_ERR_UNSTABLE;
-                act[i] = 0;
-                changed = true;
-            } else if (res[i] < tol) {
-                st[i] = LBM_OK;
-                reached[i] = b->mem[i]->steps;
+            const int r = rs[i] != LBM_OK
+                              ? (int)LBM_STEADY_UNSTABLE
+                              : tr[i].update(res[i], b->mem[i]->steps, tol, plateau_checks);
+            if (r >= 0) {
+                end[i] = r;
                 act[i] = 0;
                 changed = true;
             }
@@ -608,8 +606,9 @@ lbm_status lbm_batch_run_to_steady(lbm_batch* b, double tol, int64_t check_every
         }
     }
     for (int i = 0; i < b->n; ++i) {
-        if (steps) steps[i] = reached[i];
-        if (status) status[i] = st[i];
+        const bool ok = end[i] == LBM_STEADY_TOL || end[i] == LBM_STEADY_PLATEAU;
+        if (steps) steps[i] = ok ? tr[i].best_step : -1;
+        if (how) how[i] = end[i];
         if (last_residual) last_residual[i] = b->last_res[i];
     }
     return LBM_OK;
@@ -659,13 +658,13 @@ lbm_status lbm_batch_autotune(lbm_batch* b, int32_t steps_per_trial, int32_t* ou
             if (s != LBM_OK) break;
             s = lbm_batch_step(b, 2);
             if (s != LBM_OK) break;
-            (void)hipEventRecord(e0, b->stream);
-            s = lbm_batch_step(b, steps_per_trial);
-            (void)hipEventRecord(e1, b->stream);
-            e = hipEventSynchronize(e1);
-            if (s != LBM_OK || e != hipSuccess) break;
+            e = hipEventRecord(e0, b->stream);
+            if (e == hipSuccess) s = lbm_batch_step(b, steps_per_trial);
+            if (e == hipSuccess && s == LBM_OK) e = hipEventRecord(e1, b->stream);
+            if (e == hipSuccess && s == LBM_OK) e = hipEventSynchronize(e1);
             float ms = 0;
-            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (e == hipSuccess && s == LBM_OK) e = hipEventElapsedTime(&ms, e0, e1);
+            if (s != LBM_OK || e != hipSuccess) break;
             if (ms < best) best = ms, bt = t, bb = bp;
         }
         if (s != LBM_OK || e != hipSuccess) break;

@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <string>
 
 #include "../../include/lbm.h"
@@ -53,6 +54,29 @@ struct lbm_handle {
 };
 
 namespace lbm {
+// Stopping rule of a run to steady state, fed one residual per check.
+struct SteadyTracker {
+    double best = INFINITY;
+    int64_t best_step = -1;
+    int32_t since = 0;  // checks since the last new minimum
+    // Returns an lbm_steady value once the run should stop, else -1.
+    int update(double res, int64_t step, double tol, int32_t plateau_checks) {
+        if (!std::isfinite(res)) return res != res ? LBM_STEADY_UNSTABLE : -1;
+        if (res < tol) {
+            best_step = step;
+            return LBM_STEADY_TOL;
+        }
+        if (res < best) {
+            best = res;
+            best_step = step;
+            since = 0;
+        } else if (plateau_checks > 0 && ++since >= plateau_checks) {
+            return LBM_STEADY_PLATEAU;
+        }
+        return -1;
+    }
+};
+
 void set_geom(lbm_handle* h, int bx, int by);
 // A member of a batch may be re-initialised only at an even batch step.
 bool batch_allows_reinit(const lbm_batch* b);

@@ -46,6 +46,9 @@ hipError_t launch_macros(Prec p, int qt, const Geom& g, int64_t ps, StateBuf st,
 hipError_t launch_nusselt(Prec p, int qt, const Geom& g, int64_t ps, StateBuf st,
                           double* local_hot, double* local_cold, double* result,
                           const Coefs& c, hipStream_t s);
+hipError_t launch_centerlines(Prec p, int qt, const Geom& g, int64_t ps, StateBuf st,
+                              double* u_line, double* w_line, const Coefs& c, double u0,
+                              hipStream_t s);
 hipError_t launch_residual(Prec p, int qt, const Geom& g, int64_t ps, StateBuf st, void* snapshot,
                            bool compare, unsigned long long* max_bits, unsigned int* bad_flag,
                            hipStream_t s);

@@ -91,6 +91,21 @@ class Cavity:
     def residual(self):
         return capi.lbm_residual(self.h)
 
+    def centerlines(self, profiles=False):
+        """Peak velocities of Table 1 (lbm_peaks, units of u0); with
+        profiles=True also the two centreline profiles (float64 tensors)."""
+        if not profiles:
+            return capi.lbm_centerlines(self.h)
+        ul = torch.empty(self.p.nz, dtype=torch.float64, device=self.device)
+        wl = torch.empty(self.p.nx, dtype=torch.float64, device=self.device)
+        self._inputs_ready()
+        pk = capi.lbm_centerlines(self.h, ul.data_ptr(), wl.data_ptr())
+        return pk, ul, wl
+
+    def run_to_steady(self, tol=1e-8, check_every=1000, max_steps=10 ** 7, plateau_checks=0):
+        """(steps, how, last residual) of lbm_run_to_steady."""
+        return capi.lbm_run_to_steady(self.h, tol, check_every, max_steps, plateau_checks)
+
     def populations(self):
         F = self._empty(15)
         G = self._empty(self.p.thermal_q)
@@ -203,8 +218,9 @@ class Batch:
     def set_active(self, active):
         capi.lbm_batch_set_active(self.b, active)
 
-    def run_to_steady(self, tol, check_every=1000, max_steps=10 ** 6):
-        return capi.lbm_batch_run_to_steady(self.b, self.n, tol, check_every, max_steps)
+    def run_to_steady(self, tol, check_every=1000, max_steps=10 ** 6, plateau_checks=0):
+        return capi.lbm_batch_run_to_steady(self.b, self.n, tol, check_every, max_steps,
+                                            plateau_checks)
 
     def set_launch(self, threads, blocks_per_cu, graph_steps):
         capi.lbm_batch_set_launch(self.b, threads, blocks_per_cu, graph_steps)

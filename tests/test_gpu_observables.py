@@ -103,3 +103,55 @@ def test_macros_single_and_double(solver, oracle, prec):
             lim = tol if fp64 else max(tol, 1e-6)
             assert err <= lim, (k, fp64, err)
     cav.close()
+
+
+@pytest.mark.parametrize("shape", [(14, 12, 10), (13, 11, 9)])
+def test_centerlines_match_oracle(solver, oracle, shape):
+    """Velocity profiles on the symmetry plane and their Table 1 peaks agree
+    with the oracle's definitions (FP64)."""
+    from oracle.oracle import centerline_profiles, table1_peaks
+    nx, ny, nz = shape
+    log(f"case: centerlines {shape} fp64")
+    p = oracle.cavity_params(nx, 2e3, u0=0.1, ny=ny, nz=nz, omega_bulk=1.0, fourth_maxwell=1)
+    F, G = oracle.rest_state(p)
+    _, _, mac = oracle.run(p, 400, F, G)
+    ul_ref, wl_ref = centerline_profiles(mac, 0.1)
+    pk_ref = table1_peaks(mac, 0.1)
+    cav = solver.Cavity(solver.make_params(nx=nx, ny=ny, nz=nz, Ra=2e3, u0=0.1,
+                                           precision="fp64", omega_bulk=1.0, fourth_maxwell=1))
+    cav.step(400)
+    pk, ul, wl = cav.centerlines(profiles=True)
+    sc = max(np.max(np.abs(ul_ref)), np.max(np.abs(wl_ref)))
+    assert np.max(np.abs(to_np(ul) - ul_ref)) < 1e-12 * sc
+    assert np.max(np.abs(to_np(wl) - wl_ref)) < 1e-12 * sc
+    for k, v in pk_ref.items():
+        assert abs(getattr(pk, k) - v) < 1e-10 * max(1.0, abs(v)), (k, getattr(pk, k), v)
+    log("peaks", pk_ref)
+    cav.close()
+
+
+def test_run_to_steady_rules(solver):
+    """Tolerance, plateau and step-limit endings of lbm_run_to_steady."""
+    from paper_1710_04751_amd import capi
+    log("case: run_to_steady single cavity")
+    mk = lambda prec: solver.Cavity(solver.make_params(12, 1e3, u0=0.1, precision=prec))
+    cav = mk("fp64")
+    steps, how, res = cav.run_to_steady(tol=1e-10, check_every=500, max_steps=200000)
+    log("fp64 tol:", steps, how, res)
+    assert how == capi.LBM_STEADY_TOL and res < 1e-10 and steps == cav.steps_done()
+    assert steps % 500 == 0 and steps > 0
+    # FP32 cannot reach 1e-15 (T is stored with 24-bit significands): the
+    # residual stalls at the precision's floor and the plateau rule stops it
+    c32 = mk("fp32")
+    steps, how, res = c32.run_to_steady(tol=1e-15, check_every=500, max_steps=400000,
+                                        plateau_checks=8)
+    log("fp32 plateau:", steps, how, res)
+    assert how in (capi.LBM_STEADY_PLATEAU, capi.LBM_STEADY_TOL)
+    if how == capi.LBM_STEADY_PLATEAU:
+        assert 0 < steps <= c32.steps_done() - 8 * 500 and res < 1e-6
+    # a step limit below the convergence time
+    c3 = mk("fp64")
+    steps, how, res = c3.run_to_steady(tol=1e-12, check_every=100, max_steps=1000)
+    assert how == capi.LBM_STEADY_MAX_STEPS and steps == -1 and c3.steps_done() == 1000
+    for c in (cav, c32, c3):
+        c.close()

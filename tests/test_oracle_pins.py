@@ -307,3 +307,47 @@ def test_linear_stability_envelope_of_the_flow_kernel(oracle):
     assert _periodic_noise_growth(oracle, 1.75, 400) < 1.0
     assert _periodic_noise_growth(oracle, 1.88, 400) > 1e3
     assert _periodic_noise_growth(oracle, 1.96, 400, omega_bulk=1.0, fourth_maxwell=1) < 1.0
+
+
+# --------------------------------------------------------------------------
+# Table 1 observables: centreline profiles and their peaks
+# --------------------------------------------------------------------------
+
+def test_parabola_peak_is_exact_for_a_parabola(oracle):
+    """Samples of A - B (s - s0)^2 at s = (i + 1/2)/n: the three-point
+    parabola through the largest sample is the function itself."""
+    from oracle.oracle import parabola_peak
+    for n, s0, A, B in [(64, 0.1913, 0.2, 3.0), (31, 0.8426, 1.3, 0.7), (90, 0.5, -0.1, 12.0)]:
+        s = (np.arange(n) + 0.5) / n
+        v, pos = parabola_peak(A - B * (s - s0) ** 2)
+        assert abs(v - A) < 1e-14 and abs(pos - s0) < 1e-13
+    # a peak on the first sample is not extrapolated
+    v, pos = parabola_peak(np.array([3.0, 2.0, 1.0]))
+    assert (v, pos) == (3.0, 0.5 / 3)
+
+
+@pytest.mark.parametrize("shape", [(12, 10, 8), (11, 9, 7)])
+def test_centerline_profiles_pick_the_symmetry_lines(oracle, shape):
+    """Fields linear across a centreline average to their centre value, so
+    the profiles are closed forms of the remaining coordinate; positions
+    follow the paper's axes (height from the bottom, heated axis from the
+    cold wall)."""
+    from oracle.oracle import centerline_profiles, table1_peaks
+    nx, ny, nz = shape
+    x = (np.arange(nx) + 0.5) / nx
+    y = (np.arange(ny) + 0.5) / ny
+    z = (np.arange(nz) + 0.5) / nz
+    Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+    mac = np.zeros((5, nz, ny, nx))
+    u0 = 0.05
+    # -u_x = u0 (1 - (z - 0.3)^2) (1 + (x - 1/2) + 2 (y - 1/2)) on x = y = 1/2
+    mac[1] = -u0 * (1 - (Z - 0.3) ** 2) * (1 + (X - 0.5) + 2 * (Y - 0.5))
+    # u_z = u0 (0.5 - (x - 0.15)^2) (1 + 3 (z - 1/2) - (y - 1/2)) on y = z = 1/2
+    mac[3] = u0 * (0.5 - (X - 0.15) ** 2) * (1 + 3 * (Z - 0.5) - (Y - 0.5))
+    ul, wl = centerline_profiles(mac, u0)
+    assert np.max(np.abs(ul - (1 - (z - 0.3) ** 2))) < 1e-14
+    assert np.max(np.abs(wl - (0.5 - (x - 0.15) ** 2))) < 1e-14
+    pk = table1_peaks(mac, u0)
+    assert abs(pk["u_max"] - 1.0) < 1e-13 and abs(pk["u_pos"] - 0.3) < 1e-12
+    # the hot wall is at x = 0, so the peak lies 0.85 L from the cold wall
+    assert abs(pk["w_max"] - 0.5) < 1e-13 and abs(pk["w_pos"] - 0.85) < 1e-12
