@@ -70,6 +70,20 @@ def sample_cells(shape, n, seed, include_edges=True):
     return np.array(pts[:n], dtype=np.int32)
 
 
+# Rate set of the uneven batch and the warm-start runs, which reach
+# relaxation rates up to 1.98 (small boxes at Ra = 1e6): bulk rate 1, the
+# Maxwellian fourth-order flow equilibrium, and the D3Q7 scalar lattice with
+# c_sphi^2 = 1/4 (rest weight 1/4).  With c_sphi^2 = 1/3 the D3Q7 lattice
+# has no rest population and 64^3 cavities at Ra >= 1e5 diverge.
+STABLE_RATES = {"omega_bulk": 1.0, "fourth_maxwell": 1, "cs2_T": 0.25}
+
+
+# Steady-state rule: max |T_n - T_(n-1000)| < 1e-8, or, when the residual
+# has stalled for 10 checks below 1e-6 (16 units in the last place of
+# T = 0.5 in FP32), the precision's floor.
+STEADY_RULE = {"tol": 1e-8, "check_every": 1000, "plateau_checks": 10, "plateau_floor": 1e-6}
+
+
 def batched_cavities(count=64, seed=1710, sizes=(32, 48, 64, 80, 96), log_ra=(3.0, 6.0)):
     """The uneven batch: edge lengths uniform over `sizes`, Ra log-uniform."""
     rng = np.random.default_rng(seed)
