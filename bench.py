@@ -135,12 +135,12 @@ def copy_calibration(nbytes=4 << 30, reps=5, log=print):
 def batched_params(count=64, seed=1710, precision="fp32"):
     """The uneven batch: edge lengths uniform over {32, 48, 64, 80, 96}, Ra
     log-uniform in [1e3, 1e6] (seeded), Pr = 0.71, u0 = 0.05, D3Q7.  Small
-    boxes at high Ra need relaxation rates up to 1.98, beyond the linear
-    stability range of the default rate set, so the batch uses the bulk rate
-    1 and the Maxwellian fourth-order equilibrium."""
+    boxes at high Ra need relaxation rates up to 1.98, so the batch uses the
+    stable rate set (bulk rate 1, Maxwellian fourth-order equilibrium,
+    c_sphi^2 = 1/4)."""
     from paper_1710_04751_amd import solver as S
     from paper_1710_04751_amd import workloads as W
-    return [S.make_params(n, ra, precision=precision, omega_bulk=1.0, fourth_maxwell=1)
+    return [S.make_params(n, ra, precision=precision, **W.STABLE_RATES)
             for n, ra in W.batched_cavities(count, seed)]
 
 
@@ -195,6 +195,58 @@ def time_batched(steps, log=print):
             "graph_steps": info["graph_steps"]}
 
 
+def time_batched_steady(log=print):
+    """Every cavity of the batch run to steady state (the steady rule of
+    workloads.STEADY_RULE): once in the batch, retiring members as they
+    converge, and once cavity after cavity with single-cavity launches.
+    Aggregate MLUPS = sum over cavities of cells x steps taken / wall time."""
+    import torch
+    from paper_1710_04751_amd import solver as S
+    from paper_1710_04751_amd import workloads as W
+
+    params = batched_params()
+    cells = [p.nx * p.ny * p.nz for p in params]
+    rule = dict(W.STEADY_RULE)
+    batch = S.Batch(params)
+    threads, bpc = batch.autotune(steps_per_trial=6)
+    for m in batch.members:  # autotuning advanced the members: start from rest
+        m.init_rest()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    steps_b, how_b, _ = batch.run_to_steady(max_steps=1_000_000, **rule)
+    torch.cuda.synchronize()
+    wall_b = time.perf_counter() - t0
+    done_b = [m.steps_done() for m in batch.members]
+    upd_b = sum(c * s for c, s in zip(cells, done_b))
+    batch.close()
+    del batch
+    torch.cuda.empty_cache()
+    log(f"batched to steady: {wall_b:.1f} s, {upd_b / wall_b / 1e6:.0f} MLUPS")
+    stream = torch.cuda.Stream()
+    wall_s, upd_s, steps_s = 0.0, 0, []
+    for i, p in enumerate(params):
+        cav = S.Cavity(p, stream=stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, how, _ = cav.run_to_steady(max_steps=1_000_000, **rule)
+        torch.cuda.synchronize()
+        wall_s += time.perf_counter() - t0
+        upd_s += cells[i] * cav.steps_done()
+        steps_s.append(st)
+        cav.close()
+        if i % 8 == 7:
+            log(f"sequential to steady: {i + 1}/{len(params)} cavities, {wall_s:.1f} s")
+    mb, ms = upd_b / wall_b / 1e6, upd_s / wall_s / 1e6
+    log(f"to steady: batched {mb:.0f} MLUPS ({wall_b:.1f} s) vs sequential {ms:.0f} MLUPS "
+        f"({wall_s:.1f} s)")
+    return {"value": round(mb, 1), "unit": "MLUPS", "wall_s": round(wall_b, 2),
+            "sequential_MLUPS": round(ms, 1), "sequential_wall_s": round(wall_s, 2),
+            "speedup_wall": round(wall_s / wall_b, 3), "cell_updates": upd_b,
+            "rule": rule, "ended": {str(h): how_b.count(h) for h in sorted(set(how_b))},
+            "steps_to_steady": steps_b, "steps_to_steady_sequential": steps_s,
+            "threads": threads, "blocks_per_cu": bpc}
+
+
 def cpu_baseline(n_full, ra, seconds_hint=15.0, log=print):
     """The oracle on a bounded sample of the workload: a 64^3 block of cells
     with the 512^3 case's lattice parameters, a few steps, all host threads."""
@@ -234,6 +286,9 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=2000)
     ap.add_argument("--block", type=str, default=None, help="bx,by of the step kernel")
+    ap.add_argument("--batched-steady", action="store_true",
+                    help="also run every cavity of the batch to steady state, batched and "
+                         "sequentially (about 3 minutes)")
     args = ap.parse_args()
 
     def log(*a):
@@ -257,6 +312,8 @@ def main():
     f16 = time_variant(args.n, args.Ra, "fp16", f16_steps, args.warmup, block, log)
     log(json.dumps(f16))
     batched = None if args.no_batched else time_batched(args.batched_steps, log=log)
+    if batched is not None and args.batched_steady:
+        batched["to_steady"] = time_batched_steady(log=log)
     cpu = None if args.no_cpu else cpu_baseline(args.n, args.Ra, log=log)
 
     rec = {

@@ -205,18 +205,21 @@ lbm_status lbm_residual(lbm_handle* h, double* max_dT);
 lbm_status lbm_centerlines(lbm_handle* h, double* u_line, double* w_line, lbm_peaks* peaks);
 
 /* Step until steady: every check_every steps (even, > 0) take lbm_residual;
- * stop when it is below tol (LBM_STEADY_TOL), or when plateau_checks > 0
- * and it has not reached a new minimum for plateau_checks checks in a row
- * (LBM_STEADY_PLATEAU: the steady state is the precision's floor; *steps
- * is then the step at which the minimum was first seen), or after
- * max_steps (LBM_STEADY_MAX_STEPS).  The first check only takes the
+ * stop when it is below tol (LBM_STEADY_TOL), or when plateau_checks > 0,
+ * its smallest value so far is below plateau_floor and it has not reached a
+ * new minimum for plateau_checks checks in a row (LBM_STEADY_PLATEAU: the
+ * state wanders at the storage precision's floor, e.g. FP32 stalls at a few
+ * units in the last place of T; *steps is then the step at which the
+ * minimum was first seen), or after max_steps (LBM_STEADY_MAX_STEPS).  A
+ * residual that stalls above plateau_floor (a slowly oscillating approach)
+ * keeps the run going.  The first check only takes the
  * snapshot.  Outputs (host pointers, may be NULL): steps taken to the
  * stopping criterion, how it ended (lbm_steady), the last residual.
  * Returns LBM_ERR_UNSTABLE (with *how = LBM_STEADY_UNSTABLE) on NaN/Inf.
  * Synchronises. */
 lbm_status lbm_run_to_steady(lbm_handle* h, double tol, int64_t check_every, int64_t max_steps,
-                             int32_t plateau_checks, int64_t* steps, int32_t* how,
-                             double* last_residual);
+                             int32_t plateau_checks, double plateau_floor, int64_t* steps,
+                             int32_t* how, double* last_residual);
 
 /* Full populations as FP64 (device pointers): F [15][ncell], G [q][ncell]
  * (f itself, not the stored deviation).  Either may be NULL.  Asynchronous. */
@@ -307,8 +310,9 @@ lbm_status lbm_batch_set_active(lbm_batch* b, const int32_t* active);
  * criterion (-1 if it hit max_steps or became unstable), how it ended
  * (lbm_steady), last residual.  Synchronises. */
 lbm_status lbm_batch_run_to_steady(lbm_batch* b, double tol, int64_t check_every,
-                                   int64_t max_steps, int32_t plateau_checks, int64_t* steps,
-                                   int32_t* how, double* last_residual);
+                                   int64_t max_steps, int32_t plateau_checks,
+                                   double plateau_floor, int64_t* steps, int32_t* how,
+                                   double* last_residual);
 
 /* Launch shape: threads per block (a multiple of 64, >= the largest nx, at
  * most 1024), blocks per compute unit (1..32), steps per captured graph

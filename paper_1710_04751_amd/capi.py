@@ -75,7 +75,8 @@ _SIGS = {
     "lbm_residual": (ctypes.c_int, [H, ctypes.POINTER(ctypes.c_double)]),
     "lbm_centerlines": (ctypes.c_int, [H, vp, vp, ctypes.POINTER(lbm_peaks)]),
     "lbm_run_to_steady": (ctypes.c_int, [H, ctypes.c_double, ctypes.c_int64, ctypes.c_int64,
-                                         ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
+                                         ctypes.c_int32, ctypes.c_double,
+                                         ctypes.POINTER(ctypes.c_int64),
                                          ctypes.POINTER(ctypes.c_int32),
                                          ctypes.POINTER(ctypes.c_double)]),
     "lbm_get_populations": (ctypes.c_int, [H, vp, vp]),
@@ -99,7 +100,7 @@ _SIGS = {
                                            ctypes.POINTER(ctypes.c_int32)]),
     "lbm_batch_set_active": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_int32)]),
     "lbm_batch_run_to_steady": (ctypes.c_int, [vp, ctypes.c_double, ctypes.c_int64,
-                                               ctypes.c_int64, ctypes.c_int32,
+                                               ctypes.c_int64, ctypes.c_int32, ctypes.c_double,
                                                ctypes.POINTER(ctypes.c_int64),
                                                ctypes.POINTER(ctypes.c_int32),
                                                ctypes.POINTER(ctypes.c_double)]),
@@ -222,12 +223,13 @@ def lbm_centerlines(h, u_line=None, w_line=None, peaks=True):
     return pk
 
 
-def lbm_run_to_steady(h, tol, check_every, max_steps, plateau_checks=0):
+def lbm_run_to_steady(h, tol, check_every, max_steps, plateau_checks=0, plateau_floor=0.0):
     """Returns (steps, how, last residual); how is an LBM_STEADY_* value.  An
     unstable run raises LbmError(LBM_ERR_UNSTABLE)."""
     steps, how, res = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_double()
     check(lib().lbm_run_to_steady(h, float(tol), int(check_every), int(max_steps),
-                                  int(plateau_checks), ctypes.byref(steps), ctypes.byref(how),
+                                  int(plateau_checks), float(plateau_floor), ctypes.byref(steps),
+                                  ctypes.byref(how),
                                   ctypes.byref(res)))
     return steps.value, how.value, res.value
 
@@ -317,13 +319,15 @@ def lbm_batch_set_active(b, active):
     return check(lib().lbm_batch_set_active(b, a))
 
 
-def lbm_batch_run_to_steady(b, n, tol, check_every, max_steps, plateau_checks=0):
+def lbm_batch_run_to_steady(b, n, tol, check_every, max_steps, plateau_checks=0,
+                            plateau_floor=0.0):
     """Returns (steps, how, last residual) per member; how is an LBM_STEADY_* value."""
     steps = (ctypes.c_int64 * n)()
     st = (ctypes.c_int32 * n)()
     res = (ctypes.c_double * n)()
     check(lib().lbm_batch_run_to_steady(b, float(tol), int(check_every), int(max_steps),
-                                        int(plateau_checks), steps, st, res))
+                                        int(plateau_checks), float(plateau_floor), steps, st,
+                                        res))
     return list(steps), list(st), list(res)
 
 

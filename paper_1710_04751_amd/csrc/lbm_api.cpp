@@ -450,8 +450,8 @@ lbm_status lbm_centerlines(lbm_handle* h, double* u_line, double* w_line, lbm_pe
 }
 
 lbm_status lbm_run_to_steady(lbm_handle* h, double tol, int64_t check_every, int64_t max_steps,
-                             int32_t plateau_checks, int64_t* steps, int32_t* how,
-                             double* last_residual) {
+                             int32_t plateau_checks, double plateau_floor, int64_t* steps,
+                             int32_t* how, double* last_residual) {
     if (!h) return fail(LBM_ERR_ARG, "null handle");
     if (h->owner) return fail(LBM_ERR_STATE, "batch members are run by lbm_batch_run_to_steady");
     if (check_every <= 0 || (check_every & 1) || max_steps < 0 || plateau_checks < 0)
@@ -467,7 +467,7 @@ lbm_status lbm_run_to_steady(lbm_handle* h, double tol, int64_t check_every, int
         done += check_every;
         s = lbm_residual(h, &res);
         if (s != LBM_OK) break;
-        const int r = tr.update(res, h->steps, tol, plateau_checks);
+        const int r = tr.update(res, h->steps, tol, plateau_checks, plateau_floor);
         if (r >= 0) {
             result = r;
             break;

@@ -566,8 +566,9 @@ lbm_status lbm_batch_set_active(lbm_batch* b, const int32_t* active) {
 }
 
 lbm_status lbm_batch_run_to_steady(lbm_batch* b, double tol, int64_t check_every,
-                                   int64_t max_steps, int32_t plateau_checks, int64_t* steps,
-                                   int32_t* how, double* last_residual) {
+                                   int64_t max_steps, int32_t plateau_checks,
+                                   double plateau_floor, int64_t* steps, int32_t* how,
+                                   double* last_residual) {
     if (!b || check_every <= 0 || (check_every & 1) || max_steps < 0 || plateau_checks < 0)
         return fail(LBM_ERR_ARG, "check_every must be positive and even");
     std::vector<SteadyTracker> tr(b->n);
@@ -593,7 +594,8 @@ lbm_status lbm_batch_run_to_steady(lbm_batch* b, double tol, int64_t check_every
             if (!b->active[i]) continue;
             const int r = rs[i] != LBM_OK
                               ? (int)LBM_STEADY_UNSTABLE
-                              : tr[i].update(res[i], b->mem[i]->steps, tol, plateau_checks);
+                              : tr[i].update(res[i], b->mem[i]->steps, tol, plateau_checks,
+                                             plateau_floor);
             if (r >= 0) {
                 end[i] = r;
                 act[i] = 0;

@@ -102,9 +102,11 @@ class Cavity:
         pk = capi.lbm_centerlines(self.h, ul.data_ptr(), wl.data_ptr())
         return pk, ul, wl
 
-    def run_to_steady(self, tol=1e-8, check_every=1000, max_steps=10 ** 7, plateau_checks=0):
+    def run_to_steady(self, tol=1e-8, check_every=1000, max_steps=10 ** 7, plateau_checks=0,
+                      plateau_floor=0.0):
         """(steps, how, last residual) of lbm_run_to_steady."""
-        return capi.lbm_run_to_steady(self.h, tol, check_every, max_steps, plateau_checks)
+        return capi.lbm_run_to_steady(self.h, tol, check_every, max_steps, plateau_checks,
+                                      plateau_floor)
 
     def populations(self):
         F = self._empty(15)
@@ -218,9 +220,10 @@ class Batch:
     def set_active(self, active):
         capi.lbm_batch_set_active(self.b, active)
 
-    def run_to_steady(self, tol, check_every=1000, max_steps=10 ** 6, plateau_checks=0):
+    def run_to_steady(self, tol, check_every=1000, max_steps=10 ** 6, plateau_checks=0,
+                      plateau_floor=0.0):
         return capi.lbm_batch_run_to_steady(self.b, self.n, tol, check_every, max_steps,
-                                            plateau_checks)
+                                            plateau_checks, plateau_floor)
 
     def set_launch(self, threads, blocks_per_cu, graph_steps):
         capi.lbm_batch_set_launch(self.b, threads, blocks_per_cu, graph_steps)

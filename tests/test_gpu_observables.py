@@ -144,11 +144,20 @@ def test_run_to_steady_rules(solver):
     # residual stalls at the precision's floor and the plateau rule stops it
     c32 = mk("fp32")
     steps, how, res = c32.run_to_steady(tol=1e-15, check_every=500, max_steps=400000,
-                                        plateau_checks=8)
+                                        plateau_checks=8, plateau_floor=1e-6)
     log("fp32 plateau:", steps, how, res)
     assert how in (capi.LBM_STEADY_PLATEAU, capi.LBM_STEADY_TOL)
     if how == capi.LBM_STEADY_PLATEAU:
         assert 0 < steps <= c32.steps_done() - 8 * 500 and res < 1e-6
+    # with the floor below what FP32 reaches, the stall does not end the run
+    c4 = mk("fp32")
+    steps, how, res = c4.run_to_steady(tol=1e-15, check_every=500, max_steps=30000,
+                                       plateau_checks=8, plateau_floor=1e-12)
+    log("fp32 floor 1e-12:", steps, how, res)
+    assert how in (capi.LBM_STEADY_MAX_STEPS, capi.LBM_STEADY_TOL)
+    if how == capi.LBM_STEADY_MAX_STEPS:
+        assert steps == -1 and c4.steps_done() == 30000
+    c4.close()
     # a step limit below the convergence time
     c3 = mk("fp64")
     steps, how, res = c3.run_to_steady(tol=1e-12, check_every=100, max_steps=1000)

@@ -41,12 +41,12 @@ def table1():
 def steady(solver):
     """The four steady solutions: (qt, precision) -> observables."""
     from paper_1710_04751_amd import capi
+    from paper_1710_04751_amd import workloads as W
     out = {}
     for qt in (7, 15):
         for prec in ("fp64", "fp32"):
             cav = solver.Cavity(solver.make_params(64, 1e4, precision=prec, thermal_q=qt))
-            steps, how, res = cav.run_to_steady(tol=1e-8, check_every=1000, max_steps=2_000_000,
-                                                plateau_checks=10)
+            steps, how, res = cav.run_to_steady(max_steps=2_000_000, **W.STEADY_RULE)
             nu = cav.nusselt()
             pk = cav.centerlines()
             r = {"steps": steps, "how": how, "residual": res,
