@@ -46,6 +46,12 @@ class lbm_peaks(ctypes.Structure):
 LBM_STEADY_TOL, LBM_STEADY_PLATEAU, LBM_STEADY_MAX_STEPS, LBM_STEADY_UNSTABLE = 0, 1, 2, 3
 
 
+class lbm_nn_config(ctypes.Structure):
+    _fields_ = [("grid", ctypes.c_int32), ("batch", ctypes.c_int32), ("lr", ctypes.c_float),
+                ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
+                ("target_scale", ctypes.c_float * 4)]
+
+
 class LbmError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"lbm status {status}: {msg}")
@@ -112,6 +118,25 @@ _SIGS = {
                                              ctypes.POINTER(ctypes.c_int32),
                                              ctypes.POINTER(ctypes.c_int32),
                                              ctypes.POINTER(ctypes.c_int64)]),
+    # include/lbm_nn.h
+    "lbm_nn_param_count": (ctypes.c_int64, []),
+    "lbm_nn_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(lbm_nn_config)]),
+    "lbm_nn_create": (ctypes.c_int, [ctypes.POINTER(lbm_nn_config), vp, ctypes.c_size_t, vp,
+                                     ctypes.POINTER(vp)]),
+    "lbm_nn_destroy": (ctypes.c_int, [vp]),
+    "lbm_nn_set_params": (ctypes.c_int, [vp, vp]),
+    "lbm_nn_get_params": (ctypes.c_int, [vp, vp]),
+    "lbm_nn_forward": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_float), vp,
+                                      ctypes.POINTER(ctypes.c_float)]),
+    "lbm_nn_gradient": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_float), vp,
+                                       ctypes.POINTER(ctypes.c_int32), ctypes.c_int64, vp,
+                                       ctypes.POINTER(ctypes.c_double)]),
+    "lbm_nn_train_step": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_float), vp,
+                                         ctypes.POINTER(ctypes.c_int32), ctypes.c_int64,
+                                         ctypes.POINTER(ctypes.c_double)]),
+    "lbm_nn_activation": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.c_int32, vp]),
+    "lbm_nn_flops": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(ctypes.c_double)]),
 }
 
 
@@ -349,3 +374,84 @@ def lbm_batch_launch_info(b):
                                       ctypes.byref(gs), ctypes.byref(st)))
     return {"threads": t.value, "grid_blocks": g.value, "active_tiles": at.value,
             "graph_steps": gs.value, "steps": st.value}
+
+
+# ---------------------------------------------------------------------------
+# include/lbm_nn.h
+# ---------------------------------------------------------------------------
+
+def lbm_nn_param_count():
+    return int(lib().lbm_nn_param_count())
+
+
+def nn_config(grid, batch, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, target_scale=(1, 1, 1, 1)):
+    c = lbm_nn_config()
+    c.grid, c.batch, c.lr, c.beta1, c.beta2, c.eps = grid, batch, lr, beta1, beta2, eps
+    for i in range(4):
+        c.target_scale[i] = float(target_scale[i])
+    return c
+
+
+def lbm_nn_workspace_bytes(cfg):
+    n = lib().lbm_nn_workspace_bytes(ctypes.byref(cfg))
+    if n == 0:
+        raise LbmError(LBM_ERR_ARG, lbm_last_error())
+    return n
+
+
+def lbm_nn_create(cfg, workspace_ptr, workspace_bytes, stream_ptr=None):
+    h = vp()
+    check(lib().lbm_nn_create(ctypes.byref(cfg), workspace_ptr, workspace_bytes, stream_ptr,
+                              ctypes.byref(h)))
+    return h.value
+
+
+def lbm_nn_destroy(h):
+    return check(lib().lbm_nn_destroy(h))
+
+
+def lbm_nn_set_params(h, params_ptr):
+    return check(lib().lbm_nn_set_params(h, params_ptr))
+
+
+def lbm_nn_get_params(h, params_ptr):
+    return check(lib().lbm_nn_get_params(h, params_ptr))
+
+
+def _floats(vals):
+    return (ctypes.c_float * len(vals))(*[float(v) for v in vals])
+
+
+def _ints(vals):
+    return (ctypes.c_int32 * len(vals))(*[int(v) for v in vals])
+
+
+def lbm_nn_forward(h, log10_ra, out_ptr, out_scale=None):
+    sc = _floats(out_scale) if out_scale is not None else None
+    return check(lib().lbm_nn_forward(h, len(log10_ra), _floats(log10_ra), out_ptr, sc))
+
+
+def lbm_nn_gradient(h, log10_ra, targets_ptr, target_index, target_stride, grad_ptr=None):
+    loss = ctypes.c_double()
+    check(lib().lbm_nn_gradient(h, len(log10_ra), _floats(log10_ra), targets_ptr,
+                                _ints(target_index), int(target_stride), grad_ptr,
+                                ctypes.byref(loss)))
+    return loss.value
+
+
+def lbm_nn_train_step(h, log10_ra, targets_ptr, target_index, target_stride, want_loss=True):
+    loss = ctypes.c_double()
+    check(lib().lbm_nn_train_step(h, len(log10_ra), _floats(log10_ra), targets_ptr,
+                                  _ints(target_index), int(target_stride),
+                                  ctypes.byref(loss) if want_loss else None))
+    return loss.value if want_loss else None
+
+
+def lbm_nn_activation(h, layer, n, out_ptr):
+    return check(lib().lbm_nn_activation(h, int(layer), int(n), out_ptr))
+
+
+def lbm_nn_flops(h, n):
+    f, t = ctypes.c_double(), ctypes.c_double()
+    check(lib().lbm_nn_flops(h, int(n), ctypes.byref(f), ctypes.byref(t)))
+    return f.value, t.value

@@ -1,0 +1,88 @@
+// Host-side declarations shared by the warm-start network driver
+// (nn_net.cpp) and its kernels (nn_kernels.hip).  Not part of the public
+// interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbmnn {
+
+constexpr int kMaxBatch = 64;  // samples per call
+
+// One convolution over n samples on a cubic grid of edge 2^lg.  The input
+// is the channel concatenation of x1 (c1s stored channels on this grid, of
+// which c1 are real; the rest hold zeros) and, when c2 > 0, x2 (c2 channels
+// on the grid of edge 2^(lg-1), read through nearest-neighbour upsampling).
+struct ConvGeom {
+    int32_t n, lg;
+    int32_t taps;       // 27 (3x3x3) or 1 (1x1x1)
+    int32_t c1, c1s, c2;
+    int32_t cin;        // c1s + c2: stored input channels, K per tap
+    int32_t K, kpad;    // taps * cin, rounded up to 32
+    int32_t cout;       // real output channels
+    int32_t coutp;      // rows of the packed weight: cout rounded up to 16
+    int32_t ys;         // stored channels of the output and its gradient: cout rounded up to 8
+    int32_t kpad_t;     // columns of the transposed weight: taps * ys rounded up to 32
+    int32_t cinp;       // rows of the transposed weight: cin rounded up to 16
+};
+
+ConvGeom make_geom(int n, int lg, int taps, int c1, int c2, int cout);
+
+// Master weight w[co][tap][ci] (ci over the c1 + c2 real channels) ->
+// packed BF16 rows wp[coutp][kpad] (k = tap * cin + stored channel) and the
+// transposed, tap-flipped copy wt[cinp][kpad_t] (k = tap * ys + co) that
+// turns the input gradient into a forward convolution.
+hipError_t pack_weights(const ConvGeom& g, const float* w, __bf16* wp, __bf16* wt,
+                        hipStream_t s);
+
+// out = conv(x1 (masked by mask > 0 when mask is given), x2) + bias, ReLU if
+// relu; BF16 channels-last [n][v][ys] (mode 0), or FP32 channel-first
+// [n][cout][v] times scale[c] (mode 1, cout <= 4).
+hipError_t conv_forward(const ConvGeom& g, const __bf16* x1, const __bf16* x2,
+                        const __bf16* mask, const __bf16* wp, const float* bias, int relu,
+                        int mode, void* out, const float* scale4, hipStream_t s);
+
+// Input gradient: dx[n][v][cin] = sum over taps and co of dpre at the
+// neighbour times the weight, with dpre = dy * (y > 0) (relu) or dy.
+hipError_t conv_backward_data(const ConvGeom& g, const __bf16* dy, const __bf16* y, int relu,
+                              const __bf16* wt, __bf16* dx, hipStream_t s);
+
+// Weight and bias gradients, accumulated (atomic adds) into the master
+// layout: dw[co][tap][ci] += sum_v dpre[v][co] x(v + tap)[ci], db[co] +=
+// sum_v dpre[v][co].
+hipError_t conv_backward_weight(const ConvGeom& g, const __bf16* x1, const __bf16* x2,
+                                const __bf16* dy, const __bf16* y, int relu, float* dw,
+                                float* db, hipStream_t s);
+
+// Average pooling of 2x2x2 blocks: x on grid 2^lg, y on 2^(lg-1), c channels.
+hipError_t pool_forward(int n, int lg, int c, const __bf16* x, __bf16* y, hipStream_t s);
+// dx (grid 2^lg) = dy_coarse(parent) / 8 + skip[v][0..c) (skip has ctot
+// channels per cell; NULL adds nothing).
+hipError_t pool_backward_add(int n, int lg, int c, const __bf16* dy, const __bf16* skip, int ctot,
+                             __bf16* dx, hipStream_t s);
+// dlow (grid 2^(lg-1)) = sum over the 8 children of dcat[child][coff..coff+c).
+hipError_t upsample_backward(int n, int lg, int c, const __bf16* dcat, int ctot, int coff,
+                             __bf16* dlow, hipStream_t s);
+
+// Network input [n][v][8] (BF16): (log10 Ra - 4)/2, x, y, z, 0, 0, 0, 0;
+// log10_ra is a host array of n <= kMaxBatch values (passed by value).
+hipError_t make_inputs(int n, int lg, const float* log10_ra, __bf16* x, hipStream_t s);
+
+// MSE loss of out (FP32 channel-first [n][4][v]) against targets[idx[i]]
+// (idx: host array of n <= kMaxBatch, passed by value) times tscale; writes dy[n][v][8] = 2 (out - t) / count (channels 4..7
+// zero) and one partial sum per block into partial (double).
+hipError_t mse_forward_backward(int n, int lg, const float* out, const float* targets,
+                                const int32_t* idx, int64_t stride, const float* tscale4,
+                                __bf16* dy, double* partial, int* nblocks, hipStream_t s);
+hipError_t reduce_sum(const double* partial, int n, double* out, hipStream_t s);
+
+hipError_t adam_update(int64_t count, float* theta, float* m, float* v, const float* g, int t,
+                       float lr, float beta1, float beta2, float eps, hipStream_t s);
+hipError_t fill_zero_f32(float* p, int64_t count, hipStream_t s);
+// BF16 channels-last [n][v][cs] (first c channels) -> FP32 [n][v][c].
+hipError_t bf16_to_f32(const __bf16* x, int64_t cells, int cs, int c, float* y, hipStream_t s);
+// FP32 channel-first [n][c][v] -> channels-last [n][v][c].
+hipError_t cf_to_cl(const float* x, int n, int64_t v, int c, float* y, hipStream_t s);
+
+}  // namespace lbmnn

@@ -1,0 +1,712 @@
+// gfx950 kernels of the warm-start network: 3D convolutions as implicit
+// GEMMs on the BF16 matrix cores (v_mfma_f32_16x16x32_bf16, FP32
+// accumulation), pooling, upsampling, the loss and Adam.
+//
+// Matrix-core fragments (64 lanes, r = lane % 16, q = lane / 16):
+//   A (16 x 32): lane holds row r, k = 8q .. 8q+7;
+//   B (32 x 16): lane holds column r, k = 8q .. 8q+7;
+//   D (16 x 16, FP32): lane holds rows 4q .. 4q+3 of column r.
+// Forward: rows are 16 voxels, columns output channels, k runs over
+// (tap, input channel) with the channels of one tap contiguous, so a lane's
+// 8 k values are one 16-byte load of a channels-last voxel.  The input
+// gradient is the same kernel run on the output gradient with the
+// transposed, tap-flipped weight.  The weight gradient takes rows = output
+// channels, columns = (tap, input channel) and k = voxels, summed over
+// chunks of voxels with FP32 atomic adds.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include <algorithm>
+
+#include "nn_internal.hpp"
+
+namespace lbmnn {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+namespace {
+
+inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+inline int round_up(int a, int b) { return (a + b - 1) / b * b; }
+
+// Per-sample scalars passed by value (at most kMaxBatch samples).
+struct SampleFloats {
+    float v[kMaxBatch];
+};
+struct SampleInts {
+    int32_t v[kMaxBatch];
+};
+
+struct ConvArgs {
+    const __bf16* x1;
+    const __bf16* x2;
+    const __bf16* mask;
+    const __bf16* w;
+    const float* bias;
+    void* out;
+    float scale[4];
+    int32_t n, lg, taps, c1s, c2, cin, K, kpad, cout, ys, relu;
+};
+
+// One block = one wave: 16 voxels x (NSUB * 16) output channels, channel
+// group blockIdx.y.
+template <int NSUB, int MODE>
+__global__ void __launch_bounds__(64) k_conv(ConvArgs a) {
+    const int lane = threadIdx.x, r = lane & 15, q = lane >> 4;
+    const int lg = a.lg, G = 1 << lg;
+    const int64_t V = (int64_t)1 << (3 * lg);
+    const int64_t M = (int64_t)a.n * V;
+    const int64_t vb = (int64_t)blockIdx.x * 16;
+    const int cobase = blockIdx.y * NSUB * 16;
+    const int64_t v = vb + r;
+    const bool vok = v < M;
+    int s = 0, z = 0, y = 0, x = 0;
+    if (vok) {
+        s = (int)(v >> (3 * lg));
+        const int rem = (int)(v & (V - 1));
+        z = rem >> (2 * lg);
+        y = (rem >> lg) & (G - 1);
+        x = rem & (G - 1);
+    }
+    floatx4 acc[NSUB];
+#pragma unroll
+    for (int j = 0; j < NSUB; ++j) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    int tap = 0, c = q * 8;
+    while (c >= a.cin) c -= a.cin, ++tap;
+    for (int k0 = q * 8; k0 < a.kpad; k0 += 32) {
+        bf16x8 av;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) av[i] = (__bf16)0.f;
+        if (vok && k0 < a.K) {
+            int zz = z, yy = y, xx = x;
+            if (a.taps == 27) {
+                zz += tap / 9 - 1;
+                yy += (tap / 3) % 3 - 1;
+                xx += tap % 3 - 1;
+            }
+            if ((unsigned)zz < (unsigned)G && (unsigned)yy < (unsigned)G &&
+                (unsigned)xx < (unsigned)G) {
+                if (c < a.c1s) {
+                    const int64_t vi = ((int64_t)s << (3 * lg)) + ((int64_t)zz << (2 * lg)) +
+                                       ((int64_t)yy << lg) + xx;
+                    av = *(const bf16x8*)(a.x1 + vi * a.c1s + c);
+                    if (a.mask) {
+                        const bf16x8 mk = *(const bf16x8*)(a.mask + vi * a.c1s + c);
+#pragma unroll
+                        for (int i = 0; i < 8; ++i)
+                            if (!((float)mk[i] > 0.f)) av[i] = (__bf16)0.f;
+                    }
+                } else {
+                    const int h = lg - 1;
+                    const int64_t vi = ((int64_t)s << (3 * h)) + ((int64_t)(zz >> 1) << (2 * h)) +
+                                       ((int64_t)(yy >> 1) << h) + (xx >> 1);
+                    av = *(const bf16x8*)(a.x2 + vi * a.c2 + (c - a.c1s));
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < NSUB; ++j) {
+            const bf16x8 bv = *(const bf16x8*)(a.w + (int64_t)(cobase + j * 16 + r) * a.kpad + k0);
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[j], 0, 0, 0);
+        }
+        c += 32;
+        while (c >= a.cin) c -= a.cin, ++tap;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int64_t vo = vb + q * 4 + i;
+        if (vo >= M) continue;
+#pragma unroll
+        for (int j = 0; j < NSUB; ++j) {
+            const int co = cobase + j * 16 + r;
+            if (MODE == 0) {
+                if (co < a.ys) {
+                    float val = 0.f;
+                    if (co < a.cout) {
+                        val = acc[j][i] + (a.bias ? a.bias[co] : 0.f);
+                        if (a.relu) val = fmaxf(val, 0.f);
+                    }
+                    ((__bf16*)a.out)[vo * a.ys + co] = (__bf16)val;
+                }
+            } else if (co < a.cout) {
+                const float val = acc[j][i] + (a.bias ? a.bias[co] : 0.f);
+                const int64_t sidx = vo >> (3 * lg), vin = vo & (V - 1);
+                ((float*)a.out)[(sidx * a.cout + co) * V + vin] = val * a.scale[co];
+            }
+        }
+    }
+}
+
+struct WgradArgs {
+    const __bf16* x1;
+    const __bf16* x2;
+    const __bf16* dy;
+    const __bf16* y;
+    float* dw;
+    int32_t n, lg, taps, c1, c1s, c2, cin, K, cout, ys, relu, cin_real;
+    int64_t vchunk;
+};
+
+// One block = one wave: output channels blockIdx.y * 16 + (0..15) x
+// (tap, channel) columns blockIdx.x * 64 + (0..63), voxels of chunk
+// blockIdx.z.
+__global__ void __launch_bounds__(64) k_wgrad(WgradArgs a) {
+    const int lane = threadIdx.x, r = lane & 15, q = lane >> 4;
+    const int lg = a.lg, G = 1 << lg;
+    const int64_t V = (int64_t)1 << (3 * lg);
+    const int64_t M = (int64_t)a.n * V;
+    const int co = blockIdx.y * 16 + r;
+    bool kok[4];
+    int kc[4], kdz[4], kdy[4], kdx[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int kcol = blockIdx.x * 64 + j * 16 + r;
+        kok[j] = kcol < a.K;
+        const int t = kok[j] ? kcol / a.cin : 0;
+        kc[j] = kok[j] ? kcol - t * a.cin : 0;
+        kdz[j] = a.taps == 27 ? t / 9 - 1 : 0;
+        kdy[j] = a.taps == 27 ? (t / 3) % 3 - 1 : 0;
+        kdx[j] = a.taps == 27 ? t % 3 - 1 : 0;
+    }
+    floatx4 acc[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    const int64_t v0 = (int64_t)blockIdx.z * a.vchunk;
+    const int64_t v1 = std::min(M, v0 + a.vchunk);
+    for (int64_t vb = v0; vb < v1; vb += 32) {
+        bf16x8 av;
+        int vs[8], vz[8], vy[8], vx[8];
+        bool vin[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int64_t vv = vb + q * 8 + i;
+            vin[i] = vv < v1;
+            float d = 0.f;
+            if (vin[i] && co < a.cout) {
+                d = (float)a.dy[vv * a.ys + co];
+                if (a.relu && !((float)a.y[vv * a.ys + co] > 0.f)) d = 0.f;
+            }
+            av[i] = (__bf16)d;
+            const int64_t vc = vin[i] ? vv : 0;
+            vs[i] = (int)(vc >> (3 * lg));
+            const int rem = (int)(vc & (V - 1));
+            vz[i] = rem >> (2 * lg);
+            vy[i] = (rem >> lg) & (G - 1);
+            vx[i] = rem & (G - 1);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            bf16x8 bv;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                __bf16 val = (__bf16)0.f;
+                const int zz = vz[i] + kdz[j], yy = vy[i] + kdy[j], xx = vx[i] + kdx[j];
+                if (vin[i] && kok[j] && (unsigned)zz < (unsigned)G && (unsigned)yy < (unsigned)G &&
+                    (unsigned)xx < (unsigned)G) {
+                    if (kc[j] < a.c1s) {
+                        const int64_t vi = ((int64_t)vs[i] << (3 * lg)) + ((int64_t)zz << (2 * lg)) +
+                                           ((int64_t)yy << lg) + xx;
+                        val = a.x1[vi * a.c1s + kc[j]];
+                    } else {
+                        const int h = lg - 1;
+                        const int64_t vi = ((int64_t)vs[i] << (3 * h)) +
+                                           ((int64_t)(zz >> 1) << (2 * h)) +
+                                           ((int64_t)(yy >> 1) << h) + (xx >> 1);
+                        val = a.x2[vi * a.c2 + (kc[j] - a.c1s)];
+                    }
+                }
+                bv[i] = val;
+            }
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[j], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int kcol = blockIdx.x * 64 + j * 16 + r;
+        if (kcol >= a.K) continue;
+        const int t = kcol / a.cin;
+        const int cc = kcol - t * a.cin;
+        if (cc < a.c1s && cc >= a.c1) continue;  // zero padding channels of x1
+        const int ci = cc < a.c1s ? cc : a.c1 + (cc - a.c1s);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int coo = blockIdx.y * 16 + q * 4 + i;
+            if (coo < a.cout)
+                atomicAdd(&a.dw[((int64_t)coo * a.taps + t) * a.cin_real + ci], acc[j][i]);
+        }
+    }
+}
+
+// Bias gradient: 64 channels x 4 voxel lanes per block, over a voxel chunk.
+__global__ void __launch_bounds__(256) k_bias_grad(const __bf16* __restrict__ dy,
+                                                   const __bf16* __restrict__ y, int relu,
+                                                   int64_t M, int ys, int cout, int64_t vchunk,
+                                                   float* __restrict__ db) {
+    __shared__ float red[256];
+    const int co = blockIdx.y * 64 + (threadIdx.x & 63);
+    const int sub = threadIdx.x >> 6;
+    const int64_t v0 = (int64_t)blockIdx.x * vchunk;
+    const int64_t v1 = std::min(M, v0 + vchunk);
+    float acc = 0.f;
+    if (co < cout)
+        for (int64_t v = v0 + sub; v < v1; v += 4) {
+            float d = (float)dy[v * ys + co];
+            if (relu && !((float)y[v * ys + co] > 0.f)) d = 0.f;
+            acc += d;
+        }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    if (sub == 0 && co < cout)
+        atomicAdd(&db[co], red[threadIdx.x] + red[threadIdx.x + 64] + red[threadIdx.x + 128] +
+                               red[threadIdx.x + 192]);
+}
+
+__global__ void k_pack_w(int coutp, int kpad, int cout, int K, int cin, int c1, int c1s, int taps,
+                         int cin_real, const float* __restrict__ w, __bf16* __restrict__ wp) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)coutp * kpad) return;
+    const int co = (int)(idx / kpad), k = (int)(idx - (int64_t)co * kpad);
+    float val = 0.f;
+    if (co < cout && k < K) {
+        const int t = k / cin, cc = k - t * cin;
+        if (cc < c1s) {
+            if (cc < c1) val = w[((int64_t)co * taps + t) * cin_real + cc];
+        } else {
+            val = w[((int64_t)co * taps + t) * cin_real + c1 + (cc - c1s)];
+        }
+    }
+    wp[idx] = (__bf16)val;
+}
+
+__global__ void k_pack_wt(int cinp, int kpad_t, int cin, int ys, int cout, int c1, int c1s,
+                          int taps, int cin_real, const float* __restrict__ w,
+                          __bf16* __restrict__ wt) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)cinp * kpad_t) return;
+    const int ci = (int)(idx / kpad_t), k = (int)(idx - (int64_t)ci * kpad_t);
+    float val = 0.f;
+    if (ci < cin && k < taps * ys) {
+        const int t = k / ys, co = k - t * ys;
+        const bool real = ci >= c1s || ci < c1;
+        if (co < cout && real) {
+            const int cir = ci < c1s ? ci : c1 + (ci - c1s);
+            val = w[((int64_t)co * taps + (taps - 1 - t)) * cin_real + cir];
+        }
+    }
+    wt[idx] = (__bf16)val;
+}
+
+__device__ __forceinline__ int64_t fine_index(int s, int z, int y, int x, int lg) {
+    return ((int64_t)s << (3 * lg)) + ((int64_t)z << (2 * lg)) + ((int64_t)y << lg) + x;
+}
+
+// thread per (coarse cell, group of 8 channels)
+__global__ void k_pool(int n, int lg, int c, const __bf16* __restrict__ x, __bf16* __restrict__ y) {
+    const int h = lg - 1, cg = c / 8;
+    const int64_t Vc = (int64_t)1 << (3 * h);
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)n * Vc * cg) return;
+    const int g = (int)(idx % cg);
+    const int64_t vc = idx / cg;
+    const int s = (int)(vc >> (3 * h));
+    const int rem = (int)(vc & (Vc - 1));
+    const int Z = rem >> (2 * h), Y = (rem >> h) & ((1 << h) - 1), X = rem & ((1 << h) - 1);
+    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int dz = 0; dz < 2; ++dz)
+        for (int dy = 0; dy < 2; ++dy)
+            for (int dx = 0; dx < 2; ++dx) {
+                const int64_t vf = fine_index(s, 2 * Z + dz, 2 * Y + dy, 2 * X + dx, lg);
+                const bf16x8 t = *(const bf16x8*)(x + vf * c + g * 8);
+#pragma unroll
+                for (int i = 0; i < 8; ++i) acc[i] += (float)t[i];
+            }
+    bf16x8 o;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) o[i] = (__bf16)(acc[i] * 0.125f);
+    *(bf16x8*)(y + vc * c + g * 8) = o;
+}
+
+// thread per (fine cell, group of 8 channels)
+__global__ void k_pool_bwd_add(int n, int lg, int c, const __bf16* __restrict__ dy,
+                               const __bf16* __restrict__ skip, int ctot, __bf16* __restrict__ dx) {
+    const int h = lg - 1, cg = c / 8, G = 1 << lg;
+    const int64_t V = (int64_t)1 << (3 * lg);
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)n * V * cg) return;
+    const int g = (int)(idx % cg);
+    const int64_t v = idx / cg;
+    const int s = (int)(v >> (3 * lg));
+    const int rem = (int)(v & (V - 1));
+    const int z = rem >> (2 * lg), y = (rem >> lg) & (G - 1), x = rem & (G - 1);
+    const int64_t vc = ((int64_t)s << (3 * h)) + ((int64_t)(z >> 1) << (2 * h)) +
+                       ((int64_t)(y >> 1) << h) + (x >> 1);
+    const bf16x8 p = *(const bf16x8*)(dy + vc * c + g * 8);
+    bf16x8 o;
+    if (skip) {
+        const bf16x8 k = *(const bf16x8*)(skip + v * ctot + g * 8);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) o[i] = (__bf16)((float)p[i] * 0.125f + (float)k[i]);
+    } else {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) o[i] = (__bf16)((float)p[i] * 0.125f);
+    }
+    *(bf16x8*)(dx + v * c + g * 8) = o;
+}
+
+// thread per (coarse cell, group of 8 channels)
+__global__ void k_up_bwd(int n, int lg, int c, const __bf16* __restrict__ dcat, int ctot, int coff,
+                         __bf16* __restrict__ dlow) {
+    const int h = lg - 1, cg = c / 8;
+    const int64_t Vc = (int64_t)1 << (3 * h);
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)n * Vc * cg) return;
+    const int g = (int)(idx % cg);
+    const int64_t vc = idx / cg;
+    const int s = (int)(vc >> (3 * h));
+    const int rem = (int)(vc & (Vc - 1));
+    const int Z = rem >> (2 * h), Y = (rem >> h) & ((1 << h) - 1), X = rem & ((1 << h) - 1);
+    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int dz = 0; dz < 2; ++dz)
+        for (int dy = 0; dy < 2; ++dy)
+            for (int dx = 0; dx < 2; ++dx) {
+                const int64_t vf = fine_index(s, 2 * Z + dz, 2 * Y + dy, 2 * X + dx, lg);
+                const bf16x8 t = *(const bf16x8*)(dcat + vf * ctot + coff + g * 8);
+#pragma unroll
+                for (int i = 0; i < 8; ++i) acc[i] += (float)t[i];
+            }
+    bf16x8 o;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) o[i] = (__bf16)acc[i];
+    *(bf16x8*)(dlow + vc * c + g * 8) = o;
+}
+
+__global__ void k_inputs(int n, int lg, SampleFloats lra, __bf16* __restrict__ x) {
+    const int G = 1 << lg;
+    const int64_t V = (int64_t)1 << (3 * lg);
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= (int64_t)n * V) return;
+    const int s = (int)(v >> (3 * lg));
+    const int rem = (int)(v & (V - 1));
+    const int z = rem >> (2 * lg), y = (rem >> lg) & (G - 1), xx = rem & (G - 1);
+    const float inv = 2.0f / (float)G;
+    bf16x8 o;
+    o[0] = (__bf16)((lra.v[s] - 4.0f) * 0.5f);
+    o[1] = (__bf16)((xx + 0.5f) * inv - 1.0f);
+    o[2] = (__bf16)((y + 0.5f) * inv - 1.0f);
+    o[3] = (__bf16)((z + 0.5f) * inv - 1.0f);
+    o[4] = o[5] = o[6] = o[7] = (__bf16)0.f;
+    *(bf16x8*)(x + v * 8) = o;
+}
+
+__global__ void __launch_bounds__(256) k_mse(int n, int lg, const float* __restrict__ out,
+                                             const float* __restrict__ tg, SampleInts idx,
+                                             int64_t stride,
+                                             float4 ts, __bf16* __restrict__ dy,
+                                             double* __restrict__ partial) {
+    __shared__ double red[256];
+    const int64_t V = (int64_t)1 << (3 * lg);
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const double inv = 2.0 / ((double)n * 4.0 * (double)V);
+    double acc = 0.0;
+    if (v < (int64_t)n * V) {
+        const int s = (int)(v >> (3 * lg));
+        const int64_t vin = v & (V - 1);
+        const float tsc[4] = {ts.x, ts.y, ts.z, ts.w};
+        bf16x8 o;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const float ov = out[((int64_t)s * 4 + c) * V + vin];
+            const float tv = tg[(int64_t)idx.v[s] * stride + c * V + vin] * tsc[c];
+            const double d = (double)ov - (double)tv;
+            acc += d * d;
+            o[c] = (__bf16)(float)(d * inv);
+        }
+        o[4] = o[5] = o[6] = o[7] = (__bf16)0.f;
+        *(bf16x8*)(dy + v * 8) = o;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(1024) k_reduce(const double* __restrict__ p, int n,
+                                                 double* __restrict__ out) {
+    __shared__ double red[1024];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += 1024) acc += p[i];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = red[0];
+}
+
+__global__ void k_adam(int64_t count, float* __restrict__ th, float* __restrict__ m,
+                       float* __restrict__ v, const float* __restrict__ g, float lr, float b1,
+                       float b2, float eps, float c1, float c2) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    th[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+__global__ void k_zero(float* __restrict__ p, int64_t count) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = 0.f;
+}
+
+__global__ void k_bf16_to_f32(const __bf16* __restrict__ x, int64_t cells, int cs, int c,
+                              float* __restrict__ y) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cells * c) return;
+    const int64_t v = i / c;
+    const int ch = (int)(i - v * c);
+    y[i] = (float)x[v * cs + ch];
+}
+
+__global__ void k_cf_to_cl(const float* __restrict__ x, int n, int64_t V, int c,
+                           float* __restrict__ y) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)n * V * c) return;
+    const int ch = (int)(i % c);
+    const int64_t v = (i / c) % V;
+    const int64_t s = i / (c * V);
+    y[i] = x[(s * c + ch) * V + v];
+}
+
+template <int MODE>
+hipError_t launch_conv(const ConvArgs& a, int coutp, hipStream_t s) {
+    const int64_t M = (int64_t)a.n << (3 * a.lg);
+    const int sub = coutp / 16;
+    const int nsub = sub % 4 == 0 ? 4 : sub % 3 == 0 ? 3 : sub % 2 == 0 ? 2 : 1;
+    const dim3 grid(ceil_div(M, 16), sub / nsub);
+    switch (nsub) {
+        case 4: hipLaunchKernelGGL((k_conv<4, MODE>), grid, dim3(64), 0, s, a); break;
+        case 3: hipLaunchKernelGGL((k_conv<3, MODE>), grid, dim3(64), 0, s, a); break;
+        case 2: hipLaunchKernelGGL((k_conv<2, MODE>), grid, dim3(64), 0, s, a); break;
+        default: hipLaunchKernelGGL((k_conv<1, MODE>), grid, dim3(64), 0, s, a); break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+ConvGeom make_geom(int n, int lg, int taps, int c1, int c2, int cout) {
+    ConvGeom g;
+    g.n = n;
+    g.lg = lg;
+    g.taps = taps;
+    g.c1 = c1;
+    g.c1s = round_up(c1, 8);
+    g.c2 = c2;
+    g.cin = g.c1s + c2;
+    g.K = taps * g.cin;
+    g.kpad = round_up(g.K, 32);
+    g.cout = cout;
+    g.coutp = round_up(cout, 16);
+    g.ys = round_up(cout, 8);
+    g.kpad_t = round_up(taps * g.ys, 32);
+    g.cinp = round_up(g.cin, 16);
+    return g;
+}
+
+hipError_t pack_weights(const ConvGeom& g, const float* w, __bf16* wp, __bf16* wt,
+                        hipStream_t s) {
+    const int cin_real = g.c1 + g.c2;
+    const int64_t n1 = (int64_t)g.coutp * g.kpad;
+    hipLaunchKernelGGL(k_pack_w, dim3(ceil_div(n1, 256)), dim3(256), 0, s, g.coutp, g.kpad, g.cout,
+                       g.K, g.cin, g.c1, g.c1s, g.taps, cin_real, w, wp);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !wt) return e;
+    const int64_t n2 = (int64_t)g.cinp * g.kpad_t;
+    hipLaunchKernelGGL(k_pack_wt, dim3(ceil_div(n2, 256)), dim3(256), 0, s, g.cinp, g.kpad_t, g.cin,
+                       g.ys, g.cout, g.c1, g.c1s, g.taps, cin_real, w, wt);
+    return hipGetLastError();
+}
+
+hipError_t conv_forward(const ConvGeom& g, const __bf16* x1, const __bf16* x2,
+                        const __bf16* mask, const __bf16* wp, const float* bias, int relu,
+                        int mode, void* out, const float* scale4, hipStream_t s) {
+    if (!x1 || !wp || !out || (g.c2 > 0 && (!x2 || g.lg < 1)) || g.c1s % 8 || g.c2 % 8 ||
+        (mode == 1 && g.cout > 4))
+        return hipErrorInvalidValue;
+    ConvArgs a;
+    a.x1 = x1;
+    a.x2 = x2;
+    a.mask = mask;
+    a.w = wp;
+    a.bias = bias;
+    a.out = out;
+    for (int i = 0; i < 4; ++i) a.scale[i] = scale4 ? scale4[i] : 1.f;
+    a.n = g.n;
+    a.lg = g.lg;
+    a.taps = g.taps;
+    a.c1s = g.c1s;
+    a.c2 = g.c2;
+    a.cin = g.cin;
+    a.K = g.K;
+    a.kpad = g.kpad;
+    a.cout = g.cout;
+    a.ys = g.ys;
+    a.relu = relu;
+    return mode == 0 ? launch_conv<0>(a, g.coutp, s) : launch_conv<1>(a, g.coutp, s);
+}
+
+hipError_t conv_backward_data(const ConvGeom& g, const __bf16* dy, const __bf16* y, int relu,
+                              const __bf16* wt, __bf16* dx, hipStream_t s) {
+    if (!dy || !wt || !dx || (relu && !y)) return hipErrorInvalidValue;
+    ConvArgs a;
+    a.x1 = dy;
+    a.x2 = nullptr;
+    a.mask = relu ? y : nullptr;
+    a.w = wt;
+    a.bias = nullptr;
+    a.out = dx;
+    for (int i = 0; i < 4; ++i) a.scale[i] = 1.f;
+    a.n = g.n;
+    a.lg = g.lg;
+    a.taps = g.taps;
+    a.c1s = g.ys;
+    a.c2 = 0;
+    a.cin = g.ys;
+    a.K = g.taps * g.ys;
+    a.kpad = g.kpad_t;
+    a.cout = g.cin;
+    a.ys = g.cin;
+    a.relu = 0;
+    return launch_conv<0>(a, g.cinp, s);
+}
+
+hipError_t conv_backward_weight(const ConvGeom& g, const __bf16* x1, const __bf16* x2,
+                                const __bf16* dy, const __bf16* y, int relu, float* dw,
+                                float* db, hipStream_t s) {
+    if (!x1 || !dy || !dw || !db || (relu && !y) || (g.c2 > 0 && (!x2 || g.lg < 1)))
+        return hipErrorInvalidValue;
+    const int64_t M = (int64_t)g.n << (3 * g.lg);
+    WgradArgs a;
+    a.x1 = x1;
+    a.x2 = x2;
+    a.dy = dy;
+    a.y = y;
+    a.dw = dw;
+    a.n = g.n;
+    a.lg = g.lg;
+    a.taps = g.taps;
+    a.c1 = g.c1;
+    a.c1s = g.c1s;
+    a.c2 = g.c2;
+    a.cin = g.cin;
+    a.K = g.K;
+    a.cout = g.cout;
+    a.ys = g.ys;
+    a.relu = relu;
+    a.cin_real = g.c1 + g.c2;
+    const int kt = ceil_div(g.K, 64), ct = g.coutp / 16;
+    const int64_t steps = (M + 31) / 32;
+    const int64_t chunks = std::max<int64_t>(1, std::min<int64_t>(steps, 16384 / (kt * ct)));
+    a.vchunk = (steps + chunks - 1) / chunks * 32;
+    const int nz = ceil_div(M, a.vchunk);
+    hipLaunchKernelGGL(k_wgrad, dim3(kt, ct, nz), dim3(64), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t bchunk = std::max<int64_t>(256, (M + 1023) / 1024);
+    hipLaunchKernelGGL(k_bias_grad, dim3(ceil_div(M, bchunk), ceil_div(g.cout, 64)), dim3(256), 0,
+                       s, dy, y, relu, M, g.ys, g.cout, bchunk, db);
+    return hipGetLastError();
+}
+
+hipError_t pool_forward(int n, int lg, int c, const __bf16* x, __bf16* y, hipStream_t s) {
+    if (lg < 1 || c % 8 || !x || !y) return hipErrorInvalidValue;
+    const int64_t t = ((int64_t)n << (3 * (lg - 1))) * (c / 8);
+    hipLaunchKernelGGL(k_pool, dim3(ceil_div(t, 256)), dim3(256), 0, s, n, lg, c, x, y);
+    return hipGetLastError();
+}
+
+hipError_t pool_backward_add(int n, int lg, int c, const __bf16* dy, const __bf16* skip, int ctot,
+                             __bf16* dx, hipStream_t s) {
+    if (lg < 1 || c % 8 || !dy || !dx || (skip && (ctot < c || ctot % 8))) return hipErrorInvalidValue;
+    const int64_t t = ((int64_t)n << (3 * lg)) * (c / 8);
+    hipLaunchKernelGGL(k_pool_bwd_add, dim3(ceil_div(t, 256)), dim3(256), 0, s, n, lg, c, dy, skip,
+                       ctot, dx);
+    return hipGetLastError();
+}
+
+hipError_t upsample_backward(int n, int lg, int c, const __bf16* dcat, int ctot, int coff,
+                             __bf16* dlow, hipStream_t s) {
+    if (lg < 1 || c % 8 || coff % 8 || coff + c > ctot || !dcat || !dlow)
+        return hipErrorInvalidValue;
+    const int64_t t = ((int64_t)n << (3 * (lg - 1))) * (c / 8);
+    hipLaunchKernelGGL(k_up_bwd, dim3(ceil_div(t, 256)), dim3(256), 0, s, n, lg, c, dcat, ctot, coff,
+                       dlow);
+    return hipGetLastError();
+}
+
+hipError_t make_inputs(int n, int lg, const float* log10_ra, __bf16* x, hipStream_t s) {
+    if (n < 1 || n > kMaxBatch || !log10_ra || !x) return hipErrorInvalidValue;
+    SampleFloats lra;
+    for (int i = 0; i < kMaxBatch; ++i) lra.v[i] = i < n ? log10_ra[i] : 0.f;
+    const int64_t t = (int64_t)n << (3 * lg);
+    hipLaunchKernelGGL(k_inputs, dim3(ceil_div(t, 256)), dim3(256), 0, s, n, lg, lra, x);
+    return hipGetLastError();
+}
+
+hipError_t mse_forward_backward(int n, int lg, const float* out, const float* targets,
+                                const int32_t* idx, int64_t stride, const float* tscale4,
+                                __bf16* dy, double* partial, int* nblocks, hipStream_t s) {
+    if (n < 1 || n > kMaxBatch || !out || !targets || !idx || !dy || !partial)
+        return hipErrorInvalidValue;
+    SampleInts ix;
+    for (int i = 0; i < kMaxBatch; ++i) ix.v[i] = i < n ? idx[i] : 0;
+    const int64_t t = (int64_t)n << (3 * lg);
+    const int nb = ceil_div(t, 256);
+    *nblocks = nb;
+    const float4 ts = make_float4(tscale4[0], tscale4[1], tscale4[2], tscale4[3]);
+    hipLaunchKernelGGL(k_mse, dim3(nb), dim3(256), 0, s, n, lg, out, targets, ix, stride, ts, dy,
+                       partial);
+    return hipGetLastError();
+}
+
+hipError_t reduce_sum(const double* partial, int n, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, s, partial, n, out);
+    return hipGetLastError();
+}
+
+hipError_t adam_update(int64_t count, float* theta, float* m, float* v, const float* g, int t,
+                       float lr, float beta1, float beta2, float eps, hipStream_t s) {
+    const float c1 = 1.f - powf(beta1, (float)t), c2 = 1.f - powf(beta2, (float)t);
+    hipLaunchKernelGGL(k_adam, dim3(ceil_div(count, 256)), dim3(256), 0, s, count, theta, m, v, g,
+                       lr, beta1, beta2, eps, c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t fill_zero_f32(float* p, int64_t count, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero, dim3(ceil_div(count, 256)), dim3(256), 0, s, p, count);
+    return hipGetLastError();
+}
+
+hipError_t bf16_to_f32(const __bf16* x, int64_t cells, int cs, int c, float* y, hipStream_t s) {
+    const int64_t t = cells * c;
+    hipLaunchKernelGGL(k_bf16_to_f32, dim3(ceil_div(t, 256)), dim3(256), 0, s, x, cells, cs, c, y);
+    return hipGetLastError();
+}
+
+hipError_t cf_to_cl(const float* x, int n, int64_t v, int c, float* y, hipStream_t s) {
+    const int64_t t = (int64_t)n * v * c;
+    hipLaunchKernelGGL(k_cf_to_cl, dim3(ceil_div(t, 256)), dim3(256), 0, s, x, n, v, c, y);
+    return hipGetLastError();
+}
+
+}  // namespace lbmnn

@@ -7,13 +7,15 @@ import re
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "lbm.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("lbm.h", "lbm_nn.h")]
 
 
 def declared_functions():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(lbm_[a-z_0-9]+)\s*\(", text)))
+    names = set()
+    for h in HEADERS:
+        text = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b(lbm_[a-z_0-9]+)\s*\(", text))
+    return sorted(names)
 
 
 @pytest.fixture(scope="module")
@@ -96,3 +98,16 @@ def test_batch_validation_on_host(capi):
         capi.lbm_batch_workspace_bytes([a, b])
     with pytest.raises(capi.LbmError, match="1 to 255"):
         capi.lbm_batch_workspace_bytes([a] * 256)
+
+
+def test_network_parameter_count_and_config_checks(capi):
+    from oracle import nn_oracle
+    assert capi.lbm_nn_param_count() == nn_oracle.param_count()
+    c = capi.nn_config(64, 8)
+    assert capi.lbm_nn_workspace_bytes(c) > 4 * 4 * nn_oracle.param_count()
+    for bad in (capi.nn_config(48, 8), capi.nn_config(64, 0), capi.nn_config(64, 65),
+                capi.nn_config(4, 1), capi.nn_config(64, 8, lr=-1.0)):
+        with pytest.raises(capi.LbmError):
+            capi.lbm_nn_workspace_bytes(bad)
+    with pytest.raises(capi.LbmError):
+        capi.lbm_nn_create(c, 0x1000, 16)

@@ -1,0 +1,218 @@
+"""The warm-start network's BF16 matrix-core kernels against the FP64 NumPy
+oracle (oracle/nn_oracle.py).
+
+Per layer, the GPU's own BF16 input activations are fed to the oracle, so
+each convolution is checked alone: BF16 products are exact in FP32, the
+matrix cores sum up to 27 * 192 of them in FP32 (relative error below
+1e-4 of the sum of absolute terms), and the result is rounded once to BF16
+(2^-9 relative); the bar is 2^-8 |ref| + 1e-4 sum|terms|.  The whole
+network and its gradient carry about 30 such BF16 roundings (activations and
+their gradients), about 2^-9 sqrt(30) ~ 1e-2 relative; their bars are 3e-2
+(output) and 5e-2 (relative L2 error of each layer's gradient)."""
+import numpy as np
+import pytest
+
+from gpu_helpers import log, to_np
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def net_mod():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1710_04751_amd import network
+    return network
+
+
+@pytest.fixture(scope="module")
+def N():
+    from oracle import nn_oracle
+    return nn_oracle
+
+
+def to_bf16(a):
+    """Round to the nearest BF16 value (ties to even), returned as float64."""
+    f = np.asarray(a, dtype=np.float32)
+    b = f.view(np.uint32).astype(np.uint64)
+    b = (b + 0x7FFF + ((b >> 16) & 1)) & 0xFFFF0000
+    return b.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def params(N, seed):
+    """He-initialised weights rounded to BF16 (what the kernels use) and
+    small random FP32 biases."""
+    theta = N.init_params(seed)
+    rng = np.random.default_rng(seed + 100)
+    P = N.unflatten(theta)
+    for name, *_ in N.LAYERS:
+        w, b = P[name]
+        w[...] = to_bf16(w)
+        b[...] = np.float32(0.05 * rng.standard_normal(b.shape))
+    return theta
+
+
+GRID, LRA = 16, [3.3, 5.2]
+
+
+def layer_input(N, name, acts, x0):
+    """Input of a layer built from the GPU's activations as the kernels see
+    it (pooled tensors are rounded to BF16 by the pooling kernel)."""
+    pools = {"enc2a": "enc1b", "enc3a": "enc2b", "bota": "enc3b"}
+    cats = {"dec3a": ("enc3b", "botc"), "dec2a": ("enc2b", "dec3b"), "dec1a": ("enc1b", "dec2b")}
+    order = [l[0] for l in N.LAYERS]
+    if name == "enc1a":
+        return x0
+    if name in pools:
+        return to_bf16(N.avgpool2(acts[pools[name]]))
+    if name in cats:
+        a, b = cats[name]
+        return np.concatenate([acts[a], N.upsample2(acts[b])], axis=-1)
+    return acts[order[order.index(name) - 1]]
+
+
+def test_each_layer_matches_oracle_on_gpu_inputs(net_mod, N):
+    log("case: nn per-layer forward, grid 16")
+    theta = params(N, 11)
+    net = net_mod.WarmStartNet(GRID, 2)
+    net.set_params(torch.from_numpy(theta.astype(np.float32)))
+    net.forward(LRA)
+    acts = {}
+    for i, name in enumerate(net_mod.LAYER_NAMES):
+        acts[name] = to_np(net.activation(i, 2)).astype(np.float64)
+    x0 = to_bf16(N.inputs(LRA, GRID))
+    P = N.unflatten(theta)
+    for name, ci, co, k, relu in N.LAYERS:
+        x = layer_input(N, name, acts, x0)
+        w, b = P[name]
+        ref = N.conv3d(x, w, b)
+        bound_terms = N.conv3d(np.abs(x), np.abs(w), np.abs(b))
+        if relu:
+            ref = N.relu(ref)
+        err = np.abs(acts[name] - ref)
+        lim = 2.0 ** -8 * np.abs(ref) + 1e-4 * bound_terms
+        worst = float(np.max(err - lim))
+        log(f"{name}: max err {np.max(err):.2e} (max |ref| {np.max(np.abs(ref)):.2e})")
+        assert worst <= 0, (name, worst)
+    net.close()
+
+
+def test_network_output_matches_oracle(net_mod, N):
+    log("case: nn full forward, grid 16 and 8")
+    theta = params(N, 12)
+    for grid in (16, 8):
+        net = net_mod.WarmStartNet(grid, 2)
+        net.set_params(torch.from_numpy(theta.astype(np.float32)))
+        scale = [2.0, 1.0, 0.5, 1.0]
+        out = to_np(net.forward(LRA, out_scale=scale)).astype(np.float64)
+        ref, _ = N.forward(theta, to_bf16(N.inputs(LRA, grid)))
+        ref = np.moveaxis(ref, -1, 1) * np.array(scale)[None, :, None, None, None]
+        err = np.max(np.abs(out - ref)) / np.max(np.abs(ref))
+        log(f"grid {grid}: normalised max error {err:.2e}")
+        assert err < 3e-2
+        net.close()
+
+
+def gpu_cache(N, net_mod, net, n, x0):
+    """The oracle's activation cache filled with the GPU's own activations
+    (pooled inputs rounded to BF16 as the pooling kernel does)."""
+    acts = {name: to_np(net.activation(i, n)).astype(np.float64)
+            for i, name in enumerate(net_mod.LAYER_NAMES)}
+    a = dict(acts)
+    a["in"] = x0
+    a["pool1"] = to_bf16(N.avgpool2(acts["enc1b"]))
+    a["pool2"] = to_bf16(N.avgpool2(acts["enc2b"]))
+    a["pool3"] = to_bf16(N.avgpool2(acts["enc3b"]))
+    a["cat3"] = np.concatenate([acts["enc3b"], N.upsample2(acts["botc"])], axis=-1)
+    a["cat2"] = np.concatenate([acts["enc2b"], N.upsample2(acts["dec3b"])], axis=-1)
+    a["cat1"] = np.concatenate([acts["enc1b"], N.upsample2(acts["dec2b"])], axis=-1)
+    return a, acts["head"]
+
+
+def per_layer_rel(N, g, ref_g):
+    out, o = {}, 0
+    for name, ci, co, k, _ in N.LAYERS:
+        n = co * k ** 3 * ci + co
+        a, b = g[o:o + n], ref_g[o:o + n]
+        out[name] = (np.linalg.norm(a - b) / np.linalg.norm(b),
+                     float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b))))
+        o += n
+    return out
+
+
+def test_gradient_matches_oracle(net_mod, N):
+    """Two checks of lbm_nn_gradient.  (1) The oracle's backward pass run on
+    the GPU's own activations (same ReLU masks, same layer inputs) and on
+    the GPU's output: the remaining difference is the BF16 rounding of the
+    gradient tensors, about 10 roundings deep at the first layer, so each
+    layer's relative L2 error stays below 2e-2.  (2) The pure oracle from
+    the inputs: on a 16^3 grid the coarse levels hold 4^3 and 2^3 cells, and
+    ReLU units whose input is within BF16 rounding of zero switch, so only
+    the direction is held: cosine above 0.99 per layer, loss within 2e-2."""
+    log("case: nn gradient, grid 16")
+    theta = params(N, 13)
+    rng = np.random.default_rng(14)
+    tscale = [20.0, 20.0, 20.0, 1.0]
+    targets = (0.02 * rng.standard_normal((3, 4, GRID, GRID, GRID))).astype(np.float32)
+    index = [2, 0]
+    net = net_mod.WarmStartNet(GRID, 2, target_scale=tscale)
+    net.set_params(torch.from_numpy(theta.astype(np.float32)))
+    loss, g = net.gradient(LRA, torch.from_numpy(targets).cuda(), index)
+    g = to_np(g).astype(np.float64)
+    tg = np.moveaxis(targets[index].astype(np.float64), 1, -1) * np.array(tscale)
+    x0 = to_bf16(N.inputs(LRA, GRID))
+    a, out = gpu_cache(N, net_mod, net, 2, x0)
+    net.close()
+    same = per_layer_rel(N, g, N.backward(theta, a, 2.0 * (out - tg) / out.size))
+    ref_loss, ref_g = N.loss_and_gradient(theta, x0, tg)
+    pure = per_layer_rel(N, g, ref_g)
+    log(f"loss {loss:.6e} ref {ref_loss:.6e}")
+    for name in same:
+        log(f"{name}: same activations rel {same[name][0]:.2e}; pure oracle rel "
+            f"{pure[name][0]:.2e} cosine {pure[name][1]:.5f}")
+    assert abs(loss - ref_loss) < 2e-2 * ref_loss
+    bad = {k: v[0] for k, v in same.items() if not v[0] < 2e-2}
+    assert not bad, bad
+    bad = {k: v[1] for k, v in pure.items() if not v[1] > 0.99}
+    assert not bad, bad
+
+
+def test_first_adam_step(net_mod, N):
+    """Step 1 of Adam moves every parameter by lr g / (|g| + eps)."""
+    log("case: nn adam step")
+    theta = params(N, 15).astype(np.float32)
+    rng = np.random.default_rng(16)
+    targets = torch.from_numpy((0.1 * rng.standard_normal((2, 4, 8, 8, 8))).astype(np.float32))
+    targets = targets.cuda()
+    lr = 1e-3
+    net = net_mod.WarmStartNet(8, 2, lr=lr)
+    net.set_params(torch.from_numpy(theta))
+    _, g = net.gradient(LRA, targets, [0, 1])
+    net.train_step(LRA, targets, [0, 1])
+    t1 = to_np(net.get_params()).astype(np.float64)
+    g = to_np(g).astype(np.float64)
+    expect = theta.astype(np.float64) - lr * g / (np.abs(g) + 1e-8)
+    err = np.max(np.abs(t1 - expect) - 1e-6 * np.abs(theta))
+    log(f"adam: max deviation {err:.2e} of lr {lr}")
+    assert err < 1e-3 * lr
+    net.close()
+
+
+def test_training_lowers_the_loss(net_mod, N):
+    """A few dozen steps on four smooth targets (one per Rayleigh number)."""
+    log("case: nn training smoke")
+    g = 16
+    c = (np.arange(g) + 0.5) / g
+    z, y, x = np.meshgrid(c, c, c, indexing="ij")
+    lra = [3.0, 3.8, 4.6, 5.4]
+    tg = np.stack([np.stack([np.sin(np.pi * x) * np.sin(2 * np.pi * z) * r / 6,
+                             0 * x, -np.sin(2 * np.pi * x) * np.sin(np.pi * z) * r / 6,
+                             0.5 - x + 0.1 * r * np.sin(np.pi * z)]) for r in lra])
+    targets = torch.from_numpy(tg.astype(np.float32)).cuda()
+    net = net_mod.WarmStartNet(g, 4, lr=2e-3)
+    net.set_params(torch.from_numpy(N.init_params(3).astype(np.float32)))
+    losses = [net.train_step(lra, targets, [0, 1, 2, 3]) for _ in range(60)]
+    log(f"loss {losses[0]:.4e} -> {losses[-1]:.4e}")
+    assert np.isfinite(losses).all() and losses[-1] < 0.3 * losses[0]
+    net.close()
