@@ -167,7 +167,16 @@ lbm_status lbm_init_rest(lbm_handle* h);
 
 /* Equilibrium state from fields (device pointers, float, ncell each; NULL
  * means 0): rho = 1, velocity (ux, uy, uz), temperature T.  Used to start
- * from a prediction.  Asynchronous. */
+ * from a prediction.  The staggered part of the velocity is first set as a
+ * start from rest has it.  With pull streaming and bounce-back walls every
+ * population that carries x-momentum changes the parity of x at each step
+ * and the collision conserves momentum, so Qx = sum (-1)^x rho u_x only
+ * changes sign from step to step (likewise Qy); along z the collision adds
+ * S = g beta sum (-1)^z (T - T0), so Qz alternates about S/2.  Any other
+ * staggered momentum never decays: it stays as a period-2 oscillation.
+ * Hence ux -= (-1)^x Sx / ncell with Sx = sum (-1)^x ux, the same for uy,
+ * and uz -= (-1)^z (Sz - S/2) / ncell with Sz = sum (-1)^z uz.
+ * Asynchronous. */
 lbm_status lbm_init_macros(lbm_handle* h, const float* ux, const float* uy, const float* uz,
                            const float* T);
 
@@ -203,6 +212,18 @@ lbm_status lbm_residual(lbm_handle* h, double* max_dT);
  * its two neighbours (cell centres sit at (i + 1/2)/N).  Synchronises the
  * stream when peaks is given. */
 lbm_status lbm_centerlines(lbm_handle* h, double* u_line, double* w_line, lbm_peaks* peaks);
+
+/* Project fields onto the symmetries of the cavity problem (Sec. 3): the
+ * mirror y -> ny-1-y, under which uy changes sign, and the half turn about
+ * the y axis through the centre, (x, z) -> (nx-1-x, nz-1-z), under which ux,
+ * uz and T - T0 change sign (the walls swap temperatures, buoyancy
+ * reverses).  Each value becomes the signed mean over its four images.
+ * In place on device pointers (float, ncell each, the handle's grid; NULL
+ * skips a field).  A start from rest keeps these symmetries exactly; an
+ * initial field that breaks them seeds modes that the symmetric steady
+ * state does not damp at high Rayleigh numbers on coarse grids, so a
+ * predicted start is projected first.  Asynchronous. */
+lbm_status lbm_symmetrize(lbm_handle* h, float* ux, float* uy, float* uz, float* T);
 
 /* Step until steady: every check_every steps (even, > 0) take lbm_residual;
  * stop when it is below tol (LBM_STEADY_TOL), or when plateau_checks > 0,

@@ -99,6 +99,10 @@ lbm_status lbm_nn_train_step(lbm_nn* nn, int32_t n, const float* log10_ra,
                              const float* targets, const int32_t* target_index,
                              int64_t target_stride, double* loss);
 
+/* Change the Adam step size for later training steps (learning-rate
+ * schedules); lr > 0. */
+lbm_status lbm_nn_set_lr(lbm_nn* nn, float lr);
+
 /* Output of layer `layer` (0..15 in the order above; 15 is the head,
  * before out_scale) of the last forward pass as FP32 (device), channels-
  * last [n][g][g][g][c] on that layer's grid g; for checking the kernels.

@@ -277,3 +277,53 @@ def table1_peaks(mac, u0):
     u_max, u_pos = parabola_peak(u_line)
     w_max, w_pos = parabola_peak(w_line[::-1])
     return {"u_max": u_max, "u_pos": u_pos, "w_max": w_max, "w_pos": w_pos}
+
+
+def staggered_momentum(F):
+    """Staggered momentum sums (sum (-1)^x j_x, sum (-1)^y j_y,
+    sum (-1)^z j_z) of a stored state F[15][nz][ny][nx], with j the raw
+    first moment of the populations."""
+    _, nz, ny, nx = F.shape
+    ex = np.array([0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1])
+    ey = np.array([0, 0, 0, 1, -1, 0, 0, 1, 1, -1, -1, 1, 1, -1, -1])
+    ez = np.array([0, 0, 0, 0, 0, 1, -1, 1, 1, 1, 1, -1, -1, -1, -1])
+    jx = np.tensordot(ex, F, axes=1)
+    jy = np.tensordot(ey, F, axes=1)
+    jz = np.tensordot(ez, F, axes=1)
+    sx = (-1.0) ** np.arange(nx)
+    sy = (-1.0) ** np.arange(ny)
+    sz = (-1.0) ** np.arange(nz)
+    return (float(np.sum(jx * sx[None, None, :])), float(np.sum(jy * sy[None, :, None])),
+            float(np.sum(jz * sz[:, None, None])))
+
+
+def staggered_free(ux, uy, uz, T=None, gbeta=0.0, T_ref=0.0):
+    """Velocity fields [nz][ny][nx] with the staggered momentum of a start
+    from rest: sum (-1)^x u_x = sum (-1)^y u_y = 0 and sum (-1)^z u_z =
+    S/2 with S = g beta sum (-1)^z (T - T_ref), reached by adding uniform
+    (-1)^x, (-1)^y, (-1)^z patterns (with rho = 1 the momentum is the
+    velocity)."""
+    out = []
+    for a, axis in ((ux, 2), (uy, 1), (uz, 0)):
+        a = np.asarray(a, dtype=np.float64)
+        shape = [1, 1, 1]
+        shape[axis] = a.shape[axis]
+        s = ((-1.0) ** np.arange(a.shape[axis])).reshape(shape)
+        target = 0.0
+        if axis == 0 and T is not None:
+            target = 0.5 * gbeta * np.sum((np.asarray(T, dtype=np.float64) - T_ref) * s)
+        out.append(a - s * (np.sum(a * s) - target) / a.size)
+    return out
+
+
+def cavity_symmetrize(ux, uy, uz, T, T0=0.0):
+    """Signed mean of fields [nz][ny][nx] over the cavity's symmetry group:
+    identity, the mirror y -> ny-1-y (uy changes sign), the half turn
+    (x, z) -> (nx-1-x, nz-1-z) (ux, uz, T - T0 change sign) and their
+    product."""
+    mir = lambda a: a[:, ::-1, :]
+    rot = lambda a: a[::-1, :, ::-1]
+    f = lambda a, sm, sr: 0.25 * (a + sm * mir(a) + sr * rot(a) + sm * sr * mir(rot(a)))
+    t = np.asarray(T, dtype=np.float64) - T0
+    return (f(np.asarray(ux, dtype=np.float64), 1, -1), f(np.asarray(uy, dtype=np.float64), -1, 1),
+            f(np.asarray(uz, dtype=np.float64), 1, -1), T0 + f(t, 1, -1))

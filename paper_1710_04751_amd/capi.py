@@ -80,6 +80,7 @@ _SIGS = {
     "lbm_nusselt": (ctypes.c_int, [H, ctypes.POINTER(lbm_nu), vp, vp]),
     "lbm_residual": (ctypes.c_int, [H, ctypes.POINTER(ctypes.c_double)]),
     "lbm_centerlines": (ctypes.c_int, [H, vp, vp, ctypes.POINTER(lbm_peaks)]),
+    "lbm_symmetrize": (ctypes.c_int, [H, vp, vp, vp, vp]),
     "lbm_run_to_steady": (ctypes.c_int, [H, ctypes.c_double, ctypes.c_int64, ctypes.c_int64,
                                          ctypes.c_int32, ctypes.c_double,
                                          ctypes.POINTER(ctypes.c_int64),
@@ -134,6 +135,7 @@ _SIGS = {
     "lbm_nn_train_step": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_float), vp,
                                          ctypes.POINTER(ctypes.c_int32), ctypes.c_int64,
                                          ctypes.POINTER(ctypes.c_double)]),
+    "lbm_nn_set_lr": (ctypes.c_int, [vp, ctypes.c_float]),
     "lbm_nn_activation": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.c_int32, vp]),
     "lbm_nn_flops": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(ctypes.c_double)]),
@@ -246,6 +248,10 @@ def lbm_centerlines(h, u_line=None, w_line=None, peaks=True):
     pk = lbm_peaks() if peaks else None
     check(lib().lbm_centerlines(h, u_line, w_line, ctypes.byref(pk) if peaks else None))
     return pk
+
+
+def lbm_symmetrize(h, ux=None, uy=None, uz=None, T=None):
+    return check(lib().lbm_symmetrize(h, ux, uy, uz, T))
 
 
 def lbm_run_to_steady(h, tol, check_every, max_steps, plateau_checks=0, plateau_floor=0.0):
@@ -445,6 +451,10 @@ def lbm_nn_train_step(h, log10_ra, targets_ptr, target_index, target_stride, wan
                                   _ints(target_index), int(target_stride),
                                   ctypes.byref(loss) if want_loss else None))
     return loss.value if want_loss else None
+
+
+def lbm_nn_set_lr(h, lr):
+    return check(lib().lbm_nn_set_lr(h, float(lr)))
 
 
 def lbm_nn_activation(h, layer, n, out_ptr):

@@ -302,8 +302,9 @@ lbm_status lbm_init_macros(lbm_handle* h, const float* ux, const float* uy, cons
     if (!h) return fail(LBM_ERR_ARG, "null handle");
     if (h->owner && !batch_allows_reinit(h->owner))
         return fail(LBM_ERR_STATE, "batch member re-initialised at an odd batch step");
+    // red()[10..13]: scratch of the staggered momentum sums
     hipError_t e = launch_init_macros((Prec)h->p.precision, h->p.thermal_q, h->geom, h->lay.ps,
-                                      h->buf(0), ux, uy, uz, T, h->c, h->stream);
+                                      h->buf(0), ux, uy, uz, T, h->red() + 10, h->c, h->stream);
     if (e != hipSuccess) return hip_fail(e, "init_macros");
     h->cur = 0;
     h->steps = 0;
@@ -446,6 +447,13 @@ lbm_status lbm_centerlines(lbm_handle* h, double* u_line, double* w_line, lbm_pe
     // distance from the cold wall: reverse the x profile
     std::vector<double> wr(hv.rbegin(), hv.rbegin() + h->p.nx);
     parabola_peak(wr.data(), h->p.nx, &peaks->w_max, &peaks->w_pos);
+    return LBM_OK;
+}
+
+lbm_status lbm_symmetrize(lbm_handle* h, float* ux, float* uy, float* uz, float* T) {
+    if (!h) return fail(LBM_ERR_ARG, "null handle");
+    hipError_t e = launch_symmetrize(h->geom, ux, uy, uz, T, h->c.T_ref, h->stream);
+    if (e != hipSuccess) return hip_fail(e, "symmetrize");
     return LBM_OK;
 }
 

@@ -37,9 +37,10 @@ int value_bytes(Prec p);
 hipError_t launch_step(Prec p, int qt, bool general, const Geom& g, int64_t ps, StateBuf in,
                        StateBuf out, const Coefs& c, hipStream_t s);
 hipError_t launch_fill_zero(void* ptr, size_t bytes, hipStream_t s);
+// stag: device scratch of 4 doubles (16-byte aligned) for the staggered sums
 hipError_t launch_init_macros(Prec p, int qt, const Geom& g, int64_t ps, StateBuf st,
                               const float* ux, const float* uy, const float* uz, const float* T,
-                              const Coefs& c, hipStream_t s);
+                              double* stag, const Coefs& c, hipStream_t s);
 hipError_t launch_macros(Prec p, int qt, const Geom& g, int64_t ps, StateBuf st, void* rho,
                          void* ux, void* uy, void* uz, void* T, bool fp64, const Coefs& c,
                          hipStream_t s);
@@ -49,6 +50,8 @@ hipError_t launch_nusselt(Prec p, int qt, const Geom& g, int64_t ps, StateBuf st
 hipError_t launch_centerlines(Prec p, int qt, const Geom& g, int64_t ps, StateBuf st,
                               double* u_line, double* w_line, const Coefs& c, double u0,
                               hipStream_t s);
+hipError_t launch_symmetrize(const Geom& g, float* ux, float* uy, float* uz, float* T, double T0,
+                             hipStream_t s);
 hipError_t launch_residual(Prec p, int qt, const Geom& g, int64_t ps, StateBuf st, void* snapshot,
                            bool compare, unsigned long long* max_bits, unsigned int* bad_flag,
                            hipStream_t s);

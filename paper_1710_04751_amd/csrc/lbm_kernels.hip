@@ -1,23 +1,8 @@
-// gfx950 kernels of the cascaded double-distribution lattice Boltzmann
-// update (arXiv:1710.04751) and the observables around it.
-//
-// Step kernel: one thread per cell, one pass per time step (A -> B).
-//   * pull streaming (eq. 2b, 13b): population a of cell x is read from
-//     x - e_a in the previous post-collision state; each value is read once
-//     and written once, so the kernel moves (15 + q) values in and out per
-//     cell and is bound by HBM bandwidth;
-//   * SoA layout, x fastest: a wave reads 64 consecutive cells of one
-//     population, shifted by at most one element, so loads are coalesced;
-//   * walls (Sec. 3): a link whose source lies outside the box takes the
-//     opposite population of the cell itself (half-way bounce-back for the
-//     flow; anti-bounce-back -g + 2 w T_wall across the two Dirichlet walls,
-//     which take precedence on edges; bounce-back across the adiabatic ones);
-//   * T = sum g (eq. 25), F = g beta (T - T0) z (Boussinesq), then the flow
-//     collision and the scalar collision with the same step's velocity, all
-//     in registers, then non-temporal stores of the post-collision state;
-//   * blocks are numbered so that each of the 8 XCDs works on a contiguous
-//     range of tiles: neighbouring tiles of a row share the partly-read
-//     cache lines of the x-shifted populations in the same L2.
+// gfx950 kernels around the cascaded double-distribution lattice Boltzmann
+// update (arXiv:1710.04751): initialisation, state I/O and the observables
+// (macroscopic fields, wall Nusselt numbers, steady-state residual), and the
+// plain copy used as the bandwidth reference.  The per-step update itself
+// lives in lbm_step.hip.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -25,50 +10,12 @@
 #include <algorithm>
 #include <type_traits>
 
+#include "lbm_dispatch.hpp"
 #include "lbm_step.hpp"
 
 namespace lbm {
 
 namespace kern {
-
-// Block number -> tile number, so that XCD k (hardware places block b on XCD
-// b mod 8) receives the contiguous tile range [start_k, start_k + count_k).
-__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t nb) {
-    const uint32_t q = nb >> 3, r = nb & 7u, k = b & 7u;
-    return k * q + (k < r ? k : r) + (b >> 3);
-}
-
-struct CellPos {
-    int x, y, z;
-    uint32_t cell;
-    bool ok;
-};
-
-__device__ __forceinline__ CellPos tile_cell(const Geom& g) {
-    const uint32_t t = xcd_tile(blockIdx.x, gridDim.x);
-    const uint32_t per_z = (uint32_t)g.tiles_x * (uint32_t)g.tiles_y;
-    const uint32_t tz = t / per_z;
-    const uint32_t rem = t - tz * per_z;
-    const uint32_t ty = rem / (uint32_t)g.tiles_x;
-    const uint32_t tx = rem - ty * (uint32_t)g.tiles_x;
-    CellPos c;
-    c.x = (int)(tx * blockDim.x + threadIdx.x);
-    c.y = (int)(ty * blockDim.y + threadIdx.y);
-    c.z = (int)tz;
-    c.ok = c.x < g.nx && c.y < g.ny;
-    c.cell = ((uint32_t)c.z * (uint32_t)g.ny + (uint32_t)c.y) * (uint32_t)g.nx + (uint32_t)c.x;
-    return c;
-}
-
-// Single cavity: one thread per cell, blocks of bx * by cells of one plane.
-template <typename R, typename S, int QT, bool HG>
-__global__ void __launch_bounds__(1024)
-k_step(const S* __restrict__ Fi, const S* __restrict__ Gi, S* __restrict__ Fo,
-       S* __restrict__ Go, int64_t ps, Geom g, KCoef<R> k) {
-    const CellPos p = tile_cell(g);
-    if (!p.ok) return;
-    update_cell<R, S, QT, HG>(Fi, Gi, Fo, Go, ps, p.cell, p.x, p.y, p.z, g.nx, g.ny, g.nz, k);
-}
 
 // ---------------------------------------------------------------------------
 // Initialisation and state I/O
@@ -79,13 +26,62 @@ __global__ void k_fill_zero(uint4* __restrict__ p, size_t n16) {
         p[i] = make_uint4(0, 0, 0, 0);
 }
 
+// Staggered sums of an initial state: sum (-1)^x ux, sum (-1)^y uy,
+// sum (-1)^z uz and sum (-1)^z (T - T_ref) (FP64, added into sums[0..3]).
+__global__ void __launch_bounds__(256) k_stagger_sums(const float* ux, const float* uy,
+                                                      const float* uz, const float* T,
+                                                      double T_ref, Geom g, double* sums) {
+    __shared__ double red[4][256];
+    const int64_t ncell = (int64_t)g.nx * g.ny * g.nz;
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+    if (c < ncell) {
+        const int x = (int)(c % g.nx);
+        const int y = (int)((c / g.nx) % g.ny);
+        const int z = (int)(c / ((int64_t)g.nx * g.ny));
+        if (ux) a[0] = (x & 1) ? -(double)ux[c] : (double)ux[c];
+        if (uy) a[1] = (y & 1) ? -(double)uy[c] : (double)uy[c];
+        if (uz) a[2] = (z & 1) ? -(double)uz[c] : (double)uz[c];
+        const double t = (T ? (double)T[c] : 0.0) - T_ref;
+        a[3] = (z & 1) ? -t : t;
+    }
+    for (int k = 0; k < 4; ++k) red[k][threadIdx.x] = a[k];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 4; ++k) atomicAdd(&sums[k], red[k][0]);
+}
+
+// Equilibrium populations of (rho = 1, u, T), with the staggered part of
+// the velocity set as a start from rest has it.  Pull streaming moves every
+// population that carries x-momentum to a cell of the other x parity,
+// bounce-back returns it with the sign of e_x reversed, and collision
+// conserves momentum, so Qx = sum (-1)^x j_x only changes sign from step to
+// step (likewise Qy); along z the collision adds S = sum (-1)^z F_z, so Qz
+// alternates about S/2.  Rest has Qx = Qy = 0 and Qz at S/2 = 0; any other
+// staggered momentum would persist as a period-2 oscillation.  So ux and uy
+// lose their staggered sums and uz gets sum (-1)^z uz = S/2 (uniform
+// (-1)^x, (-1)^y, (-1)^z corrections).
 template <typename R, typename S, int QT>
-__global__ void k_init_macros(S* __restrict__ F, S* __restrict__ G, int64_t ps, int64_t ncell,
+__global__ void k_init_macros(S* __restrict__ F, S* __restrict__ G, int64_t ps, Geom geo,
                               const float* ux, const float* uy, const float* uz, const float* T,
-                              R cs2) {
+                              const double* __restrict__ stag, double gbeta, R cs2) {
+    const int64_t ncell = (int64_t)geo.nx * geo.ny * geo.nz;
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ncell) return;
-    const R u = ux ? (R)ux[c] : R(0), v = uy ? (R)uy[c] : R(0), w = uz ? (R)uz[c] : R(0);
+    const int x = (int)(c % geo.nx);
+    const int y = (int)((c / geo.nx) % geo.ny);
+    const int z = (int)(c / ((int64_t)geo.nx * geo.ny));
+    const double inv = 1.0 / (double)ncell;
+    const double cx = stag[0] * inv, cy = stag[1] * inv;
+    const double cz = (stag[2] - 0.5 * gbeta * stag[3]) * inv;
+    const R u = ux ? (R)((double)ux[c] - ((x & 1) ? -cx : cx)) : R(0);
+    const R v = uy ? (R)((double)uy[c] - ((y & 1) ? -cy : cy)) : R(0);
+    const R w = (R)((uz ? (double)uz[c] : 0.0) - ((z & 1) ? -cz : cz));
     const R t = T ? (R)T[c] : R(0);
     R d[15];
     flow_equilibrium<R>(R(0), u, v, w, d);
@@ -287,68 +283,10 @@ __global__ void k_copy(const uint4* __restrict__ src, uint4* __restrict__ dst, s
         dst[i] = src[i];
 }
 
-template <typename S>
-struct PrecOf;
-
-// ---------------------------------------------------------------------------
-// Dispatch helpers
-// ---------------------------------------------------------------------------
-template <typename R, typename S, int QT, bool HG>
-hipError_t step_impl(const Geom& g, int64_t ps, StateBuf in, StateBuf out, const Coefs& c,
-                     hipStream_t s) {
-    const KCoef<R> k = make_kcoef<R>(c, QT);
-    const dim3 block(g.bx, g.by, 1);
-    const dim3 grid((unsigned)((int64_t)g.tiles_x * g.tiles_y * g.nz), 1, 1);
-    hipLaunchKernelGGL((k_step<R, S, QT, HG>), grid, block, 0, s, (const S*)in.F, (const S*)in.G,
-                       (S*)out.F, (S*)out.G, ps, g, k);
-    return hipGetLastError();
-}
-
-inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
-
 }  // namespace kern
 using namespace kern;
 
 int value_bytes(Prec p) { return p == Prec::FP64 ? 8 : (p == Prec::FP32 ? 4 : 2); }
-
-#define LBM_DISPATCH_PQ(p, qt, ...)                                       \
-    do {                                                                  \
-        if (p == Prec::FP64 && qt == 7) {                                 \
-            using R = double; using S = double; constexpr int Q = 7; __VA_ARGS__; \
-        } else if (p == Prec::FP64 && qt == 15) {                         \
-            using R = double; using S = double; constexpr int Q = 15; __VA_ARGS__; \
-        } else if (p == Prec::FP32 && qt == 7) {                          \
-            using R = float; using S = float; constexpr int Q = 7; __VA_ARGS__;  \
-        } else if (p == Prec::FP32 && qt == 15) {                         \
-            using R = float; using S = float; constexpr int Q = 15; __VA_ARGS__; \
-        } else if (p == Prec::FP32_S16 && qt == 7) {                      \
-            using R = float; using S = _Float16; constexpr int Q = 7; __VA_ARGS__; \
-        } else if (p == Prec::FP32_S16 && qt == 15) {                     \
-            using R = float; using S = _Float16; constexpr int Q = 15; __VA_ARGS__; \
-        } else {                                                          \
-            return hipErrorInvalidValue;                                  \
-        }                                                                 \
-    } while (0)
-
-hipError_t launch_step(Prec p, int qt, bool general, const Geom& g, int64_t ps, StateBuf in,
-                       StateBuf out, const Coefs& c, hipStream_t s) {
-    if (general) {
-        LBM_DISPATCH_PQ(p, qt, return (step_impl<R, S, Q, true>(g, ps, in, out, c, s)));
-    } else {
-        LBM_DISPATCH_PQ(p, qt, return (step_impl<R, S, Q, false>(g, ps, in, out, c, s)));
-    }
-}
-
-const char* step_kernel_name(Prec p, int qt, bool general) {
-    static const char* names[3][2][2] = {
-        {{"lbm::kern::k_step<double, double, 7, false>", "lbm::kern::k_step<double, double, 7, true>"},
-         {"lbm::kern::k_step<double, double, 15, false>", "lbm::kern::k_step<double, double, 15, true>"}},
-        {{"lbm::kern::k_step<float, float, 7, false>", "lbm::kern::k_step<float, float, 7, true>"},
-         {"lbm::kern::k_step<float, float, 15, false>", "lbm::kern::k_step<float, float, 15, true>"}},
-        {{"lbm::kern::k_step<float, _Float16, 7, false>", "lbm::kern::k_step<float, _Float16, 7, true>"},
-         {"lbm::kern::k_step<float, _Float16, 15, false>", "lbm::kern::k_step<float, _Float16, 15, true>"}}};
-    return names[(int)p][qt == 15][general ? 1 : 0];
-}
 
 hipError_t launch_fill_zero(void* ptr, size_t bytes, hipStream_t s) {
     const size_t n16 = bytes / 16;
@@ -360,11 +298,18 @@ hipError_t launch_fill_zero(void* ptr, size_t bytes, hipStream_t s) {
 
 hipError_t launch_init_macros(Prec p, int qt, const Geom& g, int64_t ps, StateBuf st,
                               const float* ux, const float* uy, const float* uz, const float* T,
-                              const Coefs& c, hipStream_t s) {
+                              double* stag, const Coefs& c, hipStream_t s) {
     const int64_t ncell = (int64_t)g.nx * g.ny * g.nz;
+    hipError_t e = launch_fill_zero(stag, 32, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_stagger_sums, dim3(blocks_for(ncell, 256)), dim3(256), 0, s, ux, uy, uz,
+                       T, c.T_ref, g, stag);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
     LBM_DISPATCH_PQ(p, qt, {
         hipLaunchKernelGGL((k_init_macros<R, S, Q>), dim3(blocks_for(ncell, 256)), dim3(256), 0, s,
-                           (S*)st.F, (S*)st.G, ps, ncell, ux, uy, uz, T, (R)c.cs2);
+                           (S*)st.F, (S*)st.G, ps, g, ux, uy, uz, T, (const double*)stag,
+                           c.gbeta, (R)c.cs2);
         return hipGetLastError();
     });
 }

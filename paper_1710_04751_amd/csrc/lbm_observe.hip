@@ -79,7 +79,55 @@ hipError_t centerlines_impl(const Geom& g, int64_t ps, StateBuf st, double* u_li
     return hipGetLastError();
 }
 
+// Projection of (ux, uy, uz, T) onto the symmetries of the cavity (Sec. 3):
+// the mirror y -> ny-1-y (uy changes sign) and the half turn about the y
+// axis through the centre, (x, z) -> (nx-1-x, nz-1-z) (ux, uz and T - T0
+// change sign).  One thread per orbit of the four-element group: it reads
+// the four images, averages them with their signs and writes all four back,
+// so orbits never overlap and the update is in place.
+__global__ void k_symmetrize(Geom g, float* ux, float* uy, float* uz, float* T, double T0) {
+    const int64_t ncell = (int64_t)g.nx * g.ny * g.nz;
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncell) return;
+    const int x = (int)(c % g.nx);
+    const int y = (int)((c / g.nx) % g.ny);
+    const int z = (int)(c / ((int64_t)g.nx * g.ny));
+    const int xm = g.nx - 1 - x, ym = g.ny - 1 - y, zm = g.nz - 1 - z;
+    if (y > ym || z > zm || (z == zm && x > xm)) return;  // not the orbit's representative
+    const int64_t id = c;
+    const int64_t mir = ((int64_t)z * g.ny + ym) * g.nx + x;
+    const int64_t rot = ((int64_t)zm * g.ny + y) * g.nx + xm;
+    const int64_t mr = ((int64_t)zm * g.ny + ym) * g.nx + xm;
+    // sign of each field under (identity, mirror, rotation, mirror-rotation)
+    if (ux) {
+        const double a = 0.25 * ((double)ux[id] + ux[mir] - ux[rot] - ux[mr]);
+        ux[id] = (float)a, ux[mir] = (float)a, ux[rot] = (float)-a, ux[mr] = (float)-a;
+    }
+    if (uy) {
+        const double a = 0.25 * ((double)uy[id] - uy[mir] + uy[rot] - uy[mr]);
+        uy[id] = (float)a, uy[mir] = (float)-a, uy[rot] = (float)a, uy[mr] = (float)-a;
+    }
+    if (uz) {
+        const double a = 0.25 * ((double)uz[id] + uz[mir] - uz[rot] - uz[mr]);
+        uz[id] = (float)a, uz[mir] = (float)a, uz[rot] = (float)-a, uz[mr] = (float)-a;
+    }
+    if (T) {
+        const double a = 0.25 * (((double)T[id] - T0) + ((double)T[mir] - T0) -
+                                 ((double)T[rot] - T0) - ((double)T[mr] - T0));
+        T[id] = (float)(T0 + a), T[mir] = (float)(T0 + a);
+        T[rot] = (float)(T0 - a), T[mr] = (float)(T0 - a);
+    }
+}
+
 }  // namespace kern
+
+hipError_t launch_symmetrize(const Geom& g, float* ux, float* uy, float* uz, float* T, double T0,
+                             hipStream_t s) {
+    const int64_t ncell = (int64_t)g.nx * g.ny * g.nz;
+    hipLaunchKernelGGL(kern::k_symmetrize, dim3((unsigned)((ncell + 255) / 256)), dim3(256), 0, s,
+                       g, ux, uy, uz, T, T0);
+    return hipGetLastError();
+}
 
 hipError_t launch_centerlines(Prec p, int qt, const Geom& g, int64_t ps, StateBuf st,
                               double* u_line, double* w_line, const Coefs& c, double u0,

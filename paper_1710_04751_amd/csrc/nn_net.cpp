@@ -433,6 +433,12 @@ lbm_status lbm_nn_train_step(lbm_nn* nn, int32_t n, const float* log10_ra,
     return loss ? read_loss(nn, n, loss) : LBM_OK;
 }
 
+lbm_status lbm_nn_set_lr(lbm_nn* nn, float lr) {
+    if (!nn || !(lr > 0)) return lbm::fail(LBM_ERR_ARG, "lr must be positive");
+    nn->cfg.lr = lr;
+    return LBM_OK;
+}
+
 lbm_status lbm_nn_activation(lbm_nn* nn, int32_t layer, int32_t n, float* out) {
     if (!nn || !out) return lbm::fail(LBM_ERR_ARG, "null argument");
     if (layer < 0 || layer >= kLayers) return lbm::fail(LBM_ERR_ARG, "layer out of range");

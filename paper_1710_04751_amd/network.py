@@ -1,6 +1,9 @@
 """The learned warm start: the encoder-decoder of include/lbm_nn.h on PyTorch
 device memory.  Argument marshalling only; every layer, the loss, the
 backward pass and Adam run in the library's HIP kernels."""
+import math
+
+import numpy as np
 import torch
 
 from . import capi
@@ -12,6 +15,25 @@ LAYER_NAMES = ["enc1a", "enc1b", "enc2a", "enc2b", "enc3a", "enc3b", "bota", "bo
                "dec3a", "dec3b", "dec2a", "dec2b", "dec1a", "dec1b", "head"]
 LAYER_OUTPUTS = [(0, 16), (0, 16), (1, 32), (1, 32), (2, 64), (2, 64), (3, 128), (3, 128),
                  (3, 128), (2, 64), (2, 64), (1, 32), (1, 32), (0, 16), (0, 16), (0, 4)]
+
+
+# (input channels, output channels, kernel edge) of each layer
+LAYER_SHAPES = [(4, 16, 3), (16, 16, 3), (16, 32, 3), (32, 32, 3), (32, 64, 3), (64, 64, 3),
+                (64, 128, 3), (128, 128, 3), (128, 128, 3), (192, 64, 3), (64, 64, 3),
+                (96, 32, 3), (32, 32, 3), (48, 16, 3), (16, 16, 3), (16, 4, 1)]
+
+
+def init_params(seed):
+    """Seeded starting parameters: normal weights with variance 2 / fan-in
+    (He initialisation, suited to ReLU), zero biases; flat FP32 vector in
+    the library's parameter layout."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for ci, co, k in LAYER_SHAPES:
+        fan_in = ci * k ** 3
+        parts.append((rng.standard_normal(co * fan_in) * math.sqrt(2.0 / fan_in)).astype(np.float32))
+        parts.append(np.zeros(co, dtype=np.float32))
+    return np.concatenate(parts)
 
 
 class WarmStartNet:
@@ -99,6 +121,9 @@ class WarmStartNet:
         capi.lbm_nn_activation(self.h, layer, n, out.data_ptr())
         self._done()
         return out
+
+    def set_lr(self, lr):
+        capi.lbm_nn_set_lr(self.h, lr)
 
     def flops(self, n):
         return capi.lbm_nn_flops(self.h, n)

@@ -70,6 +70,18 @@ class Cavity:
         capi.lbm_init_macros(self.h, *[None if t is None else t.data_ptr() for t in keep])
         self._sync_if_needed()
 
+    def symmetrize(self, ux=None, uy=None, uz=None, T=None):
+        """Project float32 device fields onto the cavity's symmetries, in
+        place (lbm_symmetrize)."""
+        fs = [ux, uy, uz, T]
+        for t in fs:
+            if t is not None and (t.dtype != torch.float32 or not t.is_contiguous() or
+                                  t.numel() != self.ncell or not t.is_cuda):
+                raise ValueError("fields must be contiguous float32 device tensors of the grid")
+        self._inputs_ready()
+        capi.lbm_symmetrize(self.h, *[None if t is None else t.data_ptr() for t in fs])
+        self._sync_if_needed()
+
     def macros(self, fp64=True):
         dt = torch.float64 if fp64 else torch.float32
         out = self._empty(5, dtype=dt)

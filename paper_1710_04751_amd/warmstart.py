@@ -1,0 +1,195 @@
+"""Learned warm start of the steady cavity solve.
+
+Steady states of the differentially heated cube (Sec. 3 of the paper) are
+produced by the batched solver from rest; the encoder-decoder of
+include/lbm_nn.h learns the map Rayleigh number -> (u, v, w, T) from them;
+a new cavity is then started from the network's prediction, projected onto
+the symmetries of the cavity (lbm_symmetrize) and turned into equilibrium
+populations (lbm_init_macros), instead of from rest.
+The plain cold-started solve stays the fallback (a warm run that fails to
+meet the steady rule is redone from rest) and the reference for the result
+(the steady Nusselt number must not move).
+
+Orchestration only: solver steps, network layers, loss, backward pass and
+Adam all run in the library's HIP kernels.
+"""
+import math
+import time
+
+import numpy as np
+import torch
+
+from . import capi
+from . import solver as S
+from . import workloads as W
+from .network import WarmStartNet
+
+
+def cavity_params(grid, ra, precision="fp32"):
+    return S.make_params(grid, ra, precision=precision, **W.STABLE_RATES)
+
+
+def solve(params, init=None, max_steps=600_000, chunk=64, rule=None, log=print):
+    """Run cavities to steady state in the batched solver, `chunk` at a time.
+
+    init: optional [N][4][G][G][G] float32 device tensor of lattice-unit
+    fields (u, v, w, T) to start from (equilibrium populations); rest
+    otherwise.  Returns a dict of per-cavity lists (steps to the steady
+    rule, how it ended, wall-mean hot Nu, mid-plane Nu), the steady fields
+    [N][4][G][G][G] (float32, device), wall time and cell updates."""
+    rule = dict(W.STEADY_RULE if rule is None else rule)
+    n = len(params)
+    g = params[0].nx
+    fields = torch.empty(n, 4, g, g, g, dtype=torch.float32, device="cuda")
+    out = {"steps": [], "how": [], "nu": [], "nu_mid": [], "residual": []}
+    wall, updates = 0.0, 0
+    for start in range(0, n, chunk):
+        part = params[start:start + chunk]
+        batch = S.Batch(part)
+        if init is not None:
+            for i, m in enumerate(batch.members):
+                f = init[start + i].clone()
+                m.symmetrize(f[0], f[1], f[2], f[3])
+                m.init_macros(ux=f[0], uy=f[1], uz=f[2], T=f[3])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        steps, how, res = batch.run_to_steady(max_steps=max_steps, **rule)
+        torch.cuda.synchronize()
+        wall += time.perf_counter() - t0
+        for i, m in enumerate(batch.members):
+            f = fields[start + i]
+            m._inputs_ready()
+            capi.lbm_macros(m.h, None, f[0].data_ptr(), f[1].data_ptr(), f[2].data_ptr(),
+                            f[3].data_ptr(), fp64=False)
+            m._sync_if_needed()
+            nu = m.nusselt()
+            out["nu"].append(nu.nu_hot_wall)
+            out["nu_mid"].append(nu.nu_hot_mid)
+            updates += part[i].nx * part[i].ny * part[i].nz * m.steps_done()
+        out["steps"] += list(steps)
+        out["how"] += list(how)
+        out["residual"] += list(res)
+        batch.close()
+        log(f"steady solve: {min(start + chunk, n)}/{n} cavities, {wall:.1f} s")
+    out.update(fields=fields, wall_s=wall, cell_updates=updates)
+    return out
+
+
+def converged(how):
+    return how in (capi.LBM_STEADY_TOL, capi.LBM_STEADY_PLATEAU)
+
+
+def train(net, log10_ra, targets, epochs, batch, lr, seed=0, log=print):
+    """Adam over shuffled mini-batches with a cosine decay of the step size
+    from lr to lr/20.  Returns the per-epoch mean losses and timing."""
+    rng = np.random.default_rng(seed)
+    n = len(log10_ra)
+    lra = np.asarray(log10_ra, dtype=np.float64)
+    steps_per_epoch = math.ceil(n / batch)
+    total = epochs * steps_per_epoch
+    hist = []
+    k = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for ep in range(epochs):
+        perm = rng.permutation(n)
+        losses = []
+        for i in range(0, n, batch):
+            idx = perm[i:i + batch]
+            net.set_lr(lr * (0.05 + 0.95 * 0.5 * (1 + math.cos(math.pi * k / total))))
+            want = ep == epochs - 1 or ep % 10 == 0
+            l = net.train_step(lra[idx].tolist(), targets, idx.tolist(), want_loss=want)
+            if want:
+                losses.append(l)
+            k += 1
+        if losses:
+            hist.append((ep, float(np.mean(losses))))
+            if ep % 20 == 0 or ep == epochs - 1:
+                log(f"epoch {ep}: loss {hist[-1][1]:.4e} ({time.perf_counter() - t0:.1f} s)")
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    _, per_step = net.flops(batch)
+    return {"history": hist, "seconds": secs, "steps": total,
+            "tflops": per_step * n / batch * epochs / secs / 1e12}
+
+
+def predict(net, log10_ra, u0):
+    """Lattice-unit fields [N][4][G][G][G] predicted for log10 Ra values."""
+    n = len(log10_ra)
+    g = net.grid
+    out = torch.empty(n, 4, g, g, g, dtype=torch.float32, device="cuda")
+    for i in range(0, n, net.batch):
+        part = list(log10_ra[i:i + net.batch])
+        out[i:i + len(part)] = net.forward(part, out_scale=[u0, u0, u0, 1.0])
+    return out
+
+
+def validation_loss(net, log10_ra, targets):
+    """Mean loss of the network on (log10_ra, targets) in batches."""
+    n = len(log10_ra)
+    tot = 0.0
+    for i in range(0, n, net.batch):
+        idx = list(range(i, min(n, i + net.batch)))
+        loss, _ = net.gradient([log10_ra[j] for j in idx], targets, idx)
+        tot += loss * len(idx)
+    return tot / n
+
+
+def study(grid=64, n_train=200, n_test=50, ra_range=(1e3, 1e5), epochs=200, batch=8, lr=2e-3,
+          seeds=(17101, 17102), init_seed=1, max_steps=600_000, log=print):
+    """The whole warm-start experiment: steady training and test sets from
+    rest (the cold solves), training, then every test cavity solved again
+    from the network's prediction.  Returns a summary dict."""
+    from .network import init_params
+    u0 = cavity_params(grid, 1e4).u0
+    lo, hi = math.log10(ra_range[0]), math.log10(ra_range[1])
+    lra_train = np.random.default_rng(seeds[0]).uniform(lo, hi, n_train)
+    lra_test = np.random.default_rng(seeds[1]).uniform(lo, hi, n_test)
+    log(f"warm start: {n_train} training and {n_test} test cavities, {grid}^3, "
+        f"Ra log-uniform in [{ra_range[0]:g}, {ra_range[1]:g}]")
+    cold_train = solve([cavity_params(grid, 10 ** r) for r in lra_train], max_steps=max_steps,
+                       log=log)
+    cold_test = solve([cavity_params(grid, 10 ** r) for r in lra_test], max_steps=max_steps,
+                      log=log)
+    ok_train = [i for i, h in enumerate(cold_train["how"]) if converged(h)]
+    targets = cold_train["fields"][ok_train].contiguous()
+    lra_fit = lra_train[ok_train]
+    net = WarmStartNet(grid, batch, lr=lr, target_scale=(1 / u0, 1 / u0, 1 / u0, 1.0))
+    net.set_params(torch.from_numpy(init_params(init_seed)))
+    fit = train(net, lra_fit, targets, epochs, batch, lr, seed=init_seed, log=log)
+    ok_test = [i for i, h in enumerate(cold_test["how"]) if converged(h)]
+    val = validation_loss(net, lra_test[ok_test].tolist(), cold_test["fields"][ok_test].contiguous())
+    pred = predict(net, lra_test.tolist(), u0)
+    warm = solve([cavity_params(grid, 10 ** r) for r in lra_test], init=pred,
+                 max_steps=max_steps, log=log)
+    # fallback: a warm run that misses the steady rule is solved from rest
+    fallback = [i for i in range(n_test) if not converged(warm["how"][i])]
+    rows = []
+    for i in range(n_test):
+        if not converged(cold_test["how"][i]):
+            continue
+        ws = warm["steps"][i] if i not in fallback else None
+        rows.append({"log10_ra": float(lra_test[i]), "cold_steps": int(cold_test["steps"][i]),
+                     "warm_steps": None if ws is None else int(ws),
+                     "nu_cold": cold_test["nu"][i], "nu_warm": warm["nu"][i],
+                     "nu_rel_diff": abs(warm["nu"][i] - cold_test["nu"][i]) / cold_test["nu"][i]})
+    both = [r for r in rows if r["warm_steps"] is not None]
+    ratio = [r["warm_steps"] / r["cold_steps"] for r in both]
+    net.close()
+    return {
+        "grid": grid, "train": n_train, "test": n_test, "ra_range": list(ra_range),
+        "train_converged": len(ok_train), "test_converged": len(rows),
+        "epochs": epochs, "batch": batch, "lr": lr,
+        "train_seconds": round(fit["seconds"], 2), "train_tflops": round(fit["tflops"], 2),
+        "final_train_loss": fit["history"][-1][1] if fit["history"] else None,
+        "val_loss": val,
+        "cold_steps_median": float(np.median([r["cold_steps"] for r in both])) if both else None,
+        "warm_steps_median": float(np.median([r["warm_steps"] for r in both])) if both else None,
+        "cold_steps_mean": float(np.mean([r["cold_steps"] for r in both])) if both else None,
+        "warm_steps_mean": float(np.mean([r["warm_steps"] for r in both])) if both else None,
+        "steps_ratio_median": float(np.median(ratio)) if ratio else None,
+        "nu_rel_diff_max": max(r["nu_rel_diff"] for r in rows) if rows else None,
+        "fallbacks": len(fallback),
+        "cold_solve_s": round(cold_test["wall_s"], 2), "warm_solve_s": round(warm["wall_s"], 2),
+        "rows": rows,
+    }

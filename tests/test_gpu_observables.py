@@ -164,3 +164,19 @@ def test_run_to_steady_rules(solver):
     assert how == capi.LBM_STEADY_MAX_STEPS and steps == -1 and c3.steps_done() == 1000
     for c in (cav, c32, c3):
         c.close()
+
+
+@pytest.mark.parametrize("shape", [(12, 10, 8), (11, 9, 7)])
+def test_symmetrize_matches_oracle(solver, oracle, shape):
+    """In-place projection onto the cavity's symmetries (float32 fields)."""
+    from paper_1710_04751_amd import workloads as W
+    nx, ny, nz = shape
+    f = [W.smooth_field((nz, ny, nx), s, a).astype(np.float32) for s, a in
+         ((21, 0.02), (22, 0.02), (23, 0.02), (24, 0.5))]
+    ref = oracle.cavity_symmetrize(*[a.astype(np.float64) for a in f])
+    cav = solver.Cavity(solver.make_params(nx=nx, ny=ny, nz=nz, Ra=1e3))
+    t = [torch.tensor(a).cuda() for a in f]
+    cav.symmetrize(*t)
+    for a, b in zip(t, ref):
+        assert np.max(np.abs(to_np(a).astype(np.float64) - b)) <= 1e-7 * np.max(np.abs(b))
+    cav.close()

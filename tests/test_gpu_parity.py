@@ -130,18 +130,28 @@ def test_ragged_random_state(solver, oracle, name, qt, over, prec, tol):
 
 
 def test_init_macros_matches_oracle_equilibrium(solver, oracle):
-    """Equilibrium initialisation from (u, T) fields (float32 inputs)."""
+    """Equilibrium initialisation from (u, T) fields (float32 inputs), with
+    the staggered velocity components removed as the oracle does; the state
+    then carries no staggered momentum, and keeps none while it steps."""
     from paper_1710_04751_amd import workloads as W
     shape = (9, 10, 11)
     p = oracle.cavity_params(11, 1e4, qt=15, ny=10, nz=9)
     fields = [W.smooth_field(shape, s, a).astype(np.float32).astype(np.float64)
               for s, a in ((11, 0.03), (12, 0.03), (13, 0.03), (14, 0.5))]
-    F, G = oracle.init_equilibrium(p, ux=fields[0], uy=fields[1], uz=fields[2], T=fields[3])
+    u = oracle.staggered_free(*fields[:3], T=fields[3], gbeta=p.gbeta, T_ref=p.T_ref)
+    F, G = oracle.init_equilibrium(p, ux=u[0], uy=u[1], uz=u[2], T=fields[3])
     cav = solver.Cavity(solver.make_params(nx=11, ny=10, nz=9, Ra=1e4, precision="fp64",
                                            thermal_q=15))
     cav.init_macros(*[torch.tensor(f, dtype=torch.float32) for f in fields])
     Fg, Gg = (to_np(t) for t in cav.populations())
     assert np.max(np.abs(Fg - F)) < 1e-15 and np.max(np.abs(Gg - G)) < 1e-15
+    q = oracle.staggered_momentum(Fg)
+    sz = (-1.0) ** np.arange(9)
+    half_s = 0.5 * p.gbeta * np.sum((fields[3] - p.T_ref) * sz[:, None, None])
+    assert abs(q[0]) < 1e-14 and abs(q[1]) < 1e-14 and abs(q[2] - half_s) < 1e-14
+    cav.step(7)
+    q = oracle.staggered_momentum(to_np(cav.populations()[0]))
+    assert abs(q[0]) < 1e-13 and abs(q[1]) < 1e-13
     cav.close()
 
 

@@ -351,3 +351,106 @@ def test_centerline_profiles_pick_the_symmetry_lines(oracle, shape):
     assert abs(pk["u_max"] - 1.0) < 1e-13 and abs(pk["u_pos"] - 0.3) < 1e-12
     # the hot wall is at x = 0, so the peak lies 0.85 L from the cold wall
     assert abs(pk["w_max"] - 0.5) < 1e-13 and abs(pk["w_pos"] - 0.85) < 1e-12
+
+
+@pytest.mark.parametrize("qt,shape", [(7, (8, 7, 6)), (15, (7, 6, 9))])
+def test_staggered_momentum_only_changes_sign(oracle, qt, shape):
+    """Pull streaming moves every population with e_x != 0 to a cell of the
+    other x parity, bounce-back returns it to the same cell with e_x
+    reversed, and collision conserves momentum (the force is along z): so
+    sum (-1)^x j_x flips sign exactly at every step, and likewise along y;
+    along z the force adds sum (-1)^z F_z, which vanishes for g beta = 0."""
+    from paper_1710_04751_amd import workloads as W
+    nx, ny, nz = shape
+    p = oracle.cavity_params(nx, 2e3, u0=0.1, qt=qt, ny=ny, nz=nz, omega_bulk=1.0)
+    F, G = oracle.rest_state(p)
+    F = F + W.perturbation(F.shape[1:], 15, 3, 1e-3)
+    G = G + W.perturbation(G.shape[1:], qt, 4, 1e-2)
+    q = [oracle.staggered_momentum(F)]
+    for _ in range(4):
+        F, G, _ = oracle.run(p, 1, F, G)
+        q.append(oracle.staggered_momentum(F))
+    for a, b in zip(q, q[1:]):
+        assert abs(a[0] + b[0]) < 1e-13 and abs(a[1] + b[1]) < 1e-13  # FP64 sums of ~5000 terms
+        assert abs(a[0]) > 1e-6 and abs(a[1]) > 1e-6
+    p0 = oracle.cavity_params(nx, 2e3, u0=0.1, qt=qt, ny=ny, nz=nz, omega_bulk=1.0)
+    p0.gbeta = 0.0
+    F, G = oracle.rest_state(p0)
+    F = F + W.perturbation(F.shape[1:], 15, 5, 1e-3)
+    qz = [oracle.staggered_momentum(F)[2]]
+    for _ in range(3):
+        F, G, _ = oracle.run(p0, 1, F, G)
+        qz.append(oracle.staggered_momentum(F)[2])
+    for a, b in zip(qz, qz[1:]):
+        assert abs(a + b) < 1e-13
+
+
+def test_staggered_free_velocity(oracle):
+    """The projected fields have zero staggered sums and differ from the
+    input by the uniform staggered pattern only."""
+    from paper_1710_04751_amd import workloads as W
+    shape = (5, 6, 7)
+    u = [W.smooth_field(shape, s, 0.02) for s in (1, 2, 3)]
+    v = oracle.staggered_free(*u)
+    sx, sy, sz = ((-1.0) ** np.arange(n) for n in (7, 6, 5))
+    assert abs(np.sum(v[0] * sx[None, None, :])) < 1e-16
+    assert abs(np.sum(v[1] * sy[None, :, None])) < 1e-16
+    assert abs(np.sum(v[2] * sz[:, None, None])) < 1e-16
+    d = u[0] - v[0]
+    assert np.allclose(d, d[0, 0, 0] * sx[None, None, :], atol=1e-18)
+    # equilibrium from them carries no staggered momentum
+    p = oracle.cavity_params(7, 1e3, ny=6, nz=5)
+    F, _ = oracle.init_equilibrium(p, ux=v[0], uy=v[1], uz=v[2], T=np.zeros(shape))
+    assert max(abs(q) for q in oracle.staggered_momentum(F)) < 1e-15
+
+
+def test_staggered_z_momentum_follows_the_force(oracle):
+    """Along z the collision adds F_z, so Qz(n+1) = -Qz(n) + S(n+1) exactly,
+    with S = g beta sum (-1)^z (T - T0) of the step's own T.  Qz therefore
+    alternates about S/2: a start with Qz = S/2 (the staggered_free rule)
+    keeps the alternating part orders of magnitude below a start with
+    Qz = 0."""
+    from paper_1710_04751_amd import workloads as W
+    nx, ny, nz = 8, 7, 6
+    p = oracle.cavity_params(nx, 2e3, u0=0.1, ny=ny, nz=nz, omega_bulk=1.0)
+    T0 = W.smooth_field((nz, ny, nx), 9, 0.4)
+    sz = (-1.0) ** np.arange(nz)
+    S = lambda T: p.gbeta * np.sum((T - p.T_ref) * sz[:, None, None])
+    amp = {}
+    for matched in (False, True):
+        zero = np.zeros((nz, ny, nx))
+        u = oracle.staggered_free(zero, zero, zero, T=T0 if matched else None, gbeta=p.gbeta,
+                                  T_ref=p.T_ref)
+        F, G = oracle.init_equilibrium(p, ux=u[0], uy=u[1], uz=u[2], T=T0)
+        q = oracle.staggered_momentum(F)[2]
+        d = []
+        for _ in range(6):
+            F, G, mac = oracle.run(p, 1, F, G)
+            q1 = oracle.staggered_momentum(F)[2]
+            s1 = S(mac[4])
+            assert abs(q1 + q - s1) < 1e-13
+            d.append(abs(q1 - 0.5 * s1))
+            q = q1
+        amp[matched] = max(d)
+    assert amp[True] < 0.01 * amp[False]
+
+
+def test_cavity_symmetrize_is_the_projection(oracle):
+    """Idempotent, leaves the oracle's own cavity solution unchanged (it has
+    the symmetries, see test_cavity_symmetries) and gives arbitrary fields
+    those symmetries."""
+    from paper_1710_04751_amd import workloads as W
+    shape = (9, 7, 10)
+    f = [W.smooth_field(shape, s, 1.0) for s in (1, 2, 3, 4)]
+    g = oracle.cavity_symmetrize(*f)
+    h = oracle.cavity_symmetrize(*g)
+    assert max(np.max(np.abs(a - b)) for a, b in zip(g, h)) < 1e-15
+    ux, uy, uz, T = g
+    assert np.max(np.abs(uy + uy[:, ::-1, :])) < 1e-15 and np.max(np.abs(T - T[:, ::-1, :])) < 1e-15
+    assert np.max(np.abs(ux + ux[::-1, :, ::-1])) < 1e-15 and np.max(np.abs(T + T[::-1, :, ::-1])) < 1e-15
+    p = oracle.cavity_params(10, 1e4, u0=0.1, ny=7, nz=9, omega_bulk=1.0)
+    F, G = oracle.rest_state(p)
+    _, _, mac = oracle.run(p, 150, F, G)
+    s = oracle.cavity_symmetrize(mac[1], mac[2], mac[3], mac[4])
+    for a, b in zip(s, mac[1:]):
+        assert np.max(np.abs(a - b)) < 1e-13
