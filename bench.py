@@ -247,6 +247,27 @@ def time_batched_steady(log=print):
             "threads": threads, "blocks_per_cu": bpc}
 
 
+def warm_start(log=print):
+    """The learned warm start at 64^3: steady training/test sets from the
+    batched solver, GPU training of the network, then every test cavity
+    solved from its prediction; steps to the steady rule warm vs cold."""
+    from paper_1710_04751_amd import warmstart as WS
+    r = WS.study(log=log)
+    keys = ("grid", "train", "test", "ra_range", "train_converged", "test_converged", "epochs",
+            "batch", "train_seconds", "train_tflops", "final_train_loss", "val_loss",
+            "cold_steps_median", "warm_steps_median", "cold_steps_mean", "warm_steps_mean",
+            "steps_ratio_median", "nu_rel_diff_max", "fallbacks", "cold_solve_s", "warm_solve_s")
+    out = {k: r[k] for k in keys}
+    out["workload"] = ("64^3 cavities, Ra log-uniform in [1e3, 4e4], 200 training (seed 17101) "
+                       "and 50 held-out (seed 17102) Rayleigh numbers, D3Q7, FP32 solver, "
+                       "stable rate set; network BF16/FP32-accumulate on the matrix cores")
+    out["unit"] = "steps to the steady rule"
+    log(f"warm start: median steps {out['warm_steps_median']:.0f} warm vs "
+        f"{out['cold_steps_median']:.0f} cold, max |dNu|/Nu {out['nu_rel_diff_max']:.1e}, "
+        f"training {out['train_tflops']:.1f} TFLOP/s")
+    return out
+
+
 def cpu_baseline(n_full, ra, seconds_hint=15.0, log=print):
     """The oracle on a bounded sample of the workload: a 64^3 block of cells
     with the 512^3 case's lattice parameters, a few steps, all host threads."""
@@ -286,6 +307,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=2000)
     ap.add_argument("--block", type=str, default=None, help="bx,by of the step kernel")
+    ap.add_argument("--warm-start", action="store_true",
+                    help="also run the learned warm-start study at 64^3 (about 4 minutes)")
     ap.add_argument("--batched-steady", action="store_true",
                     help="also run every cavity of the batch to steady state, batched and "
                          "sequentially (about 3 minutes)")
@@ -314,6 +337,7 @@ def main():
     batched = None if args.no_batched else time_batched(args.batched_steps, log=log)
     if batched is not None and args.batched_steady:
         batched["to_steady"] = time_batched_steady(log=log)
+    warm = warm_start(log=log) if args.warm_start else None
     cpu = None if args.no_cpu else cpu_baseline(args.n, args.Ra, log=log)
 
     rec = {
@@ -352,6 +376,7 @@ def main():
                          "traffic": recorded_traffic(args.n, "fp16")},
         },
         "batched": batched,
+        "warm_start": warm,
         "copy_probe": {"GBs": round(copy["GBs"], 1), "bytes": copy["bytes_per_launch_each_way"]},
         "cpu_baseline": cpu,
     }
