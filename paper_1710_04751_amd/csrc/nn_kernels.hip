@@ -145,122 +145,121 @@ struct WgradArgs {
     const __bf16* dy;
     const __bf16* y;
     float* dw;
-    int32_t n, lg, taps, c1, c1s, c2, cin, K, cout, ys, relu, cin_real;
+    float* db;
+    int32_t n, lg, taps, c1, c1s, c2, cin, K, cout, coutp, ys, relu, cin_real;
     int64_t vchunk;
 };
 
-// One block = one wave: output channels blockIdx.y * 16 + (0..15) x
-// (tap, channel) columns blockIdx.x * 64 + (0..63), voxels of chunk
-// blockIdx.z.
-__global__ void __launch_bounds__(64) k_wgrad(WgradArgs a) {
-    const int lane = threadIdx.x, r = lane & 15, q = lane >> 4;
+// Weight gradient, one block of 4 waves per (row tile, column tile, voxel
+// chunk): rows are RS * 16 output channels, columns CS * 16 (tap, channel)
+// pairs with RS * CS = 8, so each wave owns two 16 x 16 accumulators.  Per
+// 32 voxels the block loads the masked output gradient and the input patch
+// with 16-byte loads (8 channels of one voxel) and writes them transposed
+// into LDS ([channel][voxel]), where each fragment (8 consecutive voxels) is
+// one 16-byte read.  Blocks of the first column tile also sum the output
+// gradient into the bias gradient.
+template <int RS>
+__global__ void __launch_bounds__(256) k_wgrad(WgradArgs a) {
+    constexpr int CS = 8 / RS;
+    __shared__ __attribute__((aligned(16))) __bf16 dT[RS * 16][40];
+    __shared__ __attribute__((aligned(16))) __bf16 xT[CS * 16][40];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r = lane & 15, q = lane >> 4;
     const int lg = a.lg, G = 1 << lg;
     const int64_t V = (int64_t)1 << (3 * lg);
     const int64_t M = (int64_t)a.n * V;
-    const int co = blockIdx.y * 16 + r;
-    bool kok[4];
-    int kc[4], kdz[4], kdy[4], kdx[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int kcol = blockIdx.x * 64 + j * 16 + r;
-        kok[j] = kcol < a.K;
-        const int t = kok[j] ? kcol / a.cin : 0;
-        kc[j] = kok[j] ? kcol - t * a.cin : 0;
-        kdz[j] = a.taps == 27 ? t / 9 - 1 : 0;
-        kdy[j] = a.taps == 27 ? (t / 3) % 3 - 1 : 0;
-        kdx[j] = a.taps == 27 ? t % 3 - 1 : 0;
-    }
-    floatx4 acc[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    const int row0 = blockIdx.y * RS * 16, col0 = blockIdx.x * CS * 16;
+    const int wr = wave % RS, wc = 2 * (wave / RS);
+    floatx4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+    float bsum = 0.f;
     const int64_t v0 = (int64_t)blockIdx.z * a.vchunk;
     const int64_t v1 = std::min(M, v0 + a.vchunk);
     for (int64_t vb = v0; vb < v1; vb += 32) {
-        bf16x8 av;
-        int vs[8], vz[8], vy[8], vx[8];
-        bool vin[8];
+        // output gradient: RS*2 groups of 8 channels x 32 voxels
+        for (int t = tid; t < RS * 2 * 32; t += 256) {
+            const int g8 = t >> 5, vi = t & 31;
+            const int c0 = row0 + g8 * 8;
+            const int64_t vv = vb + vi;
+            bf16x8 d;
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const int64_t vv = vb + q * 8 + i;
-            vin[i] = vv < v1;
-            float d = 0.f;
-            if (vin[i] && co < a.cout) {
-                d = (float)a.dy[vv * a.ys + co];
-                if (a.relu && !((float)a.y[vv * a.ys + co] > 0.f)) d = 0.f;
+            for (int i = 0; i < 8; ++i) d[i] = (__bf16)0.f;
+            if (vv < v1 && c0 < a.ys) {
+                d = *(const bf16x8*)(a.dy + vv * a.ys + c0);
+                if (a.relu) {
+                    const bf16x8 m = *(const bf16x8*)(a.y + vv * a.ys + c0);
+#pragma unroll
+                    for (int i = 0; i < 8; ++i)
+                        if (!((float)m[i] > 0.f)) d[i] = (__bf16)0.f;
+                }
             }
-            av[i] = (__bf16)d;
-            const int64_t vc = vin[i] ? vv : 0;
-            vs[i] = (int)(vc >> (3 * lg));
-            const int rem = (int)(vc & (V - 1));
-            vz[i] = rem >> (2 * lg);
-            vy[i] = (rem >> lg) & (G - 1);
-            vx[i] = rem & (G - 1);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) dT[g8 * 8 + i][vi] = d[i];
         }
+        // input patches: CS*2 groups of 8 (tap, channel) columns x 32 voxels
+        for (int t = tid; t < CS * 2 * 32; t += 256) {
+            const int g8 = t >> 5, vi = t & 31;
+            const int k0 = col0 + g8 * 8;
+            const int64_t vv = vb + vi;
+            bf16x8 xv;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            bf16x8 bv;
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                __bf16 val = (__bf16)0.f;
-                const int zz = vz[i] + kdz[j], yy = vy[i] + kdy[j], xx = vx[i] + kdx[j];
-                if (vin[i] && kok[j] && (unsigned)zz < (unsigned)G && (unsigned)yy < (unsigned)G &&
-                    (unsigned)xx < (unsigned)G) {
-                    if (kc[j] < a.c1s) {
-                        const int64_t vi = ((int64_t)vs[i] << (3 * lg)) + ((int64_t)zz << (2 * lg)) +
-                                           ((int64_t)yy << lg) + xx;
-                        val = a.x1[vi * a.c1s + kc[j]];
+            for (int i = 0; i < 8; ++i) xv[i] = (__bf16)0.f;
+            if (vv < v1 && k0 < a.K) {
+                const int tap = k0 / a.cin, c = k0 - tap * a.cin;
+                const int s = (int)(vv >> (3 * lg));
+                const int rem = (int)(vv & (V - 1));
+                int z = rem >> (2 * lg), y = (rem >> lg) & (G - 1), x = rem & (G - 1);
+                if (a.taps == 27) {
+                    z += tap / 9 - 1;
+                    y += (tap / 3) % 3 - 1;
+                    x += tap % 3 - 1;
+                }
+                if ((unsigned)z < (unsigned)G && (unsigned)y < (unsigned)G &&
+                    (unsigned)x < (unsigned)G) {
+                    if (c < a.c1s) {
+                        const int64_t vi2 = ((int64_t)s << (3 * lg)) + ((int64_t)z << (2 * lg)) +
+                                            ((int64_t)y << lg) + x;
+                        xv = *(const bf16x8*)(a.x1 + vi2 * a.c1s + c);
                     } else {
                         const int h = lg - 1;
-                        const int64_t vi = ((int64_t)vs[i] << (3 * h)) +
-                                           ((int64_t)(zz >> 1) << (2 * h)) +
-                                           ((int64_t)(yy >> 1) << h) + (xx >> 1);
-                        val = a.x2[vi * a.c2 + (kc[j] - a.c1s)];
+                        const int64_t vi2 = ((int64_t)s << (3 * h)) +
+                                            ((int64_t)(z >> 1) << (2 * h)) +
+                                            ((int64_t)(y >> 1) << h) + (x >> 1);
+                        xv = *(const bf16x8*)(a.x2 + vi2 * a.c2 + (c - a.c1s));
                     }
                 }
-                bv[i] = val;
             }
-            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[j], 0, 0, 0);
-        }
-    }
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int kcol = blockIdx.x * 64 + j * 16 + r;
+            for (int i = 0; i < 8; ++i) xT[g8 * 8 + i][vi] = xv[i];
+        }
+        __syncthreads();
+        if (blockIdx.x == 0 && tid < RS * 16) {
+#pragma unroll 8
+            for (int i = 0; i < 32; ++i) bsum += (float)dT[tid][i];
+        }
+        const bf16x8 av = *(const bf16x8*)&dT[wr * 16 + r][q * 8];
+        const bf16x8 b0 = *(const bf16x8*)&xT[wc * 16 + r][q * 8];
+        const bf16x8 b1 = *(const bf16x8*)&xT[(wc + 1) * 16 + r][q * 8];
+        acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b0, acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b1, acc1, 0, 0, 0);
+        __syncthreads();
+    }
+    if (blockIdx.x == 0 && tid < RS * 16 && row0 + tid < a.cout) atomicAdd(&a.db[row0 + tid], bsum);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int kcol = col0 + (wc + j) * 16 + r;
         if (kcol >= a.K) continue;
         const int t = kcol / a.cin;
         const int cc = kcol - t * a.cin;
         if (cc < a.c1s && cc >= a.c1) continue;  // zero padding channels of x1
         const int ci = cc < a.c1s ? cc : a.c1 + (cc - a.c1s);
+        const floatx4 acc = j ? acc1 : acc0;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const int coo = blockIdx.y * 16 + q * 4 + i;
+            const int coo = row0 + wr * 16 + q * 4 + i;
             if (coo < a.cout)
-                atomicAdd(&a.dw[((int64_t)coo * a.taps + t) * a.cin_real + ci], acc[j][i]);
+                atomicAdd(&a.dw[((int64_t)coo * a.taps + t) * a.cin_real + ci], acc[i]);
         }
     }
-}
-
-// Bias gradient: 64 channels x 4 voxel lanes per block, over a voxel chunk.
-__global__ void __launch_bounds__(256) k_bias_grad(const __bf16* __restrict__ dy,
-                                                   const __bf16* __restrict__ y, int relu,
-                                                   int64_t M, int ys, int cout, int64_t vchunk,
-                                                   float* __restrict__ db) {
-    __shared__ float red[256];
-    const int co = blockIdx.y * 64 + (threadIdx.x & 63);
-    const int sub = threadIdx.x >> 6;
-    const int64_t v0 = (int64_t)blockIdx.x * vchunk;
-    const int64_t v1 = std::min(M, v0 + vchunk);
-    float acc = 0.f;
-    if (co < cout)
-        for (int64_t v = v0 + sub; v < v1; v += 4) {
-            float d = (float)dy[v * ys + co];
-            if (relu && !((float)y[v * ys + co] > 0.f)) d = 0.f;
-            acc += d;
-        }
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    if (sub == 0 && co < cout)
-        atomicAdd(&db[co], red[threadIdx.x] + red[threadIdx.x + 64] + red[threadIdx.x + 128] +
-                               red[threadIdx.x + 192]);
 }
 
 __global__ void k_pack_w(int coutp, int kpad, int cout, int K, int cin, int c1, int c1s, int taps,
@@ -601,6 +600,7 @@ hipError_t conv_backward_weight(const ConvGeom& g, const __bf16* x1, const __bf1
     a.dy = dy;
     a.y = y;
     a.dw = dw;
+    a.db = db;
     a.n = g.n;
     a.lg = g.lg;
     a.taps = g.taps;
@@ -610,20 +610,22 @@ hipError_t conv_backward_weight(const ConvGeom& g, const __bf16* x1, const __bf1
     a.cin = g.cin;
     a.K = g.K;
     a.cout = g.cout;
+    a.coutp = g.coutp;
     a.ys = g.ys;
     a.relu = relu;
     a.cin_real = g.c1 + g.c2;
-    const int kt = ceil_div(g.K, 64), ct = g.coutp / 16;
+    const int rs = g.coutp >= 64 ? 4 : g.coutp >= 32 ? 2 : 1;
+    const int cs = 8 / rs;
+    const int ct = ceil_div(g.coutp, 16 * rs), kt = ceil_div(g.K, 16 * cs);
     const int64_t steps = (M + 31) / 32;
-    const int64_t chunks = std::max<int64_t>(1, std::min<int64_t>(steps, 16384 / (kt * ct)));
+    const int64_t chunks = std::max<int64_t>(1, std::min<int64_t>(steps, 4096 / (kt * ct)));
     a.vchunk = (steps + chunks - 1) / chunks * 32;
-    const int nz = ceil_div(M, a.vchunk);
-    hipLaunchKernelGGL(k_wgrad, dim3(kt, ct, nz), dim3(64), 0, s, a);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    const int64_t bchunk = std::max<int64_t>(256, (M + 1023) / 1024);
-    hipLaunchKernelGGL(k_bias_grad, dim3(ceil_div(M, bchunk), ceil_div(g.cout, 64)), dim3(256), 0,
-                       s, dy, y, relu, M, g.ys, g.cout, bchunk, db);
+    const dim3 grid(kt, ct, ceil_div(M, a.vchunk));
+    switch (rs) {
+        case 4: hipLaunchKernelGGL(k_wgrad<4>, grid, dim3(256), 0, s, a); break;
+        case 2: hipLaunchKernelGGL(k_wgrad<2>, grid, dim3(256), 0, s, a); break;
+        default: hipLaunchKernelGGL(k_wgrad<1>, grid, dim3(256), 0, s, a); break;
+    }
     return hipGetLastError();
 }
 
