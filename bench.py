@@ -247,6 +247,85 @@ def time_batched_steady(log=print):
             "threads": threads, "blocks_per_cu": bpc}
 
 
+GOLDEN_128 = os.path.join(ROOT, "tests", "golden", "cavity128_ra1e6_d3q7_2500.npz")
+
+
+def block_planes(mac, planes):
+    """4x4x4 block means of 512^3 fields [5][512][512][512] taken at the
+    128^3 cell planes y = planes[0] and z = planes[1]: ([5][z][x], [5][y][x])."""
+    import torch
+    yb, zb = planes
+    a = mac[:, :, 4 * yb:4 * yb + 4, :].reshape(5, 128, 4, 4, 128, 4).mean(dim=(2, 3, 5))
+    b = mac[:, 4 * zb:4 * zb + 4, :, :].reshape(5, 4, 128, 4, 128, 4).mean(dim=(1, 3, 5))
+    return a, b
+
+
+def field_errors(a, b):
+    """Normalised max errors per field of [5][...] arrays (rho as rho - 1)."""
+    names = ("rho", "ux", "uy", "uz", "T")
+    out = {}
+    for i, k in enumerate(names):
+        ref = b[i] - 1.0 if k == "rho" else b[i]
+        out[k] = float((a[i] - b[i]).abs().max() / ref.abs().max())
+    return out
+
+
+def precision_study(steps=10_000, log=print):
+    """512^3, Ra 1e6, D3Q7 from rest for 10,000 steps with FP32 and with
+    FP16 storage (FP32 arithmetic), the stable rate set of the 128^3 FP64
+    oracle run at the same Ra, Pr, u0 and physical time (2,500 steps):
+    errors of the 4x4x4 block means against the oracle on the mid-planes,
+    and FP16 against FP32 over every cell."""
+    import numpy as np
+    import torch
+    from paper_1710_04751_amd import solver as S
+    from paper_1710_04751_amd import workloads as W
+
+    if not os.path.exists(GOLDEN_128):
+        log("precision study: 128^3 reference missing, skipped")
+        return None
+    ref = np.load(GOLDEN_128)
+    planes = (int(ref["plane_y"]), int(ref["plane_z"]))
+    ry = torch.from_numpy(ref["y64"].astype(np.float64)).cuda()
+    rz = torch.from_numpy(ref["z64"].astype(np.float64)).cuda()
+    out, full = {}, {}
+    for prec in ("fp32", "fp16"):
+        cav = S.Cavity(S.make_params(512, 1e6, precision=prec, **W.STABLE_RATES))
+        t0 = time.perf_counter()
+        done = 0
+        while done < steps:
+            k = min(2000, steps - done)
+            cav.step(k)
+            torch.cuda.synchronize()
+            done += k
+            log(f"precision study {prec}: {done}/{steps} steps")
+        secs = time.perf_counter() - t0
+        m = cav.macros(fp64=False)
+        mac = torch.stack([m[k] for k in ("rho", "ux", "uy", "uz", "T")])
+        del m
+        cav.close()
+        del cav
+        torch.cuda.empty_cache()
+        a, b = block_planes(mac, planes)
+        e_y, e_z = field_errors(a.double(), ry), field_errors(b.double(), rz)
+        out[prec] = {"vs_oracle128": {k: max(e_y[k], e_z[k]) for k in e_y},
+                     "seconds": round(secs, 2), "steps": steps}
+        full[prec] = mac
+        log(f"precision study {prec}: vs 128^3 oracle {out[prec]['vs_oracle128']}")
+    d = {}
+    for i, k in enumerate(("rho", "ux", "uy", "uz", "T")):
+        ref32 = full["fp32"][i] - 1.0 if k == "rho" else full["fp32"][i]
+        d[k] = float((full["fp16"][i] - full["fp32"][i]).abs().max() / ref32.abs().max())
+    out["fp16_vs_fp32"] = d
+    log(f"precision study: fp16 vs fp32 over all cells {d}")
+    out["workload"] = ("512^3, Ra 1e6, D3Q7, from rest, 10,000 steps, stable rate set; reference "
+                       "128^3 FP64 oracle, 2,500 steps (same t u0 / L), mid-planes y = 64, z = 64 "
+                       "of the 128^3 grid against 4x4x4 block means")
+    del full
+    torch.cuda.empty_cache()
+    return out
+
+
 def warm_start(log=print):
     """The learned warm start at 64^3: steady training/test sets from the
     batched solver, GPU training of the network, then every test cavity
@@ -307,6 +386,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=2000)
     ap.add_argument("--block", type=str, default=None, help="bx,by of the step kernel")
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the 512^3 FP32/FP16 comparison with the 128^3 oracle reference")
     ap.add_argument("--warm-start", action="store_true",
                     help="also run the learned warm-start study at 64^3 (about 4 minutes)")
     ap.add_argument("--batched-steady", action="store_true",
@@ -337,6 +418,7 @@ def main():
     batched = None if args.no_batched else time_batched(args.batched_steps, log=log)
     if batched is not None and args.batched_steady:
         batched["to_steady"] = time_batched_steady(log=log)
+    precision = None if args.no_precision else precision_study(log=log)
     warm = warm_start(log=log) if args.warm_start else None
     cpu = None if args.no_cpu else cpu_baseline(args.n, args.Ra, log=log)
 
@@ -376,6 +458,7 @@ def main():
                          "traffic": recorded_traffic(args.n, "fp16")},
         },
         "batched": batched,
+        "precision_vs_oracle": precision,
         "warm_start": warm,
         "copy_probe": {"GBs": round(copy["GBs"], 1), "bytes": copy["bytes_per_launch_each_way"]},
         "cpu_baseline": cpu,
