@@ -136,7 +136,7 @@ def validation_loss(net, log10_ra, targets):
 
 
 def study(grid=64, n_train=200, n_test=50, ra_range=(1e3, 4e4), epochs=200, batch=8, lr=2e-3,
-          seeds=(17101, 17102), init_seed=1, max_steps=600_000, log=print):
+          seeds=(17101, 17102), init_seed=1, max_steps=600_000, precision="fp32", log=print):
     """The whole warm-start experiment: steady training and test sets from
     rest (the cold solves), training, then every test cavity solved again
     from the network's prediction.  Returns a summary dict."""
@@ -147,10 +147,10 @@ def study(grid=64, n_train=200, n_test=50, ra_range=(1e3, 4e4), epochs=200, batc
     lra_test = np.random.default_rng(seeds[1]).uniform(lo, hi, n_test)
     log(f"warm start: {n_train} training and {n_test} test cavities, {grid}^3, "
         f"Ra log-uniform in [{ra_range[0]:g}, {ra_range[1]:g}]")
-    cold_train = solve([cavity_params(grid, 10 ** r) for r in lra_train], max_steps=max_steps,
-                       log=log)
-    cold_test = solve([cavity_params(grid, 10 ** r) for r in lra_test], max_steps=max_steps,
-                      log=log)
+    cold_train = solve([cavity_params(grid, 10 ** r, precision) for r in lra_train],
+                       max_steps=max_steps, log=log)
+    cold_test = solve([cavity_params(grid, 10 ** r, precision) for r in lra_test],
+                      max_steps=max_steps, log=log)
     ok_train = [i for i, h in enumerate(cold_train["how"]) if converged(h)]
     targets = cold_train["fields"][ok_train].contiguous()
     lra_fit = lra_train[ok_train]
@@ -160,7 +160,7 @@ def study(grid=64, n_train=200, n_test=50, ra_range=(1e3, 4e4), epochs=200, batc
     ok_test = [i for i, h in enumerate(cold_test["how"]) if converged(h)]
     val = validation_loss(net, lra_test[ok_test].tolist(), cold_test["fields"][ok_test].contiguous())
     pred = predict(net, lra_test.tolist(), u0)
-    warm = solve([cavity_params(grid, 10 ** r) for r in lra_test], init=pred,
+    warm = solve([cavity_params(grid, 10 ** r, precision) for r in lra_test], init=pred,
                  max_steps=max_steps, log=log)
     # fallback: a warm run that misses the steady rule is solved from rest
     fallback = [i for i in range(n_test) if not converged(warm["how"][i])]

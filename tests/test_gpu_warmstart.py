@@ -1,7 +1,18 @@
 """The learned warm start end to end at a small size: steady 32^3 cavities
-from the batched solver train the network on the GPU; held-out Rayleigh
-numbers started from its prediction reach the steady rule in fewer steps
-than from rest, at the same steady Nusselt number (within 0.5%)."""
+from the batched solver (FP32, the steady rule of the benchmark) train the
+network on the GPU; held-out Rayleigh numbers started from its prediction
+reach the steady rule in fewer steps than from rest, at the same steady
+Nusselt number (within 0.5%).
+
+Range: Ra in [1e3, 8e3].  On the 32^3 grid the symmetric steady state stops
+being an attractor from Ra ~ 1e4 (the staggered and antisymmetric modes of
+the discrete model grow), and warm starts there can leave it.  The gain at
+this size is modest (medians of the per-cavity step ratio 0.77-0.85 in
+repeated runs; training is not bitwise repeatable because the weight
+gradient sums with atomics), since a start whose error is ~1e-2 of the field
+saves about two of the eight decades the residual falls from rest; the bar
+is a median ratio below 0.95 over 24 held-out cavities.  The 64^3 study of
+the benchmark is the full-size measurement."""
 import pytest
 
 from gpu_helpers import log
@@ -16,7 +27,7 @@ def result():
         pytest.skip("no GPU")
     from paper_1710_04751_amd import warmstart
     log("case: warm start study 32^3")
-    r = warmstart.study(grid=32, n_train=24, n_test=6, ra_range=(1e3, 2e4), epochs=300, batch=8,
+    r = warmstart.study(grid=32, n_train=48, n_test=24, ra_range=(1e3, 8e3), epochs=500, batch=8,
                         lr=2e-3, max_steps=300_000, log=log)
     for row in r["rows"]:
         log(row)
@@ -25,13 +36,12 @@ def result():
 
 
 def test_every_cavity_reaches_the_steady_rule(result):
-    assert result["train_converged"] == 24 and result["test_converged"] == 6
+    assert result["train_converged"] == 48 and result["test_converged"] == 24
     assert result["fallbacks"] == 0
 
 
 def test_warm_start_cuts_steps(result):
-    assert result["warm_steps_mean"] < result["cold_steps_mean"]
-    assert result["steps_ratio_median"] < 1.0
+    assert result["steps_ratio_median"] < 0.95
 
 
 def test_nusselt_number_is_unchanged(result):
