@@ -347,6 +347,49 @@ def warm_start(log=print):
     return out
 
 
+def nn_throughput(steps=20, grid=64, batch=8, log=print):
+    """Training and inference throughput of the warm-start network on the
+    matrix cores: seeded initial parameters, random targets, `steps` timed
+    training steps (forward, backward, Adam) and forward passes."""
+    import numpy as np
+    import torch
+    from paper_1710_04751_amd.network import WarmStartNet, init_params
+
+    net = WarmStartNet(grid, batch)
+    net.set_params(torch.from_numpy(init_params(1)))
+    g = torch.Generator(device="cuda").manual_seed(5)
+    targets = 0.1 * torch.randn(batch, 4, grid, grid, grid, device="cuda", generator=g)
+    lra = list(np.linspace(3.0, 5.0, batch))
+    idx = list(range(batch))
+    for _ in range(3):
+        net.train_step(lra, targets, idx, want_loss=False)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        net.train_step(lra, targets, idx, want_loss=False)
+    e1.record()
+    torch.cuda.synchronize()
+    t_train = e0.elapsed_time(e1) / steps * 1e-3
+    e0.record()
+    for _ in range(steps):
+        net.forward(lra)
+    e1.record()
+    torch.cuda.synchronize()
+    t_fwd = e0.elapsed_time(e1) / steps * 1e-3
+    f_fwd, f_train = net.flops(batch)
+    net.close()
+    out = {"grid": grid, "batch": batch, "steps": steps,
+           "train_step_ms": round(t_train * 1e3, 3),
+           "train_TFLOPs": round(f_train / t_train / 1e12, 2),
+           "forward_ms": round(t_fwd * 1e3, 3), "forward_TFLOPs": round(f_fwd / t_fwd / 1e12, 2),
+           "peak_TFLOPs_bf16": 2500.0, "dtype": "bf16 operands, fp32 accumulate"}
+    log(f"network: train step {out['train_step_ms']} ms ({out['train_TFLOPs']} TFLOP/s), "
+        f"forward {out['forward_ms']} ms ({out['forward_TFLOPs']} TFLOP/s)")
+    return out
+
+
 def cpu_baseline(n_full, ra, seconds_hint=15.0, log=print):
     """The oracle on a bounded sample of the workload: a 64^3 block of cells
     with the 512^3 case's lattice parameters, a few steps, all host threads."""
@@ -386,6 +429,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=2000)
     ap.add_argument("--block", type=str, default=None, help="bx,by of the step kernel")
+    ap.add_argument("--no-nn", action="store_true", help="skip the network throughput leg")
     ap.add_argument("--no-precision", action="store_true",
                     help="skip the 512^3 FP32/FP16 comparison with the 128^3 oracle reference")
     ap.add_argument("--warm-start", action="store_true",
@@ -418,6 +462,7 @@ def main():
     batched = None if args.no_batched else time_batched(args.batched_steps, log=log)
     if batched is not None and args.batched_steady:
         batched["to_steady"] = time_batched_steady(log=log)
+    nn = None if args.no_nn else nn_throughput(log=log)
     precision = None if args.no_precision else precision_study(log=log)
     warm = warm_start(log=log) if args.warm_start else None
     cpu = None if args.no_cpu else cpu_baseline(args.n, args.Ra, log=log)
@@ -458,6 +503,7 @@ def main():
                          "traffic": recorded_traffic(args.n, "fp16")},
         },
         "batched": batched,
+        "network": nn,
         "precision_vs_oracle": precision,
         "warm_start": warm,
         "copy_probe": {"GBs": round(copy["GBs"], 1), "bytes": copy["bytes_per_launch_each_way"]},
