@@ -411,9 +411,19 @@ def cpu_baseline(n_full, ra, seconds_hint=15.0, log=print):
     dt = time.perf_counter() - t0
     mlups = side ** 3 * steps / dt / 1e6
     log(f"cpu oracle: {side}^3 x {steps} steps in {dt:.1f}s on {used} threads -> {mlups:.3f} MLUPS")
+    # the same on one core (2 steps)
+    O.set_threads(1)
+    t1 = time.perf_counter()
+    F, G, _ = O.run(p, 2, F, G)
+    d1 = time.perf_counter() - t1
+    O.set_threads(threads)
+    single = side ** 3 * 2 / d1 / 1e6
+    log(f"cpu oracle, one core: {single:.3f} MLUPS")
     return {"value": mlups, "unit": "MLUPS", "cores": used, "kind": "oracle",
+            "single_core_MLUPS": round(single, 4),
             "sample": f"{side}^3 cells with the {n_full}^3 Ra={ra:g} lattice parameters, "
-                      f"{steps} steps from rest ({dt:.1f} s), FP64 oracle"}
+                      f"{steps} steps from rest ({dt:.1f} s) on {used} threads, then 2 steps on "
+                      f"one core ({d1:.1f} s), FP64 oracle"}
 
 
 def main():
