@@ -50,93 +50,106 @@ struct ConvArgs {
     int32_t n, lg, taps, c1s, c2, cin, K, kpad, cout, ys, relu;
 };
 
-// One block = one wave: 16 voxels x (NSUB * 16) output channels, channel
-// group blockIdx.y.
-template <int NSUB, int MODE>
+// One block = one wave: MT * 16 voxels x (NSUB * 16) output channels,
+// channel group blockIdx.y.  Each weight fragment is loaded once and used
+// for the MT voxel tiles.
+template <int NSUB, int MODE, int MT>
 __global__ void __launch_bounds__(64) k_conv(ConvArgs a) {
     const int lane = threadIdx.x, r = lane & 15, q = lane >> 4;
     const int lg = a.lg, G = 1 << lg;
     const int64_t V = (int64_t)1 << (3 * lg);
     const int64_t M = (int64_t)a.n * V;
-    const int64_t vb = (int64_t)blockIdx.x * 16;
+    const int64_t vb = (int64_t)blockIdx.x * (16 * MT);
     const int cobase = blockIdx.y * NSUB * 16;
-    const int64_t v = vb + r;
-    const bool vok = v < M;
-    int s = 0, z = 0, y = 0, x = 0;
-    if (vok) {
-        s = (int)(v >> (3 * lg));
-        const int rem = (int)(v & (V - 1));
-        z = rem >> (2 * lg);
-        y = (rem >> lg) & (G - 1);
-        x = rem & (G - 1);
-    }
-    floatx4 acc[NSUB];
+    bool vok[MT];
+    int vs[MT], vz[MT], vy[MT], vx[MT];
 #pragma unroll
-    for (int j = 0; j < NSUB; ++j) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int m = 0; m < MT; ++m) {
+        const int64_t v = vb + m * 16 + r;
+        vok[m] = v < M;
+        const int64_t vc = vok[m] ? v : 0;
+        vs[m] = (int)(vc >> (3 * lg));
+        const int rem = (int)(vc & (V - 1));
+        vz[m] = rem >> (2 * lg);
+        vy[m] = (rem >> lg) & (G - 1);
+        vx[m] = rem & (G - 1);
+    }
+    floatx4 acc[MT][NSUB];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int j = 0; j < NSUB; ++j) acc[m][j] = floatx4{0.f, 0.f, 0.f, 0.f};
     int tap = 0, c = q * 8;
     while (c >= a.cin) c -= a.cin, ++tap;
     for (int k0 = q * 8; k0 < a.kpad; k0 += 32) {
-        bf16x8 av;
+        int dz = 0, dy = 0, dx = 0;
+        if (a.taps == 27) {
+            dz = tap / 9 - 1;
+            dy = (tap / 3) % 3 - 1;
+            dx = tap % 3 - 1;
+        }
+        bf16x8 av[MT];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) av[i] = (__bf16)0.f;
-        if (vok && k0 < a.K) {
-            int zz = z, yy = y, xx = x;
-            if (a.taps == 27) {
-                zz += tap / 9 - 1;
-                yy += (tap / 3) % 3 - 1;
-                xx += tap % 3 - 1;
-            }
-            if ((unsigned)zz < (unsigned)G && (unsigned)yy < (unsigned)G &&
+        for (int m = 0; m < MT; ++m) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) av[m][i] = (__bf16)0.f;
+            const int zz = vz[m] + dz, yy = vy[m] + dy, xx = vx[m] + dx;
+            if (vok[m] && k0 < a.K && (unsigned)zz < (unsigned)G && (unsigned)yy < (unsigned)G &&
                 (unsigned)xx < (unsigned)G) {
                 if (c < a.c1s) {
-                    const int64_t vi = ((int64_t)s << (3 * lg)) + ((int64_t)zz << (2 * lg)) +
+                    const int64_t vi = ((int64_t)vs[m] << (3 * lg)) + ((int64_t)zz << (2 * lg)) +
                                        ((int64_t)yy << lg) + xx;
-                    av = *(const bf16x8*)(a.x1 + vi * a.c1s + c);
+                    av[m] = *(const bf16x8*)(a.x1 + vi * a.c1s + c);
                     if (a.mask) {
                         const bf16x8 mk = *(const bf16x8*)(a.mask + vi * a.c1s + c);
 #pragma unroll
                         for (int i = 0; i < 8; ++i)
-                            if (!((float)mk[i] > 0.f)) av[i] = (__bf16)0.f;
+                            if (!((float)mk[i] > 0.f)) av[m][i] = (__bf16)0.f;
                     }
                 } else {
                     const int h = lg - 1;
-                    const int64_t vi = ((int64_t)s << (3 * h)) + ((int64_t)(zz >> 1) << (2 * h)) +
+                    const int64_t vi = ((int64_t)vs[m] << (3 * h)) +
+                                       ((int64_t)(zz >> 1) << (2 * h)) +
                                        ((int64_t)(yy >> 1) << h) + (xx >> 1);
-                    av = *(const bf16x8*)(a.x2 + vi * a.c2 + (c - a.c1s));
+                    av[m] = *(const bf16x8*)(a.x2 + vi * a.c2 + (c - a.c1s));
                 }
             }
         }
 #pragma unroll
         for (int j = 0; j < NSUB; ++j) {
             const bf16x8 bv = *(const bf16x8*)(a.w + (int64_t)(cobase + j * 16 + r) * a.kpad + k0);
-            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[j], 0, 0, 0);
+#pragma unroll
+            for (int m = 0; m < MT; ++m)
+                acc[m][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[m], bv, acc[m][j], 0, 0, 0);
         }
         c += 32;
         while (c >= a.cin) c -= a.cin, ++tap;
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int64_t vo = vb + q * 4 + i;
-        if (vo >= M) continue;
+    for (int m = 0; m < MT; ++m)
 #pragma unroll
-        for (int j = 0; j < NSUB; ++j) {
-            const int co = cobase + j * 16 + r;
-            if (MODE == 0) {
-                if (co < a.ys) {
-                    float val = 0.f;
-                    if (co < a.cout) {
-                        val = acc[j][i] + (a.bias ? a.bias[co] : 0.f);
-                        if (a.relu) val = fmaxf(val, 0.f);
+        for (int i = 0; i < 4; ++i) {
+            const int64_t vo = vb + m * 16 + q * 4 + i;
+            if (vo >= M) continue;
+#pragma unroll
+            for (int j = 0; j < NSUB; ++j) {
+                const int co = cobase + j * 16 + r;
+                if (MODE == 0) {
+                    if (co < a.ys) {
+                        float val = 0.f;
+                        if (co < a.cout) {
+                            val = acc[m][j][i] + (a.bias ? a.bias[co] : 0.f);
+                            if (a.relu) val = fmaxf(val, 0.f);
+                        }
+                        ((__bf16*)a.out)[vo * a.ys + co] = (__bf16)val;
                     }
-                    ((__bf16*)a.out)[vo * a.ys + co] = (__bf16)val;
+                } else if (co < a.cout) {
+                    const float val = acc[m][j][i] + (a.bias ? a.bias[co] : 0.f);
+                    const int64_t sidx = vo >> (3 * lg), vin = vo & (V - 1);
+                    ((float*)a.out)[(sidx * a.cout + co) * V + vin] = val * a.scale[co];
                 }
-            } else if (co < a.cout) {
-                const float val = acc[j][i] + (a.bias ? a.bias[co] : 0.f);
-                const int64_t sidx = vo >> (3 * lg), vin = vo & (V - 1);
-                ((float*)a.out)[(sidx * a.cout + co) * V + vin] = val * a.scale[co];
             }
         }
-    }
 }
 
 struct WgradArgs {
@@ -485,19 +498,31 @@ __global__ void k_cf_to_cl(const float* __restrict__ x, int n, int64_t V, int c,
     y[i] = x[(s * c + ch) * V + v];
 }
 
+template <int MODE, int MT>
+hipError_t launch_conv_mt(const ConvArgs& a, int coutp, hipStream_t s) {
+    const int64_t M = (int64_t)a.n << (3 * a.lg);
+    const int sub = coutp / 16;
+    const int nsub = sub % 4 == 0 ? 4 : sub % 3 == 0 ? 3 : sub % 2 == 0 ? 2 : 1;
+    const dim3 grid(ceil_div(M, 16 * MT), sub / nsub);
+    switch (nsub) {
+        case 4: hipLaunchKernelGGL((k_conv<4, MODE, MT>), grid, dim3(64), 0, s, a); break;
+        case 3: hipLaunchKernelGGL((k_conv<3, MODE, MT>), grid, dim3(64), 0, s, a); break;
+        case 2: hipLaunchKernelGGL((k_conv<2, MODE, MT>), grid, dim3(64), 0, s, a); break;
+        default: hipLaunchKernelGGL((k_conv<1, MODE, MT>), grid, dim3(64), 0, s, a); break;
+    }
+    return hipGetLastError();
+}
+
+// Four voxel tiles per wave when that still leaves at least 2048 waves (so
+// each weight fragment serves 64 voxels), one otherwise (small grids).
 template <int MODE>
 hipError_t launch_conv(const ConvArgs& a, int coutp, hipStream_t s) {
     const int64_t M = (int64_t)a.n << (3 * a.lg);
     const int sub = coutp / 16;
     const int nsub = sub % 4 == 0 ? 4 : sub % 3 == 0 ? 3 : sub % 2 == 0 ? 2 : 1;
-    const dim3 grid(ceil_div(M, 16), sub / nsub);
-    switch (nsub) {
-        case 4: hipLaunchKernelGGL((k_conv<4, MODE>), grid, dim3(64), 0, s, a); break;
-        case 3: hipLaunchKernelGGL((k_conv<3, MODE>), grid, dim3(64), 0, s, a); break;
-        case 2: hipLaunchKernelGGL((k_conv<2, MODE>), grid, dim3(64), 0, s, a); break;
-        default: hipLaunchKernelGGL((k_conv<1, MODE>), grid, dim3(64), 0, s, a); break;
-    }
-    return hipGetLastError();
+    const int64_t waves4 = (int64_t)ceil_div(M, 64) * (sub / nsub);
+    return waves4 >= 2048 ? launch_conv_mt<MODE, 4>(a, coutp, s)
+                          : launch_conv_mt<MODE, 1>(a, coutp, s);
 }
 
 }  // namespace
