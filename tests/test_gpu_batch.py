@@ -138,3 +138,22 @@ def test_member_misuse_is_refused(solver):
         capi.lbm_init_rest(h)
     assert e.value.status == capi.LBM_ERR_STATE
     batch.close()
+
+
+def test_largest_batch(solver):
+    """255 members (the limit) of small uneven boxes in one launch; a sample
+    of members equals its single-cavity run bit for bit."""
+    import numpy as np
+    log("case: batch of 255 members")
+    rng = np.random.default_rng(255)
+    sizes = [tuple(int(v) for v in rng.integers(4, 12, 3)) for _ in range(255)]
+    ras = [float(10 ** rng.uniform(3, 4)) for _ in range(255)]
+    params = _members(solver, "fp32", 7, sizes, ras)
+    batch = solver.Batch(params)
+    batch.step(60)
+    for i in (0, 17, 128, 254):
+        cav = solver.Cavity(params[i])
+        cav.step(60)
+        assert torch.equal(cav.populations()[0], batch.members[i].populations()[0]), i
+        cav.close()
+    batch.close()

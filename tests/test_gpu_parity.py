@@ -196,3 +196,38 @@ def test_full_size_sampled_one_step(solver, oracle, prec):
     cav.close()
     del cav
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("shape,qt", [((4, 4, 4), 7), ((4, 5, 6), 15), ((5, 4, 4), 7),
+                                      ((6, 4, 5), 15)])
+def test_minimal_grids(solver, oracle, shape, qt):
+    """The smallest boxes the library accepts (4 cells on an axis): every
+    cell is a wall cell on some axis; FP64 against the oracle over 300
+    steps."""
+    nx, ny, nz = shape
+    log(f"case: minimal grid {shape} q{qt} fp64")
+    p = oracle.cavity_params(nx, 2e3, u0=0.1, qt=qt, ny=ny, nz=nz, omega_bulk=1.0,
+                             fourth_maxwell=1)
+    F, G = oracle.rest_state(p)
+    F, G, mac = oracle.run(p, 300, F, G)
+    cav = solver.Cavity(solver.make_params(nx=nx, ny=ny, nz=nz, Ra=2e3, u0=0.1, precision="fp64",
+                                           thermal_q=qt, omega_bulk=1.0, fourth_maxwell=1))
+    cav.step(300)
+    Fg, Gg = (to_np(t) for t in cav.populations())
+    assert np.max(np.abs(Fg - F)) < 1e-13 and np.max(np.abs(Gg - G)) < 1e-13
+    cav.close()
+
+
+def test_zero_steps_and_smallest_box_limit(solver):
+    """lbm_step(0) leaves the state and the step count alone; a box with an
+    axis of 3 cells is refused before any device work."""
+    from paper_1710_04751_amd import capi
+    cav = solver.Cavity(solver.make_params(8, 1e3, precision="fp32"))
+    cav.step(10)
+    F0, G0 = cav.populations()
+    cav.step(0)
+    F1, G1 = cav.populations()
+    assert cav.steps_done() == 10 and torch.equal(F0, F1) and torch.equal(G0, G1)
+    cav.close()
+    with pytest.raises(capi.LbmError):
+        solver.Cavity(solver.make_params(nx=3, ny=8, nz=8, Ra=1e3))
