@@ -454,7 +454,7 @@ def main():
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "
-              "z-slab decomposition is a design, not part of this build.", file=sys.stderr)
+              "z-slab decomposition is described in the design notes, not implemented.", file=sys.stderr)
         sys.exit(2)
     import torch
     if not torch.cuda.is_available():
