@@ -43,10 +43,13 @@ hipError_t conv_forward(const ConvGeom& g, const __bf16* x1, const __bf16* x2,
                         const __bf16* mask, const __bf16* wp, const float* bias, int relu,
                         int mode, void* out, const float* scale4, hipStream_t s);
 
-// Input gradient: dx[n][v][cin] = sum over taps and co of dpre at the
-// neighbour times the weight, with dpre = dy * (y > 0) (relu) or dy.
-hipError_t conv_backward_data(const ConvGeom& g, const __bf16* dy, const __bf16* y, int relu,
-                              const __bf16* wt, __bf16* dx, hipStream_t s);
+// Input gradient: dx[n][v][cin] = sum over taps and co of dy at the
+// neighbour times the weight.  dy is the gradient of the pre-activation
+// (already masked by the ReLU).  When dxmask is given (the ReLU output of
+// the layer that produced x), dx is written as 0 where dxmask <= 0, so the
+// result is again a pre-activation gradient.
+hipError_t conv_backward_data(const ConvGeom& g, const __bf16* dy, const __bf16* wt,
+                              const __bf16* dxmask, __bf16* dx, hipStream_t s);
 
 // Weight and bias gradients, accumulated (atomic adds) into the master
 // layout: dw[co][tap][ci] += sum_v dpre[v][co] x(v + tap)[ci], db[co] +=
@@ -58,12 +61,14 @@ hipError_t conv_backward_weight(const ConvGeom& g, const __bf16* x1, const __bf1
 // Average pooling of 2x2x2 blocks: x on grid 2^lg, y on 2^(lg-1), c channels.
 hipError_t pool_forward(int n, int lg, int c, const __bf16* x, __bf16* y, hipStream_t s);
 // dx (grid 2^lg) = dy_coarse(parent) / 8 + skip[v][0..c) (skip has ctot
-// channels per cell; NULL adds nothing).
+// channels per cell; NULL adds nothing), set to 0 where ymask <= 0 (ymask:
+// [v][c], may be NULL).
 hipError_t pool_backward_add(int n, int lg, int c, const __bf16* dy, const __bf16* skip, int ctot,
-                             __bf16* dx, hipStream_t s);
-// dlow (grid 2^(lg-1)) = sum over the 8 children of dcat[child][coff..coff+c).
+                             const __bf16* ymask, __bf16* dx, hipStream_t s);
+// dlow (grid 2^(lg-1)) = sum over the 8 children of dcat[child][coff..coff+c),
+// set to 0 where ymask <= 0 (ymask: [v][c] on the coarse grid, may be NULL).
 hipError_t upsample_backward(int n, int lg, int c, const __bf16* dcat, int ctot, int coff,
-                             __bf16* dlow, hipStream_t s);
+                             const __bf16* ymask, __bf16* dlow, hipStream_t s);
 
 // Network input [n][v][8] (BF16): (log10 Ra - 4)/2, x, y, z, 0, 0, 0, 0;
 // log10_ra is a host array of n <= kMaxBatch values (passed by value).

@@ -46,16 +46,20 @@ struct ConvArgs {
     const __bf16* w;
     const float* bias;
     void* out;
+    const __bf16* omask;  // MODE 0: outputs where omask <= 0 are written as 0
     float scale[4];
     int32_t n, lg, taps, c1s, c2, cin, K, kpad, cout, ys, relu;
 };
 
-// One block = one wave: MT * 16 voxels x (NSUB * 16) output channels,
-// channel group blockIdx.y.  Each weight fragment is loaded once and used
-// for the MT voxel tiles.
-template <int NSUB, int MODE, int MT>
-__global__ void __launch_bounds__(64) k_conv(ConvArgs a) {
-    const int lane = threadIdx.x, r = lane & 15, q = lane >> 4;
+// One block: MT * 16 voxels x (NSUB * 16) output channels, channel group
+// blockIdx.y.  Each weight fragment is loaded once and used for the MT
+// voxel tiles.  The KS waves of a block split the k range (wave w takes
+// every KS-th step of 32 from step w) and add their partial sums through
+// LDS; this keeps enough waves in flight on the coarse grids.
+template <int NSUB, int MODE, int MT, int KS>
+__global__ void __launch_bounds__(64 * KS) k_conv(ConvArgs a) {
+    const int lane = threadIdx.x & 63, r = lane & 15, q = lane >> 4;
+    const int wave = threadIdx.x >> 6;
     const int lg = a.lg, G = 1 << lg;
     const int64_t V = (int64_t)1 << (3 * lg);
     const int64_t M = (int64_t)a.n * V;
@@ -79,9 +83,9 @@ __global__ void __launch_bounds__(64) k_conv(ConvArgs a) {
     for (int m = 0; m < MT; ++m)
 #pragma unroll
         for (int j = 0; j < NSUB; ++j) acc[m][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-    int tap = 0, c = q * 8;
-    while (c >= a.cin) c -= a.cin, ++tap;
-    for (int k0 = q * 8; k0 < a.kpad; k0 += 32) {
+    const int kfirst = q * 8 + 32 * wave;
+    int tap = kfirst / a.cin, c = kfirst - tap * a.cin;
+    for (int k0 = kfirst; k0 < a.kpad; k0 += 32 * KS) {
         int dz = 0, dy = 0, dx = 0;
         if (a.taps == 27) {
             dz = tap / 9 - 1;
@@ -122,8 +126,25 @@ __global__ void __launch_bounds__(64) k_conv(ConvArgs a) {
             for (int m = 0; m < MT; ++m)
                 acc[m][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[m], bv, acc[m][j], 0, 0, 0);
         }
-        c += 32;
+        c += 32 * KS;
         while (c >= a.cin) c -= a.cin, ++tap;
+    }
+    if constexpr (KS > 1) {
+        __shared__ floatx4 part[KS - 1][MT * NSUB][64];
+        if (wave > 0) {
+#pragma unroll
+            for (int m = 0; m < MT; ++m)
+#pragma unroll
+                for (int j = 0; j < NSUB; ++j) part[wave - 1][m * NSUB + j][lane] = acc[m][j];
+        }
+        __syncthreads();
+        if (wave > 0) return;
+#pragma unroll
+        for (int w = 0; w < KS - 1; ++w)
+#pragma unroll
+            for (int m = 0; m < MT; ++m)
+#pragma unroll
+                for (int j = 0; j < NSUB; ++j) acc[m][j] += part[w][m * NSUB + j][lane];
     }
 #pragma unroll
     for (int m = 0; m < MT; ++m)
@@ -140,6 +161,7 @@ __global__ void __launch_bounds__(64) k_conv(ConvArgs a) {
                         if (co < a.cout) {
                             val = acc[m][j][i] + (a.bias ? a.bias[co] : 0.f);
                             if (a.relu) val = fmaxf(val, 0.f);
+                            if (a.omask && !((float)a.omask[vo * a.ys + co] > 0.f)) val = 0.f;
                         }
                         ((__bf16*)a.out)[vo * a.ys + co] = (__bf16)val;
                     }
@@ -342,7 +364,8 @@ __global__ void k_pool(int n, int lg, int c, const __bf16* __restrict__ x, __bf1
 
 // thread per (fine cell, group of 8 channels)
 __global__ void k_pool_bwd_add(int n, int lg, int c, const __bf16* __restrict__ dy,
-                               const __bf16* __restrict__ skip, int ctot, __bf16* __restrict__ dx) {
+                               const __bf16* __restrict__ skip, int ctot,
+                               const __bf16* __restrict__ ymask, __bf16* __restrict__ dx) {
     const int h = lg - 1, cg = c / 8, G = 1 << lg;
     const int64_t V = (int64_t)1 << (3 * lg);
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -364,12 +387,18 @@ __global__ void k_pool_bwd_add(int n, int lg, int c, const __bf16* __restrict__ 
 #pragma unroll
         for (int i = 0; i < 8; ++i) o[i] = (__bf16)((float)p[i] * 0.125f);
     }
+    if (ymask) {
+        const bf16x8 mk = *(const bf16x8*)(ymask + v * c + g * 8);
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+            if (!((float)mk[i] > 0.f)) o[i] = (__bf16)0.f;
+    }
     *(bf16x8*)(dx + v * c + g * 8) = o;
 }
 
 // thread per (coarse cell, group of 8 channels)
 __global__ void k_up_bwd(int n, int lg, int c, const __bf16* __restrict__ dcat, int ctot, int coff,
-                         __bf16* __restrict__ dlow) {
+                         const __bf16* __restrict__ ymask, __bf16* __restrict__ dlow) {
     const int h = lg - 1, cg = c / 8;
     const int64_t Vc = (int64_t)1 << (3 * h);
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -391,6 +420,12 @@ __global__ void k_up_bwd(int n, int lg, int c, const __bf16* __restrict__ dcat, 
     bf16x8 o;
 #pragma unroll
     for (int i = 0; i < 8; ++i) o[i] = (__bf16)acc[i];
+    if (ymask) {
+        const bf16x8 mk = *(const bf16x8*)(ymask + vc * c + g * 8);
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+            if (!((float)mk[i] > 0.f)) o[i] = (__bf16)0.f;
+    }
     *(bf16x8*)(dlow + vc * c + g * 8) = o;
 }
 
@@ -498,31 +533,37 @@ __global__ void k_cf_to_cl(const float* __restrict__ x, int n, int64_t V, int c,
     y[i] = x[(s * c + ch) * V + v];
 }
 
-template <int MODE, int MT>
+template <int MODE, int MT, int KS>
 hipError_t launch_conv_mt(const ConvArgs& a, int coutp, hipStream_t s) {
     const int64_t M = (int64_t)a.n << (3 * a.lg);
     const int sub = coutp / 16;
     const int nsub = sub % 4 == 0 ? 4 : sub % 3 == 0 ? 3 : sub % 2 == 0 ? 2 : 1;
-    const dim3 grid(ceil_div(M, 16 * MT), sub / nsub);
+    const dim3 grid(ceil_div(M, 16 * MT), sub / nsub), block(64 * KS);
     switch (nsub) {
-        case 4: hipLaunchKernelGGL((k_conv<4, MODE, MT>), grid, dim3(64), 0, s, a); break;
-        case 3: hipLaunchKernelGGL((k_conv<3, MODE, MT>), grid, dim3(64), 0, s, a); break;
-        case 2: hipLaunchKernelGGL((k_conv<2, MODE, MT>), grid, dim3(64), 0, s, a); break;
-        default: hipLaunchKernelGGL((k_conv<1, MODE, MT>), grid, dim3(64), 0, s, a); break;
+        case 4: hipLaunchKernelGGL((k_conv<4, MODE, MT, KS>), grid, block, 0, s, a); break;
+        case 3: hipLaunchKernelGGL((k_conv<3, MODE, MT, KS>), grid, block, 0, s, a); break;
+        case 2: hipLaunchKernelGGL((k_conv<2, MODE, MT, KS>), grid, block, 0, s, a); break;
+        default: hipLaunchKernelGGL((k_conv<1, MODE, MT, KS>), grid, block, 0, s, a); break;
     }
     return hipGetLastError();
 }
 
-// Four voxel tiles per wave when that still leaves at least 2048 waves (so
-// each weight fragment serves 64 voxels), one otherwise (small grids).
+// Four voxel tiles per wave when that still leaves at least 2048 blocks (so
+// each weight fragment serves 64 voxels).  Otherwise one tile, and the k
+// range is split over 2 or 4 waves per block when there are fewer than
+// 4096 or 1024 blocks and at least two steps of 32 per wave.
 template <int MODE>
 hipError_t launch_conv(const ConvArgs& a, int coutp, hipStream_t s) {
     const int64_t M = (int64_t)a.n << (3 * a.lg);
     const int sub = coutp / 16;
     const int nsub = sub % 4 == 0 ? 4 : sub % 3 == 0 ? 3 : sub % 2 == 0 ? 2 : 1;
     const int64_t waves4 = (int64_t)ceil_div(M, 64) * (sub / nsub);
-    return waves4 >= 2048 ? launch_conv_mt<MODE, 4>(a, coutp, s)
-                          : launch_conv_mt<MODE, 1>(a, coutp, s);
+    if (waves4 >= 2048) return launch_conv_mt<MODE, 4, 1>(a, coutp, s);
+    const int64_t waves1 = (int64_t)ceil_div(M, 16) * (sub / nsub);
+    const int ksteps = a.kpad / 32;
+    if (waves1 < 1024 && ksteps >= 8) return launch_conv_mt<MODE, 1, 4>(a, coutp, s);
+    if (waves1 < 4096 && ksteps >= 4) return launch_conv_mt<MODE, 1, 2>(a, coutp, s);
+    return launch_conv_mt<MODE, 1, 1>(a, coutp, s);
 }
 
 }  // namespace
@@ -573,6 +614,7 @@ hipError_t conv_forward(const ConvGeom& g, const __bf16* x1, const __bf16* x2,
     a.w = wp;
     a.bias = bias;
     a.out = out;
+    a.omask = nullptr;
     for (int i = 0; i < 4; ++i) a.scale[i] = scale4 ? scale4[i] : 1.f;
     a.n = g.n;
     a.lg = g.lg;
@@ -588,16 +630,17 @@ hipError_t conv_forward(const ConvGeom& g, const __bf16* x1, const __bf16* x2,
     return mode == 0 ? launch_conv<0>(a, g.coutp, s) : launch_conv<1>(a, g.coutp, s);
 }
 
-hipError_t conv_backward_data(const ConvGeom& g, const __bf16* dy, const __bf16* y, int relu,
-                              const __bf16* wt, __bf16* dx, hipStream_t s) {
-    if (!dy || !wt || !dx || (relu && !y)) return hipErrorInvalidValue;
+hipError_t conv_backward_data(const ConvGeom& g, const __bf16* dy, const __bf16* wt,
+                              const __bf16* dxmask, __bf16* dx, hipStream_t s) {
+    if (!dy || !wt || !dx) return hipErrorInvalidValue;
     ConvArgs a;
     a.x1 = dy;
     a.x2 = nullptr;
-    a.mask = relu ? y : nullptr;
+    a.mask = nullptr;
     a.w = wt;
     a.bias = nullptr;
     a.out = dx;
+    a.omask = dxmask;
     for (int i = 0; i < 4; ++i) a.scale[i] = 1.f;
     a.n = g.n;
     a.lg = g.lg;
@@ -662,21 +705,21 @@ hipError_t pool_forward(int n, int lg, int c, const __bf16* x, __bf16* y, hipStr
 }
 
 hipError_t pool_backward_add(int n, int lg, int c, const __bf16* dy, const __bf16* skip, int ctot,
-                             __bf16* dx, hipStream_t s) {
+                             const __bf16* ymask, __bf16* dx, hipStream_t s) {
     if (lg < 1 || c % 8 || !dy || !dx || (skip && (ctot < c || ctot % 8))) return hipErrorInvalidValue;
     const int64_t t = ((int64_t)n << (3 * lg)) * (c / 8);
     hipLaunchKernelGGL(k_pool_bwd_add, dim3(ceil_div(t, 256)), dim3(256), 0, s, n, lg, c, dy, skip,
-                       ctot, dx);
+                       ctot, ymask, dx);
     return hipGetLastError();
 }
 
 hipError_t upsample_backward(int n, int lg, int c, const __bf16* dcat, int ctot, int coff,
-                             __bf16* dlow, hipStream_t s) {
+                             const __bf16* ymask, __bf16* dlow, hipStream_t s) {
     if (lg < 1 || c % 8 || coff % 8 || coff + c > ctot || !dcat || !dlow)
         return hipErrorInvalidValue;
     const int64_t t = ((int64_t)n << (3 * (lg - 1))) * (c / 8);
     hipLaunchKernelGGL(k_up_bwd, dim3(ceil_div(t, 256)), dim3(256), 0, s, n, lg, c, dcat, ctot, coff,
-                       dlow);
+                       ymask, dlow);
     return hipGetLastError();
 }
 

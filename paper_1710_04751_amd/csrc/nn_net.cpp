@@ -206,7 +206,9 @@ lbm_status forward(lbm_nn* nn, int n, const float* log10_ra) {
 }
 
 // Backward pass from the output gradient in dact[head]: gradients of every
-// parameter into grad (zeroed first).
+// parameter into grad (zeroed first).  Each dact[l] holds the gradient of
+// layer l's pre-activation: the kernel that writes it applies the ReLU mask
+// of act[l] once, so the convolutions read it unmasked.
 lbm_status backward(lbm_nn* nn, int n) {
     const Layout& L = nn->lay;
     hipStream_t s = nn->stream;
@@ -219,13 +221,13 @@ lbm_status backward(lbm_nn* nn, int n) {
         const ConvGeom g = nn->geom(l, n);
         const __bf16 *x1, *x2;
         layer_inputs(nn, l, &x1, &x2);
-        const __bf16* y = d.relu ? act(l) : nullptr;
         float* dw = grad + nn->off[l];
         float* db = dw + (int64_t)d.cout * d.taps * (d.c1 + d.c2);
-        NN_TRY(conv_backward_weight(g, x1, x2, dact(l), y, d.relu, dw, db, s), "weight grad");
+        NN_TRY(conv_backward_weight(g, x1, x2, dact(l), nullptr, 0, dw, db, s), "weight grad");
         if (l == 0) break;
-        // where the input gradient goes
+        // where the input gradient goes, and the ReLU mask it takes there
         __bf16* dx;
+        const __bf16* dxmask = nullptr;
         switch (l) {
             case 2: dx = nn->at<__bf16>(L.dpool[0]); break;
             case 4: dx = nn->at<__bf16>(L.dpool[1]); break;
@@ -233,14 +235,18 @@ lbm_status backward(lbm_nn* nn, int n) {
             case 9: dx = nn->at<__bf16>(L.dcat[2]); break;
             case 11: dx = nn->at<__bf16>(L.dcat[1]); break;
             case 13: dx = nn->at<__bf16>(L.dcat[0]); break;
-            default: dx = dact(l - 1); break;
+            default:
+                dx = dact(l - 1);
+                dxmask = kDefs[l - 1].relu ? act(l - 1) : nullptr;
+                break;
         }
-        NN_TRY(conv_backward_data(g, dact(l), y, d.relu, nn->at<__bf16>(L.wt[l]), dx, s),
+        NN_TRY(conv_backward_data(g, dact(l), nn->at<__bf16>(L.wt[l]), dxmask, dx, s),
                "data grad");
         if (l == 9 || l == 11 || l == 13) {
             // the upsampled half of the concatenation -> the coarse layer
             const int src = l == 9 ? 8 : l == 11 ? 10 : 12;
-            NN_TRY(upsample_backward(n, nn->lg(l), d.c2, dx, g.cin, g.c1s, dact(src), s),
+            NN_TRY(upsample_backward(n, nn->lg(l), d.c2, dx, g.cin, g.c1s,
+                                     kDefs[src].relu ? act(src) : nullptr, dact(src), s),
                    "upsample backward");
         }
         if (l == 2 || l == 4 || l == 6) {
@@ -250,7 +256,8 @@ lbm_status backward(lbm_nn* nn, int n) {
             const ConvGeom gd = nn->geom(dec, n);
             NN_TRY(pool_backward_add(n, nn->lg(l - 1), kDefs[l - 1].cout,
                                      nn->at<__bf16>(L.dpool[i]), nn->at<__bf16>(L.dcat[i]),
-                                     gd.cin, dact(l - 1), s),
+                                     gd.cin, kDefs[l - 1].relu ? act(l - 1) : nullptr,
+                                     dact(l - 1), s),
                    "pool backward");
         }
     }
