@@ -181,6 +181,94 @@ static void from_central(const lattice* L, const real* c, const real u[3], real*
     solve(L->q, A, b, f);
 }
 
+/* The paper's orthogonal basis vectors K_k evaluated at a particle velocity
+ * e: D3Q15 (Sec. 2.2, Gram-Schmidt of the monomial set) and D3Q7
+ * (Appendix C).  Used only to build the scalar source S from its printed
+ * projections m^s_k = <K_k|S>. */
+static real kbasis15(int k, int x, int y, int z) {
+    const real e2 = x * x + y * y + z * z;
+    switch (k) {
+    case 0: return 1;
+    case 1: return x;
+    case 2: return y;
+    case 3: return z;
+    case 4: return x * y;
+    case 5: return x * z;
+    case 6: return y * z;
+    case 7: return x * x - y * y;
+    case 8: return e2 - 3 * z * z;
+    case 9: return e2 - 2;
+    case 10: return 5 * x * e2 - 13 * x;
+    case 11: return 5 * y * e2 - 13 * y;
+    case 12: return 5 * z * e2 - 13 * z;
+    case 13: return x * y * z;
+    case 14: return 30 * (x * x * y * y + x * x * z * z + y * y * z * z) - 40 * e2 + 32;
+    }
+    return 0;
+}
+
+static real kbasis7(int k, int x, int y, int z) {
+    switch (k) {
+    case 0: return 1;
+    case 1: return x;
+    case 2: return y;
+    case 3: return z;
+    case 4: return x * x - y * y;
+    case 5: return 2 * (x * x - z * z) - (x * x - y * y);
+    case 6: return 7 * (x * x + y * y + z * z) - 6;
+    }
+    return 0;
+}
+
+/* Scalar source populations S^phi for a local source R at velocity u.
+ * The paper prescribes the source's continuous central moments (R; 0; ...)
+ * (eq. 16), turns them into raw moments by the binomial theorem, projects
+ * them on the orthogonal basis (eq. 19 for D3Q15, Appendix C for D3Q7) and
+ * inverts, S = K^-1 m^s (Appendix B, C).  The projections are taken as
+ * printed; reading: on D3Q7 the last one is (7 (ux^2+uy^2+uz^2) - 6) R (the
+ * Gram-Schmidt vector K6 weights the three squares alike; the printed 7 on
+ * ux^2 alone is a typo).  On D3Q15 the printed m^s_10..12 carry continuous
+ * cubes u_x^3 R although e_x^3 = e_x on the lattice, so S's lattice third-
+ * and fourth-order central moments are not zero (reading: kept as printed).
+ * The inverse is taken by a dense solve with the basis vectors, not with the
+ * printed inverse tables. */
+static void scalar_source(const lattice* L, real R, const real u[3], real* S) {
+    const real ux = u[0], uy = u[1], uz = u[2];
+    const real q2 = ux * ux + uy * uy + uz * uz;
+    real m[QMAX], A[QMAX][QMAX];
+    if (L->q == 15) {
+        m[0] = R;
+        m[1] = ux * R;
+        m[2] = uy * R;
+        m[3] = uz * R;
+        m[4] = ux * uy * R;
+        m[5] = ux * uz * R;
+        m[6] = uy * uz * R;
+        m[7] = (ux * ux - uy * uy) * R;
+        m[8] = (ux * ux + uy * uy - 2 * uz * uz) * R;
+        m[9] = (q2 - 2) * R;
+        m[10] = 5 * (ux * ux * ux + ux * uy * uy + ux * uz * uz) * R - 13 * ux * R;
+        m[11] = 5 * (ux * ux * uy + uy * uy * uy + uy * uz * uz) * R - 13 * uy * R;
+        m[12] = 5 * (ux * ux * uz + uy * uy * uz + uz * uz * uz) * R - 13 * uz * R;
+        m[13] = ux * uy * uz * R;
+        m[14] = 30 * (ux * ux * uy * uy + ux * ux * uz * uz + uy * uy * uz * uz) * R - 40 * q2 * R +
+                32 * R;
+    } else {
+        m[0] = R;
+        m[1] = ux * R;
+        m[2] = uy * R;
+        m[3] = uz * R;
+        m[4] = (ux * ux - uy * uy) * R;
+        m[5] = (ux * ux + uy * uy - 2 * uz * uz) * R;
+        m[6] = (7 * q2 - 6) * R;
+    }
+    for (int k = 0; k < L->q; ++k)
+        for (int a = 0; a < L->q; ++a)
+            A[k][a] = L->q == 15 ? kbasis15(k, L->e[a][0], L->e[a][1], L->e[a][2])
+                                 : kbasis7(k, L->e[a][0], L->e[a][1], L->e[a][2]);
+    solve(L->q, A, m, S);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Collision kernels                                                          */
 /* ------------------------------------------------------------------------ */
@@ -247,20 +335,28 @@ static void collide_flow(const real fbar[QF], const real F[3], const real omega[
 }
 
 /* Thermal: cascaded central-moment collision for the convection-diffusion
- * equation (eq. 13a), D3Q15 kernel of Sec. 2.2 or D3Q7 kernel of Appendix C,
- * with no heat source (R = 0, so S^phi = 0 and gbar = g).
- *   phi = sum gbar                                                   (eq. 25)
- *   the zeroth central moment is kept (the only collision invariant);
+ * equation with a local source R (eq. 13a), D3Q15 kernel of Sec. 2.2 or
+ * D3Q7 kernel of Appendix C.  gbar = g - S^phi/2 is the transformed
+ * distribution of eq. (13) (gbar = g when R = 0).
+ *   phi = sum gbar + R/2                                             (eq. 25)
+ *   eta = gbar + S^phi: the central moments of eta are those the kernel
+ *     relaxes (eq. 21 uses the raw moments of gbar plus those of S^phi,
+ *     reading: the lattice sums of the S^phi above);
+ *   the zeroth central moment is kept (sum of the post-collision state =
+ *     sum gbar + R);
  *   every other central moment k relaxes with omega[k] toward the discrete
- *   central moments of the scalar Maxwellian (eq. 15):
+ *   central moments of the scalar Maxwellian at phi (eq. 15):
  *     first order 0, second order xx=yy=zz=cs2 phi (so the trace is
  *     3 cs2 phi), mixed second and all third order 0, xxyy = cs2^2 phi. */
 static void collide_thermal(const lattice* L, const real* gbar, const real u[3], real cs2,
-                            const real* omega, real* out, real* phi_out) {
+                            const real* omega, real R, real* out, real* phi_out) {
     real phi = 0;
     for (int a = 0; a < L->q; ++a) phi += gbar[a];
-    real c[QMAX], ceq[QMAX], ct[QMAX];
-    central_moments(L, gbar, u, c);
+    phi += R / 2;
+    real S[QMAX], eta[QMAX], c[QMAX], ceq[QMAX], ct[QMAX];
+    scalar_source(L, R, u, S);
+    for (int a = 0; a < L->q; ++a) eta[a] = gbar[a] + S[a];
+    central_moments(L, eta, u, c);
     memset(ceq, 0, sizeof ceq);
     ceq[0] = phi;
     if (L->q == 15) {
@@ -322,6 +418,7 @@ typedef struct {
     double T_ref;          /* T0 of the Boussinesq force */
     int32_t fourth_maxwell; /* 4th-order flow equilibrium: 0 kxx~kyy~/rho, 1 rho/9 */
     int32_t pad2_;
+    double R;              /* uniform scalar source per cell and step (eq. 4) */
 } oracle_params;
 
 /* Rest equilibrium of the scalar per unit phi: the anti-bounce-back weights. */
@@ -393,10 +490,10 @@ static void step_cell(const real* nb, int x, int y, int z, const oracle_params* 
         }
     }
 
-    /* scalar first (R = 0: T = sum gbar, eq. 25), then the Boussinesq force
+    /* scalar first (T = sum gbar + R/2, eq. 25), then the Boussinesq force
      * F = g beta (T - T0) z-hat, then the flow collision, then the thermal
      * collision with the flow velocity of the same step. */
-    real T = 0;
+    real T = p->R / 2;
     for (int a = 0; a < qt; ++a) T += gbar[a];
     real F[3] = {0, 0, p->gbeta * (T - p->T_ref)};
 
@@ -409,7 +506,7 @@ static void step_cell(const real* nb, int x, int y, int z, const oracle_params* 
     real omT[QMAX];
     for (int k = 0; k < qt; ++k) omT[k] = k == 0 ? 0 : (k <= 3 ? p->omega_T : p->omega_hiT);
     real phi;
-    collide_thermal(LT, gbar, u, p->cs2T, omT, gout, &phi);
+    collide_thermal(LT, gbar, u, p->cs2T, omT, p->R, gout, &phi);
 
     if (mac) {
         mac[0] = rho;
@@ -454,12 +551,21 @@ void ORACLE_SYM(collide_flow)(const double* fbar, const double* F, const double*
 }
 
 void ORACLE_SYM(collide_thermal)(int qt, const double* gbar, const double* u, double cs2,
-                                 const double* omega, double* out) {
+                                 const double* omega, double R, double* out) {
     const lattice* L = qt == 15 ? &LAT15 : &LAT7;
     real g[QMAX] = {0}, ur[3] = {u[0], u[1], u[2]}, om[QMAX] = {0}, o[QMAX];
     for (int a = 0; a < qt; ++a) g[a] = gbar[a], om[a] = omega[a];
-    collide_thermal(L, g, ur, cs2, om, o, NULL);
+    collide_thermal(L, g, ur, cs2, om, R, o, NULL);
     for (int a = 0; a < qt; ++a) out[a] = (double)o[a];
+}
+
+/* Source populations S^phi of one cell (for checking against the printed
+ * inverse tables). */
+void ORACLE_SYM(scalar_source)(int qt, double R, const double* u, double* S) {
+    const lattice* L = qt == 15 ? &LAT15 : &LAT7;
+    real ur[3] = {u[0], u[1], u[2]}, o[QMAX];
+    scalar_source(L, R, ur, o);
+    for (int a = 0; a < qt; ++a) S[a] = (double)o[a];
 }
 
 void ORACLE_SYM(equilibrium)(int qt, double rho, const double* u, double phi, double cs2,
@@ -576,7 +682,8 @@ void ORACLE_SYM(step_cells)(const oracle_params* p, int64_t n, const double* nb,
 }
 
 /* Equilibrium state from macroscopic fields ([ncell] each, rho may be NULL
- * for rho = 1). */
+ * for rho = 1).  The scalar populations are the equilibrium at T - R/2, so
+ * that the first step sees T (eq. 25 with the source). */
 void ORACLE_SYM(init_equilibrium)(const oracle_params* p, const double* rho, const double* ux,
                                   const double* uy, const double* uz, const double* T, double* F,
                                   double* G) {
@@ -586,7 +693,7 @@ void ORACLE_SYM(init_equilibrium)(const oracle_params* p, const double* rho, con
     for (int64_t c = 0; c < (int64_t)ncell; ++c) {
         real u[3] = {ux ? ux[c] : 0, uy ? uy[c] : 0, uz ? uz[c] : 0}, f[QF], g[QMAX];
         flow_equilibrium(rho ? rho[c] : 1, u, f);
-        thermal_equilibrium(LT, T ? T[c] : 0, u, p->cs2T, g);
+        thermal_equilibrium(LT, (T ? T[c] : 0) - p->R / 2, u, p->cs2T, g);
         for (int a = 0; a < QF; ++a) F[a * ncell + c] = (double)f[a];
         for (int a = 0; a < p->qt; ++a) G[a * ncell + c] = (double)g[a];
     }

@@ -28,6 +28,7 @@ class _Params(ctypes.Structure):
         ("cs2T", ctypes.c_double), ("gbeta", ctypes.c_double),
         ("T_hot", ctypes.c_double), ("T_cold", ctypes.c_double), ("T_ref", ctypes.c_double),
         ("fourth_maxwell", ctypes.c_int32), ("pad2_", ctypes.c_int32),
+        ("R", ctypes.c_double),
     ]
 
 
@@ -50,6 +51,7 @@ class Params:
     T_ref: float = 0.0
     periodic: int = 0  # bit 0/1/2: periodic in x/y/z instead of walls
     fourth_maxwell: int = 0  # 4th-order flow equilibrium: 0 kxx~kyy~/rho, 1 rho/9
+    R: float = 0.0  # uniform scalar source per cell and step
     alpha: float = float("nan")  # thermal diffusivity, for the Nusselt number
     nu: float = float("nan")
 
@@ -61,12 +63,12 @@ class Params:
         return _Params(self.nx, self.ny, self.nz, self.qt, self.periodic, 0,
                        self.omega_nu, self.omega_bulk, self.omega_hi, self.omega_T,
                        self.omega_hiT, self.cs2T, self.gbeta, self.T_hot, self.T_cold,
-                       self.T_ref, self.fourth_maxwell, 0)
+                       self.T_ref, self.fourth_maxwell, 0, self.R)
 
 
 def cavity_params(n, Ra, Pr=0.71, u0=0.05, qt=7, cs2T=1.0 / 3.0, ny=None, nz=None,
                   T_hot=0.5, T_cold=-0.5, omega_hi=1.0, omega_hiT=1.0, omega_bulk=0.0,
-                  fourth_maxwell=0) -> Params:
+                  fourth_maxwell=0, R=0.0) -> Params:
     """Map (Ra, Pr, u0, L = n) to lattice parameters.
 
     Reading (the paper gives Ra = g beta dT L^3 / (alpha nu) and Pr = nu/alpha,
@@ -86,7 +88,7 @@ def cavity_params(n, Ra, Pr=0.71, u0=0.05, qt=7, cs2T=1.0 / 3.0, ny=None, nz=Non
                   fourth_maxwell=fourth_maxwell,
                   omega_T=1.0 / (alpha / cs2T + 0.5), omega_hiT=omega_hiT,
                   cs2T=cs2T, gbeta=gbeta, T_hot=T_hot, T_cold=T_cold,
-                  T_ref=0.5 * (T_hot + T_cold), alpha=alpha, nu=nu)
+                  T_ref=0.5 * (T_hot + T_cold), R=R, alpha=alpha, nu=nu)
 
 
 def _lib(long_double=False):
@@ -109,7 +111,8 @@ def _lib(long_double=False):
     f("set_threads", ctypes.c_int, [ctypes.c_int])
     f("real_bytes", ctypes.c_int, [])
     f("collide_flow", None, [dp, dp, dp, ctypes.c_int, dp, dp])
-    f("collide_thermal", None, [ctypes.c_int, dp, dp, ctypes.c_double, dp, dp])
+    f("collide_thermal", None, [ctypes.c_int, dp, dp, ctypes.c_double, dp, ctypes.c_double, dp])
+    f("scalar_source", None, [ctypes.c_int, ctypes.c_double, dp, dp])
     f("equilibrium", None, [ctypes.c_int, ctypes.c_double, dp, ctypes.c_double,
                             ctypes.c_double, dp, dp])
     f("run", ctypes.c_int, [P, ctypes.c_int64, dp, dp, dp])
@@ -144,13 +147,23 @@ def collide_flow(fbar, F, omega, fourth_maxwell=0, long_double=False):
     return out, ru[0], ru[1:].copy()
 
 
-def collide_thermal(qt, gbar, u, cs2, omega, long_double=False):
-    """Thermal collision of one cell (R = 0)."""
+def collide_thermal(qt, gbar, u, cs2, omega, R=0.0, long_double=False):
+    """Thermal collision of one cell with a local source R (gbar is the
+    transformed distribution g - S/2 of eq. (13))."""
     g = np.ascontiguousarray(gbar, dtype=np.float64)
     ur = np.ascontiguousarray(u, dtype=np.float64)
     om = np.ascontiguousarray(omega, dtype=np.float64)
     out = np.empty(qt)
-    _lib(long_double)["collide_thermal"](qt, _ptr(g), _ptr(ur), float(cs2), _ptr(om), _ptr(out))
+    _lib(long_double)["collide_thermal"](qt, _ptr(g), _ptr(ur), float(cs2), _ptr(om), float(R),
+                                         _ptr(out))
+    return out
+
+
+def scalar_source(qt, R, u):
+    """Source populations S^phi of a cell with source R and velocity u."""
+    ur = np.ascontiguousarray(u, dtype=np.float64)
+    out = np.empty(qt)
+    _lib()["scalar_source"](qt, float(R), _ptr(ur), _ptr(out))
     return out
 
 

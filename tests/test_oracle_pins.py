@@ -447,3 +447,49 @@ def test_cavity_symmetrize_is_the_projection(oracle):
     s = oracle.cavity_symmetrize(mac[1], mac[2], mac[3], mac[4])
     for a, b in zip(s, mac[1:]):
         assert np.max(np.abs(a - b)) < 1e-13
+
+
+# --------------------------------------------------------------------------
+# Scalar source R (Sec. 2.2, Appendix B, C)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("qt", [7, 15])
+def test_uniform_source_heats_a_periodic_box_at_rate_R(oracle, qt):
+    """A periodic box at rest with a uniform source: the scalar stays uniform
+    and T = sum gbar + R/2 grows by exactly R per step from T = 0 at the first
+    step (the equilibrium start at T - R/2).  The buoyancy of that uniform T
+    accelerates the whole box: rho u_z = sum of the earlier forces plus half
+    the current one (eq. 3), i.e. u_z = g beta R (n - 1)^2 / 2 at step n."""
+    R, gb = 0.013, 0.01
+    p = oracle.Params(nx=6, ny=5, nz=4, qt=qt, periodic=7, omega_nu=1.3, omega_T=0.9,
+                      omega_hiT=1.2, omega_hi=1.1, gbeta=gb, T_ref=0.0, R=R)
+    F, G = oracle.rest_state(p)
+    done = 0
+    for n in (1, 2, 7):
+        F, G, mac = oracle.run(p, n - done, F, G)
+        done = n
+        rho, ux, uy, uz, T = mac
+        assert np.max(np.abs(T - (n - 1) * R)) < 1e-15
+        assert np.max(np.abs(uz - gb * R * (n - 1) ** 2 / 2)) < 1e-16
+        assert np.max(np.abs(ux)) + np.max(np.abs(uy)) < 1e-15
+        assert np.max(np.abs(rho - 1)) < 1e-15
+
+
+@pytest.mark.parametrize("qt", [7, 15])
+def test_source_heat_balance_in_the_cavity(oracle, qt):
+    """Every step the scalar content of the cavity changes by the source plus
+    the heat crossing the two Dirichlet walls through the anti-bounce-back
+    links, exactly: sum T(n+1) - sum T(n) = R V + Q_hot(n) - Q_cold(n), where
+    Q are the wall link fluxes from which the Nusselt numbers are formed
+    (adiabatic bounce-back and streaming conserve the rest)."""
+    p = oracle.cavity_params(8, 2e3, qt=qt, ny=6, nz=5, R=0.002, omega_bulk=1.0)
+    F, G = oracle.rest_state(p)
+    F, G, mac = oracle.run(p, 40, F, G)
+    V = p.ncell
+    for _ in range(3):
+        nh, nc = oracle.nusselt(p, G)
+        q_in = (nh.sum() - nc.sum()) * p.alpha * (p.T_hot - p.T_cold) / p.nx
+        s0 = mac[4].sum()
+        F, G, mac = oracle.run(p, 1, F, G)
+        assert abs(mac[4].sum() - s0 - (p.R * V + q_in)) < 1e-12
+        assert abs(q_in) > 1e-3  # the walls do carry heat here

@@ -6,13 +6,18 @@ prints the closed-form result of its cascade:
   * flow, D3Q15: kernel g^ of Appendix A and its post-collision expansion;
   * thermal, D3Q15: kernel h^ of Sec. 2.2 and its post-collision expansion;
   * thermal, D3Q7: kernel h^ of Appendix C and its post-collision expansion.
-Those printed formulas are transcribed below (with R = 0) and evaluated on
-seeded random inputs; the two must agree to rounding.  A dropped term, a
+Those printed formulas are transcribed below (with and without the scalar
+source R, whose populations are the printed inverse tables of Appendix B and
+C) and evaluated on seeded random inputs; the two must agree to rounding.  A dropped term, a
 wrong sign, a wrong rate index or a transposed moment anywhere in the oracle's
 generic machinery breaks the agreement.
 
 Readings applied to the printed text (each also in the design notes):
   * Appendix C lists the first kernel component twice as h1; the first is h0 = 0.
+  * Appendix C's source: S_3 and S_4 use m^s_2 (printed m^s_1), and
+    m^s_6 = (7 (ux^2 + uy^2 + uz^2) - 6) R (printed 7 ux^2 + uy^2 + uz^2).
+  * eq. (21): the source's raw moments inside eta' are the lattice sums of
+    the source populations S^phi.
   * Appendix A: the kinematic-viscosity rates are omega_4..omega_9 (the text
     says 5..9).  Here every rate is drawn independently anyway.
   * Appendix A, g14: the 4th-order equilibrium is kxx~ kyy~ / rho, with kxx~,
@@ -75,6 +80,73 @@ def _table(text, q):
 POST15 = _table(_POST15, 15)
 POST7 = _table(_POST7, 7)
 
+# Source populations as printed: S_alpha = (sum_k c_k m^s_k) / d.
+# Appendix B (D3Q15): "alpha: d | k:c ...".
+_SRC15 = """
+0: 45 | 0:3 9:-5 14:1
+1: 180 | 0:12 1:18 7:45 8:15 9:-10 10:-9 14:-1
+2: 180 | 0:12 1:-18 7:45 8:15 9:-10 10:9 14:-1
+3: 180 | 0:12 2:18 7:-45 8:15 9:-10 11:-9 14:-1
+4: 180 | 0:12 2:-18 7:-45 8:15 9:-10 11:9 14:-1
+5: 180 | 0:12 3:18 8:-30 9:-10 12:-9 14:-1
+6: 180 | 0:12 3:-18 8:-30 9:-10 12:9 14:-1
+7: 720 | 0:48 1:72 2:72 3:72 4:90 5:90 6:90 9:40 10:9 11:9 12:9 13:90 14:1
+8: 720 | 0:48 1:-72 2:72 3:72 4:-90 5:-90 6:90 9:40 10:-9 11:9 12:9 13:-90 14:1
+9: 720 | 0:48 1:72 2:-72 3:72 4:-90 5:90 6:-90 9:40 10:9 11:-9 12:9 13:-90 14:1
+10: 720 | 0:48 1:-72 2:-72 3:72 4:90 5:-90 6:-90 9:40 10:-9 11:-9 12:9 13:90 14:1
+11: 720 | 0:48 1:72 2:72 3:-72 4:90 5:-90 6:-90 9:40 10:9 11:9 12:-9 13:-90 14:1
+12: 720 | 0:48 1:-72 2:72 3:-72 4:-90 5:90 6:-90 9:40 10:-9 11:9 12:-9 13:90 14:1
+13: 720 | 0:48 1:72 2:-72 3:-72 4:-90 5:-90 6:90 9:40 10:9 11:-9 12:-9 13:90 14:1
+14: 720 | 0:48 1:-72 2:-72 3:-72 4:90 5:90 6:90 9:40 10:-9 11:-9 12:-9 13:-90 14:1
+"""
+# Appendix C (D3Q7), with S_3, S_4 on m^s_2 (reading).
+_SRC7 = """
+0: 7 | 0:1 6:-1
+1: 84 | 0:12 1:42 4:21 5:7 6:2
+2: 84 | 0:12 1:-42 4:21 5:7 6:2
+3: 84 | 0:12 2:42 4:-21 5:7 6:2
+4: 84 | 0:12 2:-42 4:-21 5:7 6:2
+5: 42 | 0:6 3:21 5:-7 6:1
+6: 42 | 0:6 3:-21 5:-7 6:1
+"""
+
+
+def _src_table(text, q):
+    A = np.zeros((q, q))
+    for line in text.strip().splitlines():
+        row, rest = line.split(":", 1)
+        d, terms = rest.split("|")
+        for tok in terms.split():
+            k, v = tok.split(":")
+            A[int(row), int(k)] = float(v) / float(d)
+    return A
+
+
+SRC15 = _src_table(_SRC15, 15)
+SRC7 = _src_table(_SRC7, 7)
+
+
+def source_moments15(R, u):
+    """Projections m^s of the scalar source on K, eq. (19), as printed."""
+    ux, uy, uz = u
+    q2 = ux * ux + uy * uy + uz * uz
+    return np.array([
+        R, ux * R, uy * R, uz * R, ux * uy * R, ux * uz * R, uy * uz * R, (ux ** 2 - uy ** 2) * R,
+        (ux ** 2 + uy ** 2 - 2 * uz ** 2) * R, (q2 - 2) * R,
+        5 * (ux ** 3 + ux * uy ** 2 + ux * uz ** 2) * R - 13 * ux * R,
+        5 * (ux ** 2 * uy + uy ** 3 + uy * uz ** 2) * R - 13 * uy * R,
+        5 * (ux ** 2 * uz + uy ** 2 * uz + uz ** 3) * R - 13 * uz * R,
+        ux * uy * uz * R,
+        30 * (ux ** 2 * uy ** 2 + ux ** 2 * uz ** 2 + uy ** 2 * uz ** 2) * R - 40 * q2 * R + 32 * R])
+
+
+def source_moments7(R, u):
+    """Projections m^s of Appendix C (last one read as 7 (u.u) - 6)."""
+    ux, uy, uz = u
+    q2 = ux * ux + uy * uy + uz * uz
+    return np.array([R, ux * R, uy * R, uz * R, (ux ** 2 - uy ** 2) * R,
+                     (ux ** 2 + uy ** 2 - 2 * uz ** 2) * R, (7 * q2 - 6) * R])
+
 
 def _kvec15():
     """The orthogonal basis K_0..K_14 of Sec. 2.2 evaluated on D3Q15."""
@@ -125,69 +197,79 @@ def _raw(f, ex, ey, ez):
     return r
 
 
-def paper_thermal15(gbar, u, cs2, w):
-    """Sec. 2.2 kernel h^ (R = 0) and post-collision expansion."""
+def paper_thermal15(gbar, u, cs2, w, R=0.0):
+    """Sec. 2.2 kernel h^ and post-collision expansion (eq. 13a), source S^phi
+    from Appendix B; eta' = kappa' + sigma' (eq. 21), phi = sum gbar + R/2."""
     ux, uy, uz = u
-    n = _raw(gbar, EX15, EY15, EZ15)  # eta' = kappa' (no source)
-    phi = n["0"]
+    S = SRC15 @ source_moments15(R, u)
+    k = _raw(gbar, EX15, EY15, EZ15)
+    sg = _raw(S, EX15, EY15, EZ15)
+    n = {m: k[m] + sg[m] for m in k}
+    phi = k["0"] + R / 2
+    ph = phi + R / 2  # the (phi + R/2) of the printed kernel
     h = np.zeros(15)
-    h[1] = w[1] / 10 * (phi * ux - n["x"])
-    h[2] = w[2] / 10 * (phi * uy - n["y"])
-    h[3] = w[3] / 10 * (phi * uz - n["z"])
-    h[4] = w[4] / 8 * (-n["xy"] + uy * n["x"] + ux * n["y"] - phi * ux * uy) + 5 / 4 * (uy * h[1] + ux * h[2])
-    h[5] = w[5] / 8 * (-n["xz"] + uz * n["x"] + ux * n["z"] - phi * ux * uz) + 5 / 4 * (uz * h[1] + ux * h[3])
-    h[6] = w[6] / 8 * (-n["yz"] + uz * n["y"] + uy * n["z"] - phi * uy * uz) + 5 / 4 * (uz * h[2] + uy * h[3])
-    h[7] = (w[7] / 4 * (-(n["xx"] - n["yy"]) + 2 * (ux * n["x"] - uy * n["y"]) - phi * (ux ** 2 - uy ** 2))
+    h[1] = w[1] / 10 * (phi * ux - k["x"] - ux * R / 2)
+    h[2] = w[2] / 10 * (phi * uy - k["y"] - uy * R / 2)
+    h[3] = w[3] / 10 * (phi * uz - k["z"] - uz * R / 2)
+    h[4] = w[4] / 8 * (-n["xy"] + uy * n["x"] + ux * n["y"] - ph * ux * uy) + 5 / 4 * (uy * h[1] + ux * h[2])
+    h[5] = w[5] / 8 * (-n["xz"] + uz * n["x"] + ux * n["z"] - ph * ux * uz) + 5 / 4 * (uz * h[1] + ux * h[3])
+    h[6] = w[6] / 8 * (-n["yz"] + uz * n["y"] + uy * n["z"] - ph * uy * uz) + 5 / 4 * (uz * h[2] + uy * h[3])
+    h[7] = (w[7] / 4 * (-(n["xx"] - n["yy"]) + 2 * (ux * n["x"] - uy * n["y"]) - ph * (ux ** 2 - uy ** 2))
             + 5 * (ux * h[1] - uy * h[2]))
     h[8] = (w[8] / 12 * (-(n["xx"] + n["yy"] - 2 * n["zz"]) + 2 * (ux * n["x"] + uy * n["y"] - 2 * uz * n["z"])
-                         - phi * (ux ** 2 + uy ** 2 - 2 * uz ** 2))
+                         - ph * (ux ** 2 + uy ** 2 - 2 * uz ** 2))
             + 5 / 3 * (ux * h[1] + uy * h[2] - 2 * uz * h[3]))
     h[9] = (w[9] / 18 * (3 * cs2 * phi - (n["xx"] + n["yy"] + n["zz"]) + 2 * (ux * n["x"] + uy * n["y"] + uz * n["z"])
-                         - phi * (ux ** 2 + uy ** 2 + uz ** 2))
+                         - ph * (ux ** 2 + uy ** 2 + uz ** 2))
             + 10 / 9 * (ux * h[1] + uy * h[2] + uz * h[3]))
     h[10] = (w[10] / 16 * (-n["xyy"] + 2 * uy * n["xy"] - uy ** 2 * n["x"] + ux * n["yy"] - 2 * ux * uy * n["y"]
-                           + phi * ux * uy ** 2)
+                           + ph * ux * uy ** 2)
              - (5 / 8 * uy ** 2 + 1 / 2) * h[1] - 5 / 4 * ux * uy * h[2] + uy * h[4]
              + 1 / 8 * ux * (-h[7] + h[8] + 3 * h[9]))
     h[11] = (w[11] / 16 * (-n["xxy"] + 2 * ux * n["xy"] + uy * n["xx"] - ux ** 2 * n["y"] - 2 * ux * uy * n["x"]
-                           + phi * ux ** 2 * uy)
+                           + ph * ux ** 2 * uy)
              - 5 / 4 * ux * uy * h[1] - (5 / 8 * ux ** 2 + 1 / 2) * h[2] + ux * h[4]
              + 1 / 8 * uy * (h[7] + h[8] + 3 * h[9]))
     h[12] = (w[12] / 16 * (-n["xxz"] + 2 * ux * n["xz"] + uz * n["xx"] - 2 * ux * uz * n["x"] - ux ** 2 * n["z"]
-                           + phi * ux ** 2 * uz)
+                           + ph * ux ** 2 * uz)
              - 5 / 4 * ux * uz * h[1] - (5 / 8 * ux ** 2 + 1 / 2) * h[3] + ux * h[5]
              + 1 / 8 * uz * (h[7] + h[8] + 3 * h[9]))
     h[13] = (w[13] / 8 * (-n["xyz"] + ux * n["yz"] + uy * n["xz"] + uz * n["xy"] - uy * uz * n["x"]
-                          - ux * uz * n["y"] - ux * uy * n["z"] + phi * ux * uy * uz)
+                          - ux * uz * n["y"] - ux * uy * n["z"] + ph * ux * uy * uz)
              - 5 / 4 * (uy * uz * h[1] + ux * uz * h[2] + ux * uy * h[3]) + uz * h[4] + uy * h[5] + ux * h[6])
     h[14] = (w[14] / 16 * (-n["xxyy"] + 2 * uy * n["xxy"] + 2 * ux * n["xyy"] - uy ** 2 * n["xx"]
                            - ux ** 2 * n["yy"] - 4 * ux * uy * n["xy"] + 2 * ux * uy ** 2 * n["x"]
-                           + 2 * ux ** 2 * uy * n["y"] + cs2 ** 2 * phi - phi * ux ** 2 * uy ** 2)
+                           + 2 * ux ** 2 * uy * n["y"] + cs2 ** 2 * phi - ph * ux ** 2 * uy ** 2)
              + 5 / 4 * (ux * uy ** 2 * h[1] + ux ** 2 * uy * h[2]) - 2 * ux * uy * h[4]
              + 1 / 8 * (ux ** 2 - uy ** 2) * h[7] - 1 / 8 * (ux ** 2 + uy ** 2) * h[8]
              - (3 / 8 * (ux ** 2 + uy ** 2) + 1 / 2) * h[9] + 2 * (ux * h[10] + uy * h[11])
              + uy * h[2] + ux * h[1])
-    return gbar + POST15 @ h
+    return gbar + POST15 @ h + S
 
 
-def paper_thermal7(gbar, u, cs2, w):
-    """Appendix C kernel h^ (R = 0) and post-collision expansion."""
+def paper_thermal7(gbar, u, cs2, w, R=0.0):
+    """Appendix C kernel h^ and post-collision expansion, with its source
+    S^phi; eta' = kappa' + sigma' (eq. 21), phi = sum gbar + R/2."""
     ux, uy, uz = u
-    n = _raw(gbar, EX7, EY7, EZ7)
-    phi = n["0"]
+    S = SRC7 @ source_moments7(R, u)
+    k = _raw(gbar, EX7, EY7, EZ7)
+    sg = _raw(S, EX7, EY7, EZ7)
+    n = {m: k[m] + sg[m] for m in k}
+    phi = k["0"] + R / 2
+    ph = phi + R / 2
     h = np.zeros(7)
-    h[1] = w[1] / 2 * (phi * ux - n["x"])
-    h[2] = w[2] / 2 * (phi * uy - n["y"])
-    h[3] = w[3] / 2 * (phi * uz - n["z"])
-    h[4] = (w[4] / 4 * (-(n["xx"] - n["yy"]) + 2 * (ux * n["x"] - uy * n["y"]) - phi * (ux ** 2 - uy ** 2))
+    h[1] = w[1] / 2 * (phi * ux - k["x"] - ux * R / 2)
+    h[2] = w[2] / 2 * (phi * uy - k["y"] - uy * R / 2)
+    h[3] = w[3] / 2 * (phi * uz - k["z"] - uz * R / 2)
+    h[4] = (w[4] / 4 * (-(n["xx"] - n["yy"]) + 2 * (ux * n["x"] - uy * n["y"]) - ph * (ux ** 2 - uy ** 2))
             + ux * h[1] - uy * h[2])
     h[5] = (w[5] / 12 * (-(n["xx"] + n["yy"] - 2 * n["zz"]) + 2 * (ux * n["x"] + uy * n["y"] - 2 * uz * n["z"])
-                         - phi * (ux ** 2 + uy ** 2 - 2 * uz ** 2))
+                         - ph * (ux ** 2 + uy ** 2 - 2 * uz ** 2))
             + 1 / 3 * (ux * h[1] + uy * h[2] - 2 * uz * h[3]))
     h[6] = (w[6] / 6 * (3 * cs2 * phi - (n["xx"] + n["yy"] + n["zz"]) + 2 * (ux * n["x"] + uy * n["y"] + uz * n["z"])
-                        - phi * (ux ** 2 + uy ** 2 + uz ** 2))
+                        - ph * (ux ** 2 + uy ** 2 + uz ** 2))
             + 2 / 3 * (ux * h[1] + uy * h[2] + uz * h[3]))
-    return gbar + POST7 @ h
+    return gbar + POST7 @ h + S
 
 
 def _monomial_matrix():
@@ -320,3 +402,51 @@ def test_literal_fourth_order_equilibrium_moves_a_dense_rest_state(oracle):
     assert np.max(np.abs(lit1 - W15)) < 1e-15
     lit, _, _ = paper_flow(1.1 * W15, np.zeros(3), w, literal_g14=True)
     assert np.max(np.abs(lit - 1.1 * W15)) > 1e-2
+
+
+def test_source_populations_match_appendices_B_and_C(oracle):
+    """The oracle builds S^phi = K^-1 m^s by a dense solve with the basis
+    vectors; the paper prints the inverse (Appendix B, C).  They agree, and
+    the source carries R at zeroth order and no first-order central moment."""
+    rng = np.random.default_rng(4000)
+    for _ in range(10):
+        u = 0.15 * rng.standard_normal(3)
+        R = rng.uniform(-1, 1)
+        s15 = oracle.scalar_source(15, R, u)
+        s7 = oracle.scalar_source(7, R, u)
+        assert np.max(np.abs(s15 - SRC15 @ source_moments15(R, u))) < 1e-15
+        assert np.max(np.abs(s7 - SRC7 @ source_moments7(R, u))) < 1e-15
+        for S, ex, ey, ez in ((s15, EX15, EY15, EZ15), (s7, EX7, EY7, EZ7)):
+            assert abs(S.sum() - R) < 1e-15
+            for e, ud in ((ex, u[0]), (ey, u[1]), (ez, u[2])):
+                assert abs(S @ e - ud * R) < 1e-15
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_thermal15_kernel_with_source_matches_section_2_2(oracle, seed):
+    rng = np.random.default_rng(5000 + seed)
+    gbar = rng.uniform(-0.5, 0.5) * W15 + 0.02 * rng.standard_normal(15)
+    u = 0.1 * rng.standard_normal(3)
+    cs2 = rng.choice([1 / 3, 0.25, 0.3])
+    R = rng.uniform(-0.05, 0.05)
+    w = np.zeros(15)
+    w[1:] = rng.uniform(0.3, 1.95, 14)
+    ref = paper_thermal15(gbar, u, cs2, w, R)
+    out = oracle.collide_thermal(15, gbar, u, cs2, w, R)
+    assert np.max(np.abs(out - ref)) < 1e-13 * max(1e-3, np.max(np.abs(ref)))
+    assert abs(out.sum() - gbar.sum() - R) < 1e-15
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_thermal7_kernel_with_source_matches_appendix_C(oracle, seed):
+    rng = np.random.default_rng(6000 + seed)
+    gbar = rng.uniform(-0.5, 0.5) * np.array([0] + [1 / 6] * 6) + 0.02 * rng.standard_normal(7)
+    u = 0.1 * rng.standard_normal(3)
+    cs2 = rng.choice([1 / 3, 0.25, 0.3])
+    R = rng.uniform(-0.05, 0.05)
+    w = np.zeros(7)
+    w[1:] = rng.uniform(0.3, 1.95, 6)
+    ref = paper_thermal7(gbar, u, cs2, w, R)
+    out = oracle.collide_thermal(7, gbar, u, cs2, w, R)
+    assert np.max(np.abs(out - ref)) < 1e-13 * max(1e-3, np.max(np.abs(ref)))
+    assert abs(out.sum() - gbar.sum() - R) < 1e-15
