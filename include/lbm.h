@@ -14,12 +14,14 @@
  *   pull streaming, eq. (2b) and (13b), with half-way bounce-back for the
  *   flow, anti-bounce-back on the two Dirichlet walls and bounce-back on the
  *   adiabatic faces for the scalar;
- *   macroscopic fields: T = sum g (eq. 25, no heat source),
- *   F = g beta (T - T0) z-hat, rho = sum f, rho u = sum f e + F/2 (eq. 3);
+ *   macroscopic fields: T = sum gbar + R/2 (eq. 25; R the optional uniform
+ *   heat source), F = g beta (T - T0) z-hat, rho = sum f,
+ *   rho u = sum f e + F/2 (eq. 3);
  *   flow collision: the D3Q15 cascaded central-moment kernel of Appendix A
  *   with the body-force source, eq. (2a);
  *   scalar collision: the D3Q15 kernel of Sec. 2.2 or the D3Q7 kernel of
- *   Appendix C, eq. (13a), with the flow velocity of the same step.
+ *   Appendix C, eq. (13a), with the flow velocity of the same step and the
+ *   source populations S^phi of eq. (19) / Appendix B, C.
  *
  * Conventions for every function:
  *   - Return an lbm_status; nothing throws across this ABI.
@@ -75,7 +77,11 @@ typedef struct lbm_params {
     double omega_bulk;      /* flow trace rate omega_9; <= 0 means the shear rate */
     double omega_hi;        /* flow rates omega_10..omega_14 (third/fourth order); 1 */
     double omega_hi_T;      /* scalar rates of orders >= 2; 1 */
-    double R;               /* scalar source; must be 0 */
+    double R;               /* uniform scalar source of the convection-diffusion
+                               equation (eq. 4), per cell and time step in
+                               lattice units; finite.  R != 0 runs the general
+                               collision kernels (source populations of eq. 19,
+                               Appendix B/C; T = sum gbar + R/2, eq. 25) */
     int32_t lattice_units;  /* 0: derive nu, alpha, gbeta from Ra, Pr, u0 and
                                L = nx; 1: take nu, alpha, gbeta below as given */
     int32_t block_x;        /* threads per block along x (0 = default) */
@@ -145,7 +151,7 @@ lbm_status lbm_params_lattice(const lbm_params* p, lbm_lattice* out);
 size_t lbm_workspace_bytes(const lbm_params* p);
 
 /* Create a solver.  Validates p (LBM_ERR_ARG: a size < 4, thermal_q not 7 or
- * 15, R != 0, Ra, Pr or u0 <= 0, u0 / c_s > 0.3, a relaxation rate outside
+ * 15, R not finite, Ra, Pr or u0 <= 0, u0 / c_s > 0.3, a relaxation rate outside
  * (0, 2), block sizes not a multiple of 64 threads or above 1024).
  * workspace: device pointer of at least lbm_workspace_bytes(p) bytes, 256-byte
  * aligned, borrowed until lbm_destroy.  stream: hipStream_t or NULL.
@@ -162,12 +168,14 @@ lbm_status lbm_get_lattice(const lbm_handle* h, lbm_lattice* out);
 /* Number of steps taken since the last initialisation. */
 int64_t lbm_steps_done(const lbm_handle* h);
 
-/* Rest state: rho = 1, u = 0, T = 0 (f = w_a, g = 0).  Asynchronous. */
+/* Rest state: rho = 1, u = 0, T = 0 (f = w_a; g = 0, or with a source the
+ * scalar equilibrium at -R/2, so the first step sees T = 0).  Asynchronous. */
 lbm_status lbm_init_rest(lbm_handle* h);
 
 /* Equilibrium state from fields (device pointers, float, ncell each; NULL
- * means 0): rho = 1, velocity (ux, uy, uz), temperature T.  Used to start
- * from a prediction.  The staggered part of the velocity is first set as a
+ * means 0): rho = 1, velocity (ux, uy, uz), temperature T (with a source the
+ * scalar equilibrium is taken at T - R/2, so the first step sees T).  Used
+ * to start from a prediction.  The staggered part of the velocity is first set as a
  * start from rest has it.  With pull streaming and bounce-back walls every
  * population that carries x-momentum changes the parity of x at each step
  * and the collision conserves momentum, so Qx = sum (-1)^x rho u_x only
@@ -187,7 +195,8 @@ lbm_status lbm_step(lbm_handle* h, int64_t nsteps);
  * pointers, ncell values each, double if fp64 != 0 else float; NULL skips a
  * field).  They equal the pre-collision moments of the last step (eq. 3, 25),
  * recovered from the stored post-collision populations (collision conserves
- * rho and T and adds F to the momentum).  Asynchronous. */
+ * rho, adds F to the momentum and R to the scalar sum: T = sum g~ - R/2).
+ * Asynchronous. */
 lbm_status lbm_macros(lbm_handle* h, void* rho, void* ux, void* uy, void* uz, void* T, int fp64);
 
 /* Wall Nusselt numbers of the current state (FP64 reduction on the device).

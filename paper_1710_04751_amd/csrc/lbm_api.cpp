@@ -90,8 +90,8 @@ bool validate(const lbm_params* p, lbm_lattice* L, std::string* why) {
         *why = "unknown precision";
         return false;
     }
-    if (p->R != 0.0) {
-        *why = "a scalar source R != 0 is not supported";
+    if (!std::isfinite(p->R)) {
+        *why = "the scalar source R must be finite";
         return false;
     }
     if (!(p->cs2_T > 0) || !(p->cs2_T < 1.0 / 3.0 + 1e-12)) {
@@ -187,7 +187,7 @@ lbm_status make_handle(const lbm_params* p, void* workspace, size_t bytes, void*
     h->cur = 0;
     h->steps = 0;
     h->snap_valid = false;
-    h->general = p->omega_hi != 1.0 || p->omega_hi_T != 1.0;
+    h->general = uses_general_path(p);
     h->c.omega = L.omega_nu;
     h->c.omega_bulk = L.omega_bulk;
     h->c.omega_hi = p->omega_hi;
@@ -198,6 +198,7 @@ lbm_status make_handle(const lbm_params* p, void* workspace, size_t bytes, void*
     h->c.T_ref = L.T_ref;
     h->c.T_hot = p->T_hot;
     h->c.T_cold = p->T_cold;
+    h->c.src = p->R;
     h->c.alpha = L.alpha;
     h->c.fourth_maxwell = p->fourth_maxwell;
     int bx = p->block_x, by = p->block_y;
@@ -289,7 +290,9 @@ lbm_status lbm_init_rest(lbm_handle* h) {
     if (!h) return fail(LBM_ERR_ARG, "null handle");
     if (h->owner && !batch_allows_reinit(h->owner))
         return fail(LBM_ERR_STATE, "batch member re-initialised at an odd batch step");
-    hipError_t e = launch_fill_zero(h->ws + h->lay.off_A, h->lay.state_bytes, h->stream);
+    hipError_t e = launch_init_rest((Prec)h->p.precision, h->p.thermal_q, h->geom, h->lay.ps,
+                                    h->ws + h->lay.off_A, h->lay.state_bytes, h->buf(0), h->c,
+                                    h->stream);
     if (e != hipSuccess) return hip_fail(e, "init_rest");
     h->cur = 0;
     h->steps = 0;

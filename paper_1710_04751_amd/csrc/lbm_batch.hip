@@ -179,9 +179,9 @@ bool batch_layout(const lbm_params* p, int n, BatchLayout* L, std::string* why) 
             return false;
         }
         if (p[i].precision != p[0].precision || p[i].thermal_q != p[0].thermal_q ||
-            ((p[i].omega_hi != 1.0 || p[i].omega_hi_T != 1.0) !=
-             (p[0].omega_hi != 1.0 || p[0].omega_hi_T != 1.0))) {
-            *why = "batch members must share precision, thermal_q and the higher-order rate set";
+            uses_general_path(&p[i]) != uses_general_path(&p[0])) {
+            *why = "batch members must share precision, thermal_q and the collision path "
+                   "(higher-order rates other than 1 or a scalar source)";
             return false;
         }
         if (p[i].nx > 1024 || p[i].nz > 1023 || p[i].ny > 16383) {
@@ -253,6 +253,7 @@ void fill_kcoef(const lbm_handle* h, KCoef<R>* k) {
     k->t.omega_T = (R)h->c.omega_T;
     k->t.omega_hiT = (R)h->c.omega_hiT;
     k->t.cs2 = (R)h->c.cs2;
+    k->t.src = (R)h->c.src;
     k->T_hot = (R)h->c.T_hot;
     k->T_cold = (R)h->c.T_cold;
     const double cs2 = h->c.cs2;
@@ -417,7 +418,7 @@ lbm_status lbm_batch_create(const lbm_params* p, int32_t n, void* workspace, siz
     b->lay = L;
     b->prec = (Prec)p[0].precision;
     b->qt = p[0].thermal_q;
-    b->general = p[0].omega_hi != 1.0 || p[0].omega_hi_T != 1.0;
+    b->general = uses_general_path(&p[0]);
     b->gsteps = 0;
     b->threads = 256;
     b->bpc = 8;

@@ -45,6 +45,7 @@ struct ThermCoef {
     R omega_T;    // first-order rates omega_1..omega_3 (eq. 23)
     R omega_hiT;  // rates of orders >= 2
     R cs2;        // c_sphi^2
+    R src;        // uniform scalar source R per cell and step (eq. 4)
 };
 
 template <typename R>
@@ -254,19 +255,47 @@ __device__ __forceinline__ void collide_flow(R (&d)[15], R Fz, const FlowCoef<R>
 }
 
 // ---------------------------------------------------------------------------
-// Scalar collision, D3Q15 (Sec. 2.2, eq. (13a)), no source (R = 0).
-// The zeroth central moment is kept; first order relaxes with omega_T toward
-// 0; orders >= 2 with omega_hiT toward cs2 T (diagonal), 0 (mixed, third),
-// cs2^2 T (xxyy) (eq. 15).  HG = false specialises omega_hiT == 1.
+// Scalar collision, D3Q15 (Sec. 2.2, eq. (13a)).
+// g holds gbar = g - S/2 (eq. 13); the kernel relaxes the central moments of
+// eta = gbar + S (eq. 21), S the source populations.  The zeroth central
+// moment is kept; first order relaxes with omega_T toward 0; orders >= 2
+// with omega_hiT toward cs2 phi (diagonal), 0 (mixed, third), cs2^2 phi
+// (xxyy) (eq. 15), phi = sum gbar + R/2 (eq. 25).
+// HG = false specialises omega_hiT == 1 and R == 0.
 // ---------------------------------------------------------------------------
 template <typename R, bool HG>
 __device__ __forceinline__ void collide_thermal15(R (&g)[15], R ux, R uy, R uz,
                                                   const ThermCoef<R>& c) {
-    const Raw15<R> r = raw15(g);
-    const R T = r.m0;
+    Raw15<R> r = raw15(g);
+    R phi = r.m0;
+    if constexpr (HG) {
+        // lattice raw moments of S = K^-1 m^s (eq. 19 as printed; its cubic
+        // projections alias on D3Q15, whence the (u.u - 1)/2 of the
+        // third-order sums and the 1/3 of xxyy)
+        const R s = c.src;
+        const R uxx = ux * ux, uyy = uy * uy, uzz = uz * uz;
+        const R h3 = R(0.5) * (uxx + uyy + uzz - R(1)) * s;
+        phi = r.m0 + R(0.5) * s;
+        r.m0 += s;
+        r.x += ux * s;
+        r.y += uy * s;
+        r.z += uz * s;
+        r.xx += uxx * s;
+        r.yy += uyy * s;
+        r.zz += uzz * s;
+        r.xy += ux * uy * s;
+        r.xz += ux * uz * s;
+        r.yz += uy * uz * s;
+        r.xyy += ux * h3;
+        r.xxy += uy * h3;
+        r.xxz += uz * h3;
+        r.xyz += ux * uy * uz * s;
+        r.xxyy += (uxx * uyy + uxx * uzz + uyy * uzz) * s * (R(1) / R(3));
+    }
+    const R T = r.m0;  // zeroth moment of eta: the mass of the shifts
     const R o1 = R(1) - c.omega_T;
     const R k1x = o1 * (r.x - ux * T), k1y = o1 * (r.y - uy * T), k1z = o1 * (r.z - uz * T);
-    const R cT = c.cs2 * T;
+    const R cT = c.cs2 * phi;
     R kxx = cT, kyy = cT, kzz = cT, kxy = 0, kxz = 0, kyz = 0;
     R k3xyy = 0, k3xxy = 0, k3xxz = 0, k3xyz = 0, k4 = c.cs2 * cT;
     if constexpr (HG) {
@@ -303,20 +332,33 @@ __device__ __forceinline__ void collide_thermal15(R (&g)[15], R ux, R uy, R uz,
 }
 
 // ---------------------------------------------------------------------------
-// Scalar collision, D3Q7 (Appendix C, eq. (13a)), no source (R = 0).
-// Moments 1, x, y, z, xx-yy, xx+yy-2zz, xx+yy+zz; the three second-order
-// functionals share omega_hiT, so the diagonal central moments relax
-// individually toward cs2 T.
+// Scalar collision, D3Q7 (Appendix C, eq. (13a)), gbar and eta = gbar + S
+// as for D3Q15.  Moments 1, x, y, z, xx-yy, xx+yy-2zz, xx+yy+zz; the three
+// second-order functionals share omega_hiT, so the diagonal central moments
+// relax individually toward cs2 phi.  The source's raw moments on D3Q7 are
+// (R; u R; u_i^2 R) exactly.  HG = false specialises omega_hiT == 1, R == 0.
 // ---------------------------------------------------------------------------
 template <typename R, bool HG>
 __device__ __forceinline__ void collide_thermal7(R (&g)[7], R ux, R uy, R uz,
                                                  const ThermCoef<R>& c) {
-    const R px = g[1] + g[2], py = g[3] + g[4], pz = g[5] + g[6];
-    const R jx = g[1] - g[2], jy = g[3] - g[4], jz = g[5] - g[6];
-    const R T = g[0] + px + py + pz;
+    R px = g[1] + g[2], py = g[3] + g[4], pz = g[5] + g[6];
+    R jx = g[1] - g[2], jy = g[3] - g[4], jz = g[5] - g[6];
+    R T = g[0] + px + py + pz;
+    R phi = T;
+    if constexpr (HG) {
+        const R s = c.src;
+        phi = T + R(0.5) * s;
+        T += s;
+        jx += ux * s;
+        jy += uy * s;
+        jz += uz * s;
+        px += ux * ux * s;
+        py += uy * uy * s;
+        pz += uz * uz * s;
+    }
     const R o1 = R(1) - c.omega_T;
     const R kx = o1 * (jx - ux * T), ky = o1 * (jy - uy * T), kz = o1 * (jz - uz * T);
-    const R cT = c.cs2 * T;
+    const R cT = c.cs2 * phi;
     R kxx = cT, kyy = cT, kzz = cT;
     if constexpr (HG) {
         const R w = c.omega_hiT;

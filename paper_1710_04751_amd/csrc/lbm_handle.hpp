@@ -21,6 +21,11 @@ struct Layout {
 lbm_status fail(lbm_status s, const std::string& msg);
 lbm_status hip_fail(hipError_t e, const char* what);
 bool validate(const lbm_params* p, lbm_lattice* L, std::string* why);
+// Whether the general collision kernels run: higher-order rates other than
+// 1, or a scalar source.
+inline bool uses_general_path(const lbm_params* p) {
+    return p->omega_hi != 1.0 || p->omega_hi_T != 1.0 || p->R != 0.0;
+}
 Layout layout_of(const lbm_params* p);
 void default_block(int nx, int* bx, int* by);
 // Create a handle over caller memory without touching the device.

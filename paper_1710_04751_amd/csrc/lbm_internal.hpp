@@ -20,6 +20,7 @@ struct Coefs {
     double omega, omega_bulk, omega_hi;  // flow
     double omega_T, omega_hiT, cs2;      // scalar
     double gbeta, T_ref, T_hot, T_cold;
+    double src;                          // uniform scalar source R
     double alpha;                        // for the Nusselt number
     int32_t fourth_maxwell;
 };
@@ -37,6 +38,10 @@ int value_bytes(Prec p);
 hipError_t launch_step(Prec p, int qt, bool general, const Geom& g, int64_t ps, StateBuf in,
                        StateBuf out, const Coefs& c, hipStream_t s);
 hipError_t launch_fill_zero(void* ptr, size_t bytes, hipStream_t s);
+// Rest state: zero-fills state_bytes at state (both buffers), then, with a
+// scalar source, writes the scalar equilibrium at T = -R/2 into st.
+hipError_t launch_init_rest(Prec p, int qt, const Geom& g, int64_t ps, void* state,
+                            size_t state_bytes, StateBuf st, const Coefs& c, hipStream_t s);
 // stag: device scratch of 4 doubles (16-byte aligned) for the staggered sums
 hipError_t launch_init_macros(Prec p, int qt, const Geom& g, int64_t ps, StateBuf st,
                               const float* ux, const float* uy, const float* uz, const float* T,

@@ -69,7 +69,7 @@ __global__ void __launch_bounds__(256) k_stagger_sums(const float* ux, const flo
 template <typename R, typename S, int QT>
 __global__ void k_init_macros(S* __restrict__ F, S* __restrict__ G, int64_t ps, Geom geo,
                               const float* ux, const float* uy, const float* uz, const float* T,
-                              const double* __restrict__ stag, double gbeta, R cs2) {
+                              const double* __restrict__ stag, double gbeta, R cs2, R src) {
     const int64_t ncell = (int64_t)geo.nx * geo.ny * geo.nz;
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ncell) return;
@@ -82,7 +82,8 @@ __global__ void k_init_macros(S* __restrict__ F, S* __restrict__ G, int64_t ps, 
     const R u = ux ? (R)((double)ux[c] - ((x & 1) ? -cx : cx)) : R(0);
     const R v = uy ? (R)((double)uy[c] - ((y & 1) ? -cy : cy)) : R(0);
     const R w = (R)((uz ? (double)uz[c] : 0.0) - ((z & 1) ? -cz : cz));
-    const R t = T ? (R)T[c] : R(0);
+    // scalar equilibrium at T - R/2, so that the first step sees T (eq. 25)
+    const R t = (T ? (R)T[c] : R(0)) - R(0.5) * src;
     R d[15];
     flow_equilibrium<R>(R(0), u, v, w, d);
 #pragma unroll
@@ -96,12 +97,32 @@ __global__ void k_init_macros(S* __restrict__ F, S* __restrict__ G, int64_t ps, 
     for (int a = 0; a < QT; ++a) G[a * ps + c] = (S)g[a];
 }
 
+// Rest state with a scalar source: flow at rest (deviations 0) and the
+// scalar equilibrium at T = -R/2 with u = 0, so that the first step sees
+// T = sum gbar + R/2 = 0 (eq. 25).
+template <typename R, typename S, int QT>
+__global__ void k_init_rest_source(S* __restrict__ F, S* __restrict__ G, int64_t ps,
+                                   int64_t ncell, R cs2, R src) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncell) return;
+#pragma unroll
+    for (int a = 0; a < 15; ++a) F[a * ps + c] = (S)0;
+    R g[QT];
+    if constexpr (QT == 7)
+        thermal_equilibrium7<R>(R(-0.5) * src, R(0), R(0), R(0), cs2, g);
+    else
+        thermal_equilibrium15<R>(R(-0.5) * src, R(0), R(0), R(0), cs2, g);
+#pragma unroll
+    for (int a = 0; a < QT; ++a) G[a * ps + c] = (S)g[a];
+}
+
 // Macroscopic fields from the stored post-collision populations: the
-// collision conserves rho and T and adds F to the momentum, so
-// u = (sum f~ e - F/2) / rho.
+// collision conserves rho, adds F to the momentum and R to the scalar sum,
+// so u = (sum f~ e - F/2) / rho and T = sum g~ - R/2 (eq. 25).
 template <typename R, typename S, int QT, typename O>
 __global__ void k_macros(const S* __restrict__ F, const S* __restrict__ G, int64_t ps,
-                         int64_t ncell, O* rho, O* ux, O* uy, O* uz, O* To, R gbeta, R T_ref) {
+                         int64_t ncell, O* rho, O* ux, O* uy, O* uz, O* To, R gbeta, R T_ref,
+                         R src) {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ncell) return;
     R d[15];
@@ -110,6 +131,7 @@ __global__ void k_macros(const S* __restrict__ F, const S* __restrict__ G, int64
     R T = 0;
 #pragma unroll
     for (int a = 0; a < QT; ++a) T += Store<S>::template ld<R>(G + a * ps + c);
+    T -= R(0.5) * src;
     const Raw15<R> r = raw15(d);
     const R rh = R(1) + r.m0;
     const R Fz = gbeta * (T - T_ref);
@@ -296,6 +318,18 @@ hipError_t launch_fill_zero(void* ptr, size_t bytes, hipStream_t s) {
     return hipGetLastError();
 }
 
+hipError_t launch_init_rest(Prec p, int qt, const Geom& g, int64_t ps, void* state,
+                            size_t state_bytes, StateBuf st, const Coefs& c, hipStream_t s) {
+    hipError_t e = launch_fill_zero(state, state_bytes, s);
+    if (e != hipSuccess || c.src == 0.0) return e;
+    const int64_t ncell = (int64_t)g.nx * g.ny * g.nz;
+    LBM_DISPATCH_PQ(p, qt, {
+        hipLaunchKernelGGL((k_init_rest_source<R, S, Q>), dim3(blocks_for(ncell, 256)), dim3(256),
+                           0, s, (S*)st.F, (S*)st.G, ps, ncell, (R)c.cs2, (R)c.src);
+        return hipGetLastError();
+    });
+}
+
 hipError_t launch_init_macros(Prec p, int qt, const Geom& g, int64_t ps, StateBuf st,
                               const float* ux, const float* uy, const float* uz, const float* T,
                               double* stag, const Coefs& c, hipStream_t s) {
@@ -309,7 +343,7 @@ hipError_t launch_init_macros(Prec p, int qt, const Geom& g, int64_t ps, StateBu
     LBM_DISPATCH_PQ(p, qt, {
         hipLaunchKernelGGL((k_init_macros<R, S, Q>), dim3(blocks_for(ncell, 256)), dim3(256), 0, s,
                            (S*)st.F, (S*)st.G, ps, g, ux, uy, uz, T, (const double*)stag,
-                           c.gbeta, (R)c.cs2);
+                           c.gbeta, (R)c.cs2, (R)c.src);
         return hipGetLastError();
     });
 }
@@ -323,12 +357,12 @@ hipError_t launch_macros(Prec p, int qt, const Geom& g, int64_t ps, StateBuf st,
             hipLaunchKernelGGL((k_macros<R, S, Q, double>), dim3(blocks_for(ncell, 256)), dim3(256),
                                0, s, (const S*)st.F, (const S*)st.G, ps, ncell, (double*)rho,
                                (double*)ux, (double*)uy, (double*)uz, (double*)T, (R)c.gbeta,
-                               (R)c.T_ref);
+                               (R)c.T_ref, (R)c.src);
         } else {
             hipLaunchKernelGGL((k_macros<R, S, Q, float>), dim3(blocks_for(ncell, 256)), dim3(256),
                                0, s, (const S*)st.F, (const S*)st.G, ps, ncell, (float*)rho,
                                (float*)ux, (float*)uy, (float*)uz, (float*)T, (R)c.gbeta,
-                               (R)c.T_ref);
+                               (R)c.T_ref, (R)c.src);
         }
         return hipGetLastError();
     });

@@ -13,8 +13,10 @@ namespace lbm {
 namespace kern {
 
 // Velocity along x and z of one cell, FP64, from the stored post-collision
-// state: the collision conserves rho and T and adds F to the momentum, so
-// u = (sum f~ e - F/2) / rho with F = g beta (T - T0) z-hat (eq. 3).
+// state: the collision conserves rho and adds F to the momentum, so
+// u = (sum f~ e - F/2) / rho with F = g beta (T - T0) z-hat (eq. 3).  With a
+// source the stored scalar sum exceeds T by R/2 (eq. 25); the caller folds
+// that into T_ref.
 template <typename S, int QT>
 __device__ void cell_velocity(const S* __restrict__ F, const S* __restrict__ G, int64_t ps,
                               int64_t c, double gbeta, double T_ref, double* ux, double* uz) {
@@ -74,7 +76,7 @@ hipError_t centerlines_impl(const Geom& g, int64_t ps, StateBuf st, double* u_li
                             double* w_line, const Coefs& c, double u0, hipStream_t s) {
     const int n = std::max(g.nx, g.nz);
     hipLaunchKernelGGL((k_centerlines<S, QT>), dim3((n + 255) / 256), dim3(256), 0, s,
-                       (const S*)st.F, (const S*)st.G, ps, g, c.gbeta, c.T_ref, 1.0 / u0, u_line,
+                       (const S*)st.F, (const S*)st.G, ps, g, c.gbeta, c.T_ref + 0.5 * c.src, 1.0 / u0, u_line,
                        w_line);
     return hipGetLastError();
 }

@@ -119,6 +119,7 @@ KCoef<R> make_kcoef(const Coefs& c, int qt) {
     k.t.omega_T = (R)c.omega_T;
     k.t.omega_hiT = (R)c.omega_hiT;
     k.t.cs2 = (R)c.cs2;
+    k.t.src = (R)c.src;
     k.T_hot = (R)c.T_hot;
     k.T_cold = (R)c.T_cold;
     if (qt == 7) {
@@ -183,6 +184,7 @@ __device__ __forceinline__ void update_cell(const S* __restrict__ Fi, const S* _
     R T = 0;
 #pragma unroll
     for (int a = 0; a < QT; ++a) T += gq[a];
+    if constexpr (HG) T += R(0.5) * k.t.src;  // eq. (25) with the source
     const R Fz = k.f.gbeta * (T - k.f.T_ref);
     R ux, uy, uz;
     collide_flow<R, HG>(d, Fz, k.f, ux, uy, uz);

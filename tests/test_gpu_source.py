@@ -1,0 +1,199 @@
+"""The scalar source R (Sec. 2.2 eq. 16-21, Appendix B and C) on the GPU:
+parity with the CPU oracle on ragged grids (FP64 1e-12, FP32 2e-6 as for the
+source-free kernels), the rest and equilibrium starts, a sampled one-step
+check at 512^3 in the benchmark's launch configuration, the exact per-step
+heat balance of the cavity, and the batched form."""
+import numpy as np
+import pytest
+
+from gpu_helpers import cell_index, field_errors, gather_neighbourhoods, log, to_np
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def solver():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1710_04751_amd import solver as S
+    return S
+
+
+def _lattice_params(solver, op, prec, qt):
+    """GPU parameters with the oracle's lattice values."""
+    nu = (1 / op.omega_nu - 0.5) / 3
+    alpha = op.cs2T * (1 / op.omega_T - 0.5)
+    return solver.make_params(nx=op.nx, ny=op.ny, nz=op.nz, precision=prec, thermal_q=qt,
+                              lattice_units=1, nu=nu, alpha=alpha, gbeta=op.gbeta,
+                              T_hot=op.T_hot, T_cold=op.T_cold, cs2_T=op.cs2T,
+                              omega_bulk=op.omega_bulk, omega_hi=op.omega_hi,
+                              omega_hi_T=op.omega_hiT, fourth_maxwell=op.fourth_maxwell, R=op.R)
+
+
+VARIANTS = [
+    ("q7", 7, {}),
+    ("q15", 15, {}),
+    ("q15_general_rates", 15, {"omega_hi": 0.8, "omega_hiT": 1.3}),
+    ("q7_general_rates", 7, {"omega_hi": 1.2, "omega_hiT": 0.7}),
+    ("q7_cs2_quarter_cooling", 7, {"cs2T": 0.25, "R": -4e-3}),
+]
+
+
+@pytest.mark.parametrize("name,qt,over", VARIANTS, ids=[v[0] for v in VARIANTS])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 2e-6)])
+def test_ragged_random_state_with_source(solver, oracle, name, qt, over, prec, tol):
+    """Ragged 37 x 23 x 19 grid from a seeded random non-equilibrium state
+    with a uniform source: 40 steps against the oracle, populations and
+    macroscopic fields."""
+    from paper_1710_04751_amd import workloads as W
+    shape = (19, 23, 37)
+    p = oracle.cavity_params(37, 2e4, u0=0.1, qt=qt, ny=23, nz=19, R=3e-3)
+    p.omega_nu = 1.6
+    p.omega_T = 1.45
+    for k, v in over.items():
+        setattr(p, k, v)
+    log(f"case: source ragged 37x23x19 {name} {prec}")
+    F0, G0 = oracle.init_equilibrium(
+        p, ux=W.smooth_field(shape, 1, 0.02), uy=W.smooth_field(shape, 2, 0.02),
+        uz=W.smooth_field(shape, 3, 0.02), T=W.smooth_field(shape, 4, 0.5))
+    F0 = F0 + W.perturbation(shape, 15, 5, 2e-4)
+    G0 = G0 + W.perturbation(shape, qt, 6, 2e-3)
+    F1, G1, mac = oracle.run(p, 40, F0, G0)
+    cav = solver.Cavity(_lattice_params(solver, p, prec, qt))
+    cav.set_populations(F0, G0)
+    cav.step(40)
+    Fg, Gg = (to_np(t) for t in cav.populations())
+    m = {k: to_np(v) for k, v in cav.macros(fp64=True).items()}
+    ef = np.max(np.abs(Fg - F1)) / np.max(np.abs(F1))
+    eg = np.max(np.abs(Gg - G1)) / np.max(np.abs(G1))
+    err = field_errors(m, mac)
+    log(name, prec, "F", ef, "G", eg, err)
+    assert ef <= tol and eg <= tol
+    assert err["rho"] <= tol and err["u"] <= 10 * tol and err["T"] <= tol
+    cav.close()
+
+
+@pytest.mark.parametrize("qt", [7, 15])
+def test_rest_start_with_source(solver, oracle, qt):
+    """lbm_init_rest with a source starts the scalar at T = 0 (equilibrium
+    at -R/2); 300 FP64 steps of a 16^3 cavity against the oracle."""
+    log(f"case: source rest start 16^3 q{qt} fp64")
+    p = oracle.cavity_params(16, 5e3, qt=qt, u0=0.1, omega_bulk=1.0, R=2e-3)
+    F, G = oracle.rest_state(p)
+    F, G, mac = oracle.run(p, 300, F, G)
+    cav = solver.Cavity(solver.make_params(16, 5e3, precision="fp64", thermal_q=qt, u0=0.1,
+                                           omega_bulk=1.0, R=2e-3))
+    F0, G0 = (to_np(t) for t in cav.populations())
+    Fr, Gr = oracle.rest_state(p)
+    assert np.max(np.abs(F0 - Fr)) < 1e-15 and np.max(np.abs(G0 - Gr)) < 1e-17
+    cav.step(300)
+    m = {k: to_np(v) for k, v in cav.macros(fp64=True).items()}
+    err = field_errors(m, mac)
+    log("rest start", err)
+    assert err["rho"] <= 1e-12 and err["u"] <= 1e-12 and err["T"] <= 1e-12
+    cav.close()
+
+
+def test_init_macros_with_source(solver, oracle):
+    """lbm_init_macros takes the scalar equilibrium at T - R/2."""
+    from paper_1710_04751_amd import workloads as W
+    shape = (9, 10, 11)
+    p = oracle.cavity_params(11, 1e4, qt=15, ny=10, nz=9, R=5e-3)
+    fields = [W.smooth_field(shape, s, a).astype(np.float32).astype(np.float64)
+              for s, a in ((11, 0.03), (12, 0.03), (13, 0.03), (14, 0.5))]
+    u = oracle.staggered_free(*fields[:3], T=fields[3], gbeta=p.gbeta, T_ref=p.T_ref)
+    F, G = oracle.init_equilibrium(p, ux=u[0], uy=u[1], uz=u[2], T=fields[3])
+    cav = solver.Cavity(solver.make_params(nx=11, ny=10, nz=9, Ra=1e4, precision="fp64",
+                                           thermal_q=15, R=5e-3))
+    cav.init_macros(*[torch.tensor(f, dtype=torch.float32) for f in fields])
+    Fg, Gg = (to_np(t) for t in cav.populations())
+    assert np.max(np.abs(Fg - F)) < 1e-15 and np.max(np.abs(Gg - G)) < 1e-15
+    cav.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+def test_full_size_sampled_one_step_with_source(solver, oracle, prec):
+    """512^3, Ra = 1e6, D3Q7 with a source, in the launch configuration the
+    benchmark times (the general kernels): one step from a non-trivial
+    state, 3000 sampled cells updated one by one by the oracle."""
+    from paper_1710_04751_amd import workloads as W
+    n, R = 512, 1e-4
+    log(f"case: source 512^3 sampled one-step {prec}")
+    p = oracle.cavity_params(n, 1e6, R=R)
+    cav = solver.Cavity(solver.make_params(n, 1e6, precision=prec, R=R))
+    shape = cav.shape
+    zz, yy, xx = torch.meshgrid(*[(torch.arange(s, device="cuda", dtype=torch.float32) + 0.5) / s
+                                  for s in shape], indexing="ij")
+    ux = 0.02 * torch.sin(3.1 * xx) * torch.cos(2.2 * yy) * torch.sin(1.7 * zz)
+    uy = 0.015 * torch.cos(1.3 * xx) * torch.sin(2.9 * zz)
+    uz = 0.01 * torch.sin(2.3 * yy) * torch.cos(3.7 * xx)
+    T = 0.5 * torch.sin(4.1 * xx + 1.0) * torch.cos(3.3 * zz)
+    cav.init_macros(ux, uy, uz, T)
+    del ux, uy, uz, T, xx, yy, zz
+    cav.step(3)
+    pos = W.sample_cells(shape, 3000, seed=4)
+    nb = gather_neighbourhoods(cav, pos)
+    cav.step(1)
+    Fg, Gg = (to_np(t) for t in cav.gather_cells(cell_index(pos, shape)))
+    fo, go, _ = oracle.step_cells(p, nb, pos)
+    log(prec, "max |dF|", np.max(np.abs(Fg - fo)), "max |dG|", np.max(np.abs(Gg - go)))
+    if prec == "fp32":
+        assert np.max(np.abs(Fg - fo)) < 1e-7 and np.max(np.abs(Gg - go)) < 1e-7
+    else:
+        w, _ = oracle.equilibrium(7, 1.0, [0, 0, 0], 0.0)
+        ulp_f = np.spacing(np.abs(fo - w).astype(np.float16)).astype(np.float64)
+        ulp_g = np.spacing(np.abs(go).astype(np.float16)).astype(np.float64)
+        assert np.all(np.abs(Fg - fo) <= ulp_f + 1e-7)
+        assert np.all(np.abs(Gg - go) <= ulp_g + 1e-7)
+    cav.close()
+    del cav
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("n,prec,qt,rtol", [(96, "fp64", 15, 1e-10), (512, "fp32", 7, 1e-4)])
+def test_heat_balance_every_step(solver, n, prec, qt, rtol):
+    """Each step the scalar content changes by the source plus the heat the
+    Dirichlet walls pass (the link fluxes the Nusselt numbers are made of):
+    sum T(t+1) - sum T(t) = R V + Q_hot(t) - Q_cold(t).  Checked on three
+    consecutive steps of a convecting cavity (in FP32 the kernel's own
+    rounding of sum g over 1.3e8 cells sets the tolerance)."""
+    R = 2e-5
+    log(f"case: source heat balance {n}^3 {prec} q{qt}")
+    cav = solver.Cavity(solver.make_params(n, 1e5, precision=prec, thermal_q=qt, R=R))
+    cav.step(400)
+    alpha, V = cav.lattice.alpha, n ** 3
+    for _ in range(3):
+        nu = cav.nusselt()
+        q_in = (nu.nu_hot_wall - nu.nu_cold_wall) * n * n * alpha * 1.0 / n
+        s0 = float(cav.macros(fp64=True)["T"].sum())
+        cav.step(1)
+        s1 = float(cav.macros(fp64=True)["T"].sum())
+        want = R * V + q_in
+        log(f"dT sum {s1 - s0:.9e} want {want:.9e} (R V {R * V:.4e}, walls {q_in:.4e})")
+        assert abs(q_in) > 1e-3 * R * V
+        assert abs((s1 - s0) - want) <= rtol * (abs(R * V) + abs(q_in))
+    cav.close()
+    del cav
+    torch.cuda.empty_cache()
+
+
+def test_batch_with_source_equals_single_runs(solver):
+    """Members with different sources (the general kernels) step
+    bit-identically in the batch and alone."""
+    sizes = [(32, 32, 32), (20, 28, 16), (48, 12, 10)]
+    srcs = [1e-4, -3e-4, 5e-5]
+    params = [solver.make_params(nx=nx, ny=ny, nz=nz, Ra=2e4, precision="fp32", u0=0.1,
+                                 omega_bulk=1.0, fourth_maxwell=1, R=r)
+              for (nx, ny, nz), r in zip(sizes, srcs)]
+    log("case: batch with sources vs single fp32")
+    batch = solver.Batch(params)
+    batch.step(120)
+    for i, p in enumerate(params):
+        cav = solver.Cavity(p)
+        cav.step(120)
+        Fs, Gs = cav.populations()
+        Fb, Gb = batch.members[i].populations()
+        assert torch.equal(Fs, Fb) and torch.equal(Gs, Gb), i
+        cav.close()
+    batch.close()
