@@ -25,6 +25,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "coupled flow+thermal MLUPS & % HBM roofline; steps-to-steady learned vs plain"
 HBM_PEAK_GBS = 8000.0
+# uniform scalar source of the heat-source line (lattice units per cell and
+# step); it selects the general collision kernels
+SOURCE_R = 1e-6
 
 
 def recorded_traffic(n, precision):
@@ -50,12 +53,12 @@ def algorithmic_bytes_per_cell(precision, qt=7):
     return 2 * (15 + qt) * vb
 
 
-def time_variant(n, ra, precision, steps, warmup, block=None, log=print):
+def time_variant(n, ra, precision, steps, warmup, block=None, log=print, R=0.0):
     import torch
     from paper_1710_04751_amd import solver as S
 
     stream = torch.cuda.Stream()
-    params = S.make_params(n, ra, precision=precision)
+    params = S.make_params(n, ra, precision=precision, R=R)
     if block:
         params.block_x, params.block_y = block
     cav = S.Cavity(params, stream=stream)
@@ -440,6 +443,8 @@ def main():
     ap.add_argument("--batched-steps", type=int, default=2000)
     ap.add_argument("--block", type=str, default=None, help="bx,by of the step kernel")
     ap.add_argument("--no-nn", action="store_true", help="skip the network throughput leg")
+    ap.add_argument("--source-steps", type=int, default=1000,
+                    help="timed steps of the heat-source line (general kernels); 0 skips it")
     ap.add_argument("--no-precision", action="store_true",
                     help="skip the 512^3 FP32/FP16 comparison with the 128^3 oracle reference")
     ap.add_argument("--warm-start", action="store_true",
@@ -469,6 +474,11 @@ def main():
     f16_steps = args.fp16_steps if args.fp16_steps is not None else args.steps
     f16 = time_variant(args.n, args.Ra, "fp16", f16_steps, args.warmup, block, log)
     log(json.dumps(f16))
+    src = None
+    if args.source_steps > 0:
+        src = time_variant(args.n, args.Ra, "fp32", args.source_steps, args.warmup, block, log,
+                           R=SOURCE_R)
+        log(json.dumps(src))
     batched = None if args.no_batched else time_batched(args.batched_steps, log=log)
     if batched is not None and args.batched_steady:
         batched["to_steady"] = time_batched_steady(log=log)
@@ -511,6 +521,14 @@ def main():
                          "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": round(f16["frac_hbm_peak"], 4),
                          "traffic": recorded_traffic(args.n, "fp16")},
+        },
+        "heat_source": None if src is None else {
+            "value": round(src["mlups"], 1), "unit": "MLUPS", "steps": args.source_steps,
+            "R": SOURCE_R, "storage": "fp32", "ms_per_step": src["ms_per_step"],
+            "kernel": src["kernel"],
+            "roofline": {"bound": "hbm", "achieved": round(src["achieved_GBs"], 1),
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(src["frac_hbm_peak"], 4), "traffic": None},
         },
         "batched": batched,
         "network": nn,
