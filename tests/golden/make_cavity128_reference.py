@@ -11,7 +11,8 @@ T, float32) on the mid-planes y = 64 and z = 64 (0-based cell indices), the
 points the 512^3 fields are compared at after averaging each 4x4x4 block.
 
 Only the oracle is called.  Runtime: several CPU hours (OpenMP threads from
-ORACLE_THREADS, default all cores).
+ORACLE_THREADS, default all cores).  With GOLDEN_CHECKPOINT set to a file
+path the state is saved there every 500 steps and a run resumes from it.
 """
 import os
 import sys
@@ -32,8 +33,13 @@ def main():
     threads = O.set_threads(int(os.environ.get("ORACLE_THREADS", "0")) or (os.cpu_count() or 1))
     p = O.cavity_params(N, RA, omega_bulk=1.0, fourth_maxwell=1, cs2T=0.25)
     F, G = O.rest_state(p)
-    t0 = time.time()
     done, chunk = 0, 100
+    ckpt = os.environ.get("GOLDEN_CHECKPOINT")
+    if ckpt and os.path.exists(ckpt):
+        z = np.load(ckpt)
+        F, G, done = z["F"].copy(), z["G"].copy(), int(z["done"])
+        print(f"resumed at step {done}", flush=True)
+    t0 = time.time()
     while done < STEPS:
         k = min(chunk, STEPS - done)
         F, G, mac = O.run(p, k, F, G)
@@ -41,6 +47,9 @@ def main():
         if not np.all(np.isfinite(mac)):
             raise SystemExit(f"non-finite fields after {done} steps")
         print(f"{done}/{STEPS} steps, {time.time() - t0:.0f} s, {threads} threads", flush=True)
+        if ckpt and done % 500 == 0 and done < STEPS:
+            np.savez(ckpt + ".tmp.npz", F=F, G=G, done=done)
+            os.replace(ckpt + ".tmp.npz", ckpt)
     np.savez_compressed(
         OUT, steps=STEPS, n=N, Ra=RA, plane_y=64, plane_z=64,
         y64=mac[:, :, 64, :].astype(np.float32), z64=mac[:, 64, :, :].astype(np.float32),

@@ -216,3 +216,33 @@ def test_training_lowers_the_loss(net_mod, N):
     log(f"loss {losses[0]:.4e} -> {losses[-1]:.4e}")
     assert np.isfinite(losses).all() and losses[-1] < 0.3 * losses[0]
     net.close()
+
+
+def test_gradient_on_the_full_grid(net_mod, N):
+    """lbm_nn_gradient on the 64^3 grid the warm start trains on (one
+    sample), where every level has its production shape: the weight
+    gradients of levels 0-2 come from the brick kernel (16, 32 and 64 output
+    channels), the coarse convolutions from the split-k kernel.  The oracle's
+    backward pass runs on the GPU's own activations, so the remaining
+    difference is the BF16 rounding of the gradient tensors: relative L2
+    error of each layer's gradient below 2e-2 (as on the 16^3 grid)."""
+    log("case: nn gradient, grid 64, batch 1")
+    g = 64
+    theta = params(N, 17)
+    rng = np.random.default_rng(18)
+    tscale = [20.0, 20.0, 20.0, 1.0]
+    targets = (0.02 * rng.standard_normal((1, 4, g, g, g))).astype(np.float32)
+    lra = [4.4]
+    net = net_mod.WarmStartNet(g, 1, target_scale=tscale)
+    net.set_params(torch.from_numpy(theta.astype(np.float32)))
+    loss, grad = net.gradient(lra, torch.from_numpy(targets).cuda(), [0])
+    grad = to_np(grad).astype(np.float64)
+    tg = np.moveaxis(targets.astype(np.float64), 1, -1) * np.array(tscale)
+    x0 = to_bf16(N.inputs(lra, g))
+    a, out = gpu_cache(N, net_mod, net, 1, x0)
+    net.close()
+    same = per_layer_rel(N, grad, N.backward(theta, a, 2.0 * (out - tg) / out.size))
+    for name in same:
+        log(f"{name}: same activations rel {same[name][0]:.2e}")
+    bad = {k: v[0] for k, v in same.items() if not v[0] < 2e-2}
+    assert not bad, bad
