@@ -299,28 +299,32 @@ __global__ void __launch_bounds__(256) k_wgrad(WgradArgs a) {
 
 // Weight gradient on voxel bricks, for grids of at least 16 cells and
 // unmasked output gradients.  One block of 4 waves owns 16 input channels
-// (blockIdx.x) and every tap and output channel; it walks a range of bricks
-// of 16 x 2 x 1 voxels, one matrix-core k step of 32 voxels each.  Per brick
-// the input's 18 x 4 x 3 halo is loaded once (16-byte loads of 8 channels)
-// and written transposed into LDS three times, shifted by dx = -1, 0, +1,
-// so the B fragment of every tap (8 consecutive voxels of one channel) is one
-// aligned 16-byte read; the output gradient is transposed once, and its A
-// fragments serve all taps.  Wave w accumulates taps w, w + 4, ...  Results
-// go to FP32 with atomic adds; blocks of the first channel group also sum
-// the bias gradient.
-constexpr int kBrickCiStride = 3 * 4 * 16 + 8;  // one channel's halo rows, padded
+// (blockIdx.x) and every tap and output channel (RS * 16); it walks a range
+// of bricks of 16 x 4 x 2 voxels, four matrix-core k steps of 32 voxels (two
+// x rows of one plane each).  Per brick:
+//   - the input's 18 x 6 x 4 halo is loaded once: a thread takes 10
+//     consecutive x cells of one row and 8 channels (16-byte loads),
+//     transposes them in registers and writes, for dx = -1, 0, +1, the 8
+//     cells each shift needs as one 16-byte LDS store per channel, so the B
+//     fragment of every tap (8 consecutive cells of one channel) is one
+//     aligned 16-byte read;
+//   - the output gradient is transposed the same way (8 cells x 8 channels
+//     per thread), and its A fragments serve all taps.
+// Wave w accumulates taps w, w + 4, ...  Results go to FP32 with atomic
+// adds; blocks of the first channel group also sum the bias gradient.
+constexpr int kBrickRow = 4 * 6 * 16 + 8;  // one channel's halo (hz, hy, x), padded
 
 template <int RS>
 __global__ void __launch_bounds__(256) k_wgrad_brick(WgradArgs a, int64_t bricks_per_block) {
     constexpr int NT = 7;  // taps per wave: ceil(27 / 4)
-    __shared__ __attribute__((aligned(16))) __bf16 xs[3 * 16 * kBrickCiStride];
-    __shared__ __attribute__((aligned(16))) __bf16 dT[RS * 16][40];
+    __shared__ __attribute__((aligned(16))) __bf16 xs[3 * 16 * kBrickRow];
+    __shared__ __attribute__((aligned(16))) __bf16 dT[RS * 16][136];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r = lane & 15, q = lane >> 4;
     const int lg = a.lg, G = 1 << lg;
     const int c0 = blockIdx.x * 16;
-    const int bpr = G >> 4, rows2 = G >> 1;
-    const int64_t nbricks = (int64_t)a.n * G * rows2 * bpr;
+    const int nbx = G >> 4, nby = G >> 2, nbz = G >> 1;
+    const int64_t nbricks = (int64_t)a.n * nbz * nby * nbx;
     const int64_t b0 = (int64_t)blockIdx.y * bricks_per_block;
     const int64_t b1 = b0 + bricks_per_block < nbricks ? b0 + bricks_per_block : nbricks;
     floatx4 acc[NT][RS];
@@ -330,81 +334,95 @@ __global__ void __launch_bounds__(256) k_wgrad_brick(WgradArgs a, int64_t bricks
         for (int m = 0; m < RS; ++m) acc[j][m] = floatx4{0.f, 0.f, 0.f, 0.f};
     float bsum = 0.f;
     for (int64_t b = b0; b < b1; ++b) {
-        const int x0 = (int)(b % bpr) * 16;
-        int64_t rest = b / bpr;
-        const int y0 = (int)(rest % rows2) * 2;
-        rest /= rows2;
-        const int z = (int)(rest % G);
-        const int smp = (int)(rest / G);
-        // input halo: 18 x 4 x 3 voxels, two groups of 8 channels each
-        for (int t = tid; t < 432; t += 256) {
-            const int k8 = t & 1, hv = t >> 1;
-            const int hx = hv % 18, hy = (hv / 18) & 3, hz = hv / 72;
-            const int xx = x0 + hx - 1, yy = y0 + hy - 1, zz = z + hz - 1;
-            const int cc = c0 + k8 * 8;
-            bf16x8 v;
+        const int x0 = (int)(b % nbx) * 16;
+        int64_t rest = b / nbx;
+        const int y0 = (int)(rest % nby) * 4;
+        rest /= nby;
+        const int z0 = (int)(rest % nbz) * 2;
+        const int smp = (int)(rest / nbz);
+        if (tid < 96) {
+            // input halo row (hz, hy), x cells 8k .. 8k+9, channel group cg
+            // (the channel group is the slowest index, so the 8 lanes one LDS
+            // store cycle serves hit 8 different 4-bank groups)
+            const int cg = tid / 48, rem = tid - cg * 48;
+            const int k = rem & 1, hy = (rem >> 1) % 6, hz = (rem >> 1) / 6;
+            const int yy = y0 + hy - 1, zz = z0 + hz - 1, cc = c0 + cg * 8;
+            const bool row_ok = cc < a.cin && (unsigned)yy < (unsigned)G && (unsigned)zz < (unsigned)G;
+            bf16x8 v[10];
 #pragma unroll
-            for (int e = 0; e < 8; ++e) v[e] = (__bf16)0.f;
-            if (cc < a.cin && (unsigned)xx < (unsigned)G && (unsigned)yy < (unsigned)G &&
-                (unsigned)zz < (unsigned)G) {
-                if (cc < a.c1s) {
-                    const int64_t vi = ((((int64_t)smp << lg) + zz) << (2 * lg)) +
-                                       ((int64_t)yy << lg) + xx;
-                    v = *(const bf16x8*)(a.x1 + vi * a.c1s + cc);
-                } else {
-                    const int h = lg - 1;
-                    const int64_t vi = ((((int64_t)smp << h) + (zz >> 1)) << (2 * h)) +
-                                       ((int64_t)(yy >> 1) << h) + (xx >> 1);
-                    v = *(const bf16x8*)(a.x2 + vi * a.c2 + (cc - a.c1s));
+            for (int m = 0; m < 10; ++m) {
+                const int xx = x0 + 8 * k + m - 1;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) v[m][e] = (__bf16)0.f;
+                if (row_ok && (unsigned)xx < (unsigned)G) {
+                    if (cc < a.c1s) {
+                        const int64_t vi = ((((int64_t)smp << lg) + zz) << (2 * lg)) +
+                                           ((int64_t)yy << lg) + xx;
+                        v[m] = *(const bf16x8*)(a.x1 + vi * a.c1s + cc);
+                    } else {
+                        const int h = lg - 1;
+                        const int64_t vi = ((((int64_t)smp << h) + (zz >> 1)) << (2 * h)) +
+                                           ((int64_t)(yy >> 1) << h) + (xx >> 1);
+                        v[m] = *(const bf16x8*)(a.x2 + vi * a.c2 + (cc - a.c1s));
+                    }
                 }
             }
-            const int row = (hz * 4 + hy) * 16;
+            const int row = (hz * 6 + hy) * 16 + 8 * k;
 #pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                const int i = hx - d;
-                if (i >= 0 && i < 16) {
+            for (int d = 0; d < 3; ++d)
 #pragma unroll
-                    for (int e = 0; e < 8; ++e)
-                        xs[(d * 16 + k8 * 8 + e) * kBrickCiStride + row + i] = v[e];
+                for (int e = 0; e < 8; ++e) {
+                    bf16x8 w;
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) w[j] = v[j + d][e];
+                    *(bf16x8*)&xs[(d * 16 + cg * 8 + e) * kBrickRow + row] = w;
                 }
+        } else if (tid < 96 + 32 * RS) {
+            // output gradient: 8 cells (one k group) x 8 channels
+            const int t = tid - 96;
+            const int vg = t & 15, cg = t >> 4;
+            const int s = vg >> 2;  // k step
+            const int yy = y0 + (s & 1) * 2 + ((vg & 3) >> 1), zz = z0 + (s >> 1);
+            const int xb = x0 + (vg & 1) * 8;
+            const int64_t v0 = ((((int64_t)smp << lg) + zz) << (2 * lg)) + ((int64_t)yy << lg) + xb;
+            bf16x8 d[8];
+#pragma unroll
+            for (int m = 0; m < 8; ++m) {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) d[m][e] = (__bf16)0.f;
+                if (cg * 8 < a.ys) d[m] = *(const bf16x8*)(a.dy + (v0 + m) * a.ys + cg * 8);
             }
-        }
-        // output gradient of the brick's 32 voxels, transposed
-        for (int t = tid; t < RS * 2 * 32; t += 256) {
-            const int g8 = t >> 5, vi = t & 31;
-            const int64_t v = (((((int64_t)smp << lg) + z) << lg) + y0 + (vi >> 4)) * G + x0 +
-                              (vi & 15);
-            bf16x8 d;
 #pragma unroll
-            for (int e = 0; e < 8; ++e) d[e] = (__bf16)0.f;
-            if (g8 * 8 < a.ys) d = *(const bf16x8*)(a.dy + v * a.ys + g8 * 8);
+            for (int e = 0; e < 8; ++e) {
+                bf16x8 w;
 #pragma unroll
-            for (int e = 0; e < 8; ++e) dT[g8 * 8 + e][vi] = d[e];
+                for (int j = 0; j < 8; ++j) w[j] = d[j][e];
+                *(bf16x8*)&dT[cg * 8 + e][vg * 8] = w;
+            }
         }
         __syncthreads();
         if (blockIdx.x == 0 && tid < RS * 16) {
 #pragma unroll 8
-            for (int i = 0; i < 32; ++i) bsum += (float)dT[tid][i];
+            for (int i = 0; i < 128; ++i) bsum += (float)dT[tid][i];
         }
-        bf16x8 av[RS];
 #pragma unroll
-        for (int m = 0; m < RS; ++m) av[m] = *(const bf16x8*)&dT[m * 16 + r][q * 8];
+        for (int s = 0; s < 4; ++s) {
+            bf16x8 av[RS];
 #pragma unroll
-        for (int j = 0; j < NT; ++j) {
-            const int t = wave + 4 * j;
-            if (t < a.taps) {
-                int dz = 0, dy = 0, dx = 0;
-                if (a.taps == 27) {
-                    dz = t / 9 - 1;
-                    dy = (t / 3) % 3 - 1;
-                    dx = t % 3 - 1;
+            for (int m = 0; m < RS; ++m) av[m] = *(const bf16x8*)&dT[m * 16 + r][s * 32 + q * 8];
+#pragma unroll
+            for (int j = 0; j < NT; ++j) {
+                const int t = wave + 4 * j;
+                if (t < 27) {
+                    const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
+                    const int hz = (s >> 1) + dz + 1, hy = (s & 1) * 2 + (q >> 1) + dy + 1;
+                    const bf16x8 bv = *(const bf16x8*)&xs[((dx + 1) * 16 + r) * kBrickRow +
+                                                          (hz * 6 + hy) * 16 + (q & 1) * 8];
+#pragma unroll
+                    for (int m = 0; m < RS; ++m)
+                        acc[j][m] =
+                            __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[m], bv, acc[j][m], 0, 0, 0);
                 }
-                const bf16x8 bv = *(const bf16x8*)&xs[((dx + 1) * 16 + r) * kBrickCiStride +
-                                                      ((dz + 1) * 4 + (q >> 1) + dy + 1) * 16 +
-                                                      (q & 1) * 8];
-#pragma unroll
-                for (int m = 0; m < RS; ++m)
-                    acc[j][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[m], bv, acc[j][m], 0, 0, 0);
             }
         }
         __syncthreads();
@@ -416,14 +434,14 @@ __global__ void __launch_bounds__(256) k_wgrad_brick(WgradArgs a, int64_t bricks
 #pragma unroll
     for (int j = 0; j < NT; ++j) {
         const int t = wave + 4 * j;
-        if (t >= a.taps) continue;
+        if (t >= 27) continue;
 #pragma unroll
         for (int m = 0; m < RS; ++m)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int co = m * 16 + q * 4 + i;
                 if (co < a.cout)
-                    atomicAdd(&a.dw[((int64_t)co * a.taps + t) * a.cin_real + ci], acc[j][m][i]);
+                    atomicAdd(&a.dw[((int64_t)co * 27 + t) * a.cin_real + ci], acc[j][m][i]);
             }
     }
 }
@@ -813,14 +831,15 @@ hipError_t conv_backward_weight(const ConvGeom& g, const __bf16* x1, const __bf1
     a.ys = g.ys;
     a.relu = relu;
     a.cin_real = g.c1 + g.c2;
-    if (!relu && g.lg >= 4 && g.coutp == 16 && g.taps == 27 && g.cin >= 16) {
-        // bricks (measured faster only for 16 output channels: with more, the
-        // per-block atomics of all taps dominate): one block per 16 input
-        // channels and range of bricks, about 1024 blocks in all
+    if (!relu && g.lg >= 4 && g.taps == 27 && g.cin >= 16 &&
+        (g.coutp == 16 || g.coutp == 32 || g.coutp == 64)) {
+        // bricks: one block per 16 input channels and range of bricks; the
+        // number of blocks keeps the atomic adds of their partial sums (27 *
+        // 16 * coutp each) near 8e6
         const int chunks = ceil_div(g.cin, 16);
-        const int64_t nbricks = M / 32;
-        const int64_t groups =
-            std::max<int64_t>(1, std::min<int64_t>(std::max<int64_t>(1, nbricks / 4), 1024 / chunks));
+        const int64_t nbricks = M / 128;
+        const int64_t cap = std::max<int64_t>(1, 8000000 / (27 * 16 * (int64_t)g.coutp * chunks));
+        const int64_t groups = std::max<int64_t>(1, std::min<int64_t>(nbricks, cap));
         const int64_t per = (nbricks + groups - 1) / groups;
         const dim3 grid(chunks, (unsigned)ceil_div(nbricks, per));
         switch (g.coutp) {
