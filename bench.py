@@ -528,7 +528,8 @@ def main():
             "kernel": src["kernel"],
             "roofline": {"bound": "hbm", "achieved": round(src["achieved_GBs"], 1),
                          "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": round(src["frac_hbm_peak"], 4), "traffic": None},
+                         "frac": round(src["frac_hbm_peak"], 4),
+                         "traffic": recorded_traffic(args.n, "fp32_source")},
         },
         "batched": batched,
         "network": nn,
