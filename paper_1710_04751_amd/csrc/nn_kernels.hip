@@ -682,6 +682,123 @@ __global__ void k_cf_to_cl(const float* __restrict__ x, int n, int64_t V, int c,
     y[i] = x[(s * c + ch) * V + v];
 }
 
+// Forward / input-gradient convolution on LDS-staged bricks (3x3x3 taps,
+// BF16 output, grids of at least 32 cells, input channels a multiple of
+// 16).  A block of 4 waves computes 16 x 4 x 4 output voxels (wave w the
+// plane z0 + w, its four 16-voxel row tiles y0 .. y0 + 3) for NSUB * 16
+// output channels.  Per 16 input channels the block stages the 18 x 6 x 6
+// input halo channels-last in LDS (48 bytes per voxel: 16 channels and 8 of
+// padding, which puts the 16-byte reads of 8 consecutive lanes on distinct
+// banks), so every A fragment (8 channels of one voxel for one tap) is one
+// LDS read instead of a global load per tap.  A k step of 32 pairs two taps
+// of the 16 channels; B fragments are read from the packed weight ([co][k],
+// k = tap * cin + channel) and serve the four row tiles.
+constexpr int kCvVox = 24;                  // LDS elements per voxel
+constexpr int kCvHalo = 18 * 6 * 6;         // halo voxels
+
+template <int NSUB>
+__global__ void __launch_bounds__(256) k_conv_brick(ConvArgs a) {
+    __shared__ __attribute__((aligned(16))) __bf16 xs[kCvHalo * kCvVox];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r = lane & 15, q = lane >> 4;
+    const int lg = a.lg, G = 1 << lg;
+    const int nbx = G >> 4, nby = G >> 2;
+    int64_t bid = blockIdx.x;
+    const int x0 = (int)(bid % nbx) * 16;
+    bid /= nbx;
+    const int y0 = (int)(bid % nby) * 4;
+    bid /= nby;
+    const int z0 = (int)(bid % nby) * 4;
+    const int smp = (int)(bid / nby);
+    const int cobase = blockIdx.y * NSUB * 16;
+    floatx4 acc[4][NSUB];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int j = 0; j < NSUB; ++j) acc[m][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    const int ch = (q & 1) * 8;
+    for (int c0 = 0; c0 < a.cin; c0 += 16) {
+        for (int t = tid; t < 2 * kCvHalo; t += 256) {
+            const int half = t & 1, hv = t >> 1;
+            const int hx = hv % 18, hy = (hv / 18) % 6, hz = hv / 108;
+            const int xx = x0 + hx - 1, yy = y0 + hy - 1, zz = z0 + hz - 1;
+            const int cc = c0 + half * 8;
+            bf16x8 v;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) v[e] = (__bf16)0.f;
+            if ((unsigned)xx < (unsigned)G && (unsigned)yy < (unsigned)G &&
+                (unsigned)zz < (unsigned)G) {
+                if (cc < a.c1s) {
+                    const int64_t vi = ((((int64_t)smp << lg) + zz) << (2 * lg)) +
+                                       ((int64_t)yy << lg) + xx;
+                    v = *(const bf16x8*)(a.x1 + vi * a.c1s + cc);
+                } else {
+                    const int h = lg - 1;
+                    const int64_t vi = ((((int64_t)smp << h) + (zz >> 1)) << (2 * h)) +
+                                       ((int64_t)(yy >> 1) << h) + (xx >> 1);
+                    v = *(const bf16x8*)(a.x2 + vi * a.c2 + (cc - a.c1s));
+                }
+            }
+            *(bf16x8*)&xs[hv * kCvVox + half * 8] = v;
+        }
+        __syncthreads();
+#pragma unroll 2
+        for (int p = 0; p < 14; ++p) {
+            const int t = 2 * p + (q >> 1);  // this lane's tap
+            bf16x8 bv[NSUB];
+            bf16x8 av[4];
+            if (t < 27) {
+                const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
+#pragma unroll
+                for (int j = 0; j < NSUB; ++j)
+                    bv[j] = *(const bf16x8*)(a.w + (int64_t)(cobase + j * 16 + r) * a.kpad +
+                                             t * a.cin + c0 + ch);
+                const int base = ((wave + dz + 1) * 6 + dy + 1) * 18 + r + dx + 1;
+#pragma unroll
+                for (int m = 0; m < 4; ++m)
+                    av[m] = *(const bf16x8*)&xs[(base + m * 18) * kCvVox + ch];
+            } else {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+#pragma unroll
+                    for (int j = 0; j < NSUB; ++j) bv[j][e] = (__bf16)0.f;
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) av[m][e] = (__bf16)0.f;
+                }
+            }
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+#pragma unroll
+                for (int j = 0; j < NSUB; ++j)
+                    acc[m][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[m], bv[j], acc[m][j], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    // D rows 4q .. 4q+3 are x offsets, column r an output channel
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        const int64_t vrow = ((((int64_t)smp << lg) + z0 + wave) << (2 * lg)) +
+                             ((int64_t)(y0 + m) << lg) + x0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t vo = vrow + q * 4 + i;
+#pragma unroll
+            for (int j = 0; j < NSUB; ++j) {
+                const int co = cobase + j * 16 + r;
+                if (co < a.ys) {
+                    float val = 0.f;
+                    if (co < a.cout) {
+                        val = acc[m][j][i] + (a.bias ? a.bias[co] : 0.f);
+                        if (a.relu) val = fmaxf(val, 0.f);
+                        if (a.omask && !((float)a.omask[vo * a.ys + co] > 0.f)) val = 0.f;
+                    }
+                    ((__bf16*)a.out)[vo * a.ys + co] = (__bf16)val;
+                }
+            }
+        }
+    }
+}
+
 template <int MODE, int MT, int KS>
 hipError_t launch_conv_mt(const ConvArgs& a, int coutp, hipStream_t s) {
     const int64_t M = (int64_t)a.n << (3 * a.lg);
@@ -706,6 +823,18 @@ hipError_t launch_conv(const ConvArgs& a, int coutp, hipStream_t s) {
     const int64_t M = (int64_t)a.n << (3 * a.lg);
     const int sub = coutp / 16;
     const int nsub = sub % 4 == 0 ? 4 : sub % 3 == 0 ? 3 : sub % 2 == 0 ? 2 : 1;
+    if (MODE == 0 && a.taps == 27 && a.lg >= 5 && a.cin % 16 == 0 && !a.mask &&
+        a.kpad >= 27 * a.cin) {
+        const int64_t G = (int64_t)1 << a.lg;
+        const dim3 grid((unsigned)((G / 16) * (G / 4) * (G / 4) * a.n), sub / nsub);
+        switch (nsub) {
+            case 4: hipLaunchKernelGGL(k_conv_brick<4>, grid, dim3(256), 0, s, a); break;
+            case 3: hipLaunchKernelGGL(k_conv_brick<3>, grid, dim3(256), 0, s, a); break;
+            case 2: hipLaunchKernelGGL(k_conv_brick<2>, grid, dim3(256), 0, s, a); break;
+            default: hipLaunchKernelGGL(k_conv_brick<1>, grid, dim3(256), 0, s, a); break;
+        }
+        return hipGetLastError();
+    }
     const int64_t waves4 = (int64_t)ceil_div(M, 64) * (sub / nsub);
     if (waves4 >= 2048) return launch_conv_mt<MODE, 4, 1>(a, coutp, s);
     const int64_t waves1 = (int64_t)ceil_div(M, 16) * (sub / nsub);

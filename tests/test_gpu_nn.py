@@ -72,16 +72,18 @@ def layer_input(N, name, acts, x0):
     return acts[order[order.index(name) - 1]]
 
 
-def test_each_layer_matches_oracle_on_gpu_inputs(net_mod, N):
-    log("case: nn per-layer forward, grid 16")
+@pytest.mark.parametrize("grid", [16, 32])
+def test_each_layer_matches_oracle_on_gpu_inputs(net_mod, N, grid):
+    """grid 32 puts the finest level on the LDS-staged brick convolution."""
+    log(f"case: nn per-layer forward, grid {grid}")
     theta = params(N, 11)
-    net = net_mod.WarmStartNet(GRID, 2)
+    net = net_mod.WarmStartNet(grid, 2)
     net.set_params(torch.from_numpy(theta.astype(np.float32)))
     net.forward(LRA)
     acts = {}
     for i, name in enumerate(net_mod.LAYER_NAMES):
         acts[name] = to_np(net.activation(i, 2)).astype(np.float64)
-    x0 = to_bf16(N.inputs(LRA, GRID))
+    x0 = to_bf16(N.inputs(LRA, grid))
     P = N.unflatten(theta)
     for name, ci, co, k, relu in N.LAYERS:
         x = layer_input(N, name, acts, x0)
