@@ -79,9 +79,11 @@ def converged(how):
     return how in (capi.LBM_STEADY_TOL, capi.LBM_STEADY_PLATEAU)
 
 
-def train(net, log10_ra, targets, epochs, batch, lr, seed=0, log=print):
-    """Adam over shuffled mini-batches with a cosine decay of the step size
-    from lr to lr/20.  Returns the per-epoch mean losses and timing."""
+def train(net, log10_ra, targets, epochs, batch, lr, seed=0, log=print, warmup=0.05):
+    """Adam over shuffled mini-batches: the step size ramps linearly up to lr
+    over the first `warmup` fraction of the steps (large first Adam steps can
+    switch off whole ReLU layers), then decays along a cosine to lr/20.
+    Returns the per-epoch mean losses and timing."""
     rng = np.random.default_rng(seed)
     n = len(log10_ra)
     lra = np.asarray(log10_ra, dtype=np.float64)
@@ -96,7 +98,8 @@ def train(net, log10_ra, targets, epochs, batch, lr, seed=0, log=print):
         losses = []
         for i in range(0, n, batch):
             idx = perm[i:i + batch]
-            net.set_lr(lr * (0.05 + 0.95 * 0.5 * (1 + math.cos(math.pi * k / total))))
+            ramp = min(1.0, (k + 1) / max(1.0, warmup * total))
+            net.set_lr(ramp * lr * (0.05 + 0.95 * 0.5 * (1 + math.cos(math.pi * k / total))))
             want = ep == epochs - 1 or ep % 10 == 0
             l = net.train_step(lra[idx].tolist(), targets, idx.tolist(), want_loss=want)
             if want:
