@@ -340,7 +340,7 @@ def warm_start(log=print):
             "cold_steps_median", "warm_steps_median", "cold_steps_mean", "warm_steps_mean",
             "steps_ratio_median", "nu_rel_diff_max", "fallbacks", "cold_solve_s", "warm_solve_s")
     out = {k: r[k] for k in keys}
-    out["workload"] = ("64^3 cavities, Ra log-uniform in [1e3, 4e4], 200 training (seed 17101) "
+    out["workload"] = ("64^3 cavities, Ra log-uniform in [1e3, 1e5], 200 training (seed 17101) "
                        "and 50 held-out (seed 17102) Rayleigh numbers, D3Q7, FP32 solver, "
                        "stable rate set; network BF16/FP32-accumulate on the matrix cores")
     out["unit"] = "steps to the steady rule"

@@ -138,7 +138,7 @@ def validation_loss(net, log10_ra, targets):
     return tot / n
 
 
-def study(grid=64, n_train=200, n_test=50, ra_range=(1e3, 4e4), epochs=200, batch=8, lr=2e-3,
+def study(grid=64, n_train=200, n_test=50, ra_range=(1e3, 1e5), epochs=200, batch=8, lr=2e-3,
           seeds=(17101, 17102), init_seed=1, max_steps=600_000, precision="fp32", log=print):
     """The whole warm-start experiment: steady training and test sets from
     rest (the cold solves), training, then every test cavity solved again
