@@ -683,7 +683,7 @@ __global__ void k_cf_to_cl(const float* __restrict__ x, int n, int64_t V, int c,
 }
 
 // Forward / input-gradient convolution on LDS-staged bricks (3x3x3 taps,
-// BF16 output, grids of at least 32 cells, input channels a multiple of
+// BF16 output, grids of at least 16 cells, input channels a multiple of
 // 16).  A block of 4 waves computes 16 x 4 x 4 output voxels (wave w the
 // plane z0 + w, its four 16-voxel row tiles y0 .. y0 + 3) for NSUB * 16
 // output channels.  Per 16 input channels the block stages the 18 x 6 x 6
@@ -823,11 +823,13 @@ hipError_t launch_conv(const ConvArgs& a, int coutp, hipStream_t s) {
     const int64_t M = (int64_t)a.n << (3 * a.lg);
     const int sub = coutp / 16;
     const int nsub = sub % 4 == 0 ? 4 : sub % 3 == 0 ? 3 : sub % 2 == 0 ? 2 : 1;
-    if (MODE == 0 && a.taps == 27 && a.lg >= 5 && a.cin % 16 == 0 && !a.mask &&
+    if (MODE == 0 && a.taps == 27 && a.lg >= 4 && a.cin % 16 == 0 && !a.mask &&
         a.kpad >= 27 * a.cin) {
+        // on the 16-cell grid one output-channel group per block, for blocks
         const int64_t G = (int64_t)1 << a.lg;
-        const dim3 grid((unsigned)((G / 16) * (G / 4) * (G / 4) * a.n), sub / nsub);
-        switch (nsub) {
+        const int nb = a.lg >= 5 ? nsub : 1;
+        const dim3 grid((unsigned)((G / 16) * (G / 4) * (G / 4) * a.n), sub / nb);
+        switch (nb) {
             case 4: hipLaunchKernelGGL(k_conv_brick<4>, grid, dim3(256), 0, s, a); break;
             case 3: hipLaunchKernelGGL(k_conv_brick<3>, grid, dim3(256), 0, s, a); break;
             case 2: hipLaunchKernelGGL(k_conv_brick<2>, grid, dim3(256), 0, s, a); break;
