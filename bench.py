@@ -264,12 +264,22 @@ def block_planes(mac, planes):
 
 
 def field_errors(a, b):
-    """Normalised max errors per field of [5][...] arrays (rho as rho - 1)."""
+    """Errors per field of [5][...] arrays: max and root-mean-square of a - b,
+    each normalised by max |b| (rho by max |rho - 1|, the velocity components
+    by the largest reference velocity component)."""
     names = ("rho", "ux", "uy", "uz", "T")
+    umax = max(float(b[i].abs().max()) for i in (1, 2, 3))
     out = {}
     for i, k in enumerate(names):
-        ref = b[i] - 1.0 if k == "rho" else b[i]
-        out[k] = float((a[i] - b[i]).abs().max() / ref.abs().max())
+        if k == "rho":
+            scale = float((b[i] - 1.0).abs().max())
+        elif k == "T":
+            scale = float(b[i].abs().max())
+        else:
+            scale = umax
+        d = a[i] - b[i]
+        out[k] = float(d.abs().max()) / scale
+        out[k + "_rms"] = float(d.pow(2).mean().sqrt()) / scale
     return out
 
 
@@ -315,10 +325,7 @@ def precision_study(steps=10_000, log=print):
                      "seconds": round(secs, 2), "steps": steps}
         full[prec] = mac
         log(f"precision study {prec}: vs 128^3 oracle {out[prec]['vs_oracle128']}")
-    d = {}
-    for i, k in enumerate(("rho", "ux", "uy", "uz", "T")):
-        ref32 = full["fp32"][i] - 1.0 if k == "rho" else full["fp32"][i]
-        d[k] = float((full["fp16"][i] - full["fp32"][i]).abs().max() / ref32.abs().max())
+    d = field_errors(full["fp16"], full["fp32"])
     out["fp16_vs_fp32"] = d
     log(f"precision study: fp16 vs fp32 over all cells {d}")
     out["workload"] = ("512^3, Ra 1e6, D3Q7, from rest, 10,000 steps, stable rate set; reference "
