@@ -53,12 +53,12 @@ def algorithmic_bytes_per_cell(precision, qt=7):
     return 2 * (15 + qt) * vb
 
 
-def time_variant(n, ra, precision, steps, warmup, block=None, log=print, R=0.0):
+def time_variant(n, ra, precision, steps, warmup, block=None, log=print, R=0.0, sr=0):
     import torch
     from paper_1710_04751_amd import solver as S
 
     stream = torch.cuda.Stream()
-    params = S.make_params(n, ra, precision=precision, R=R)
+    params = S.make_params(n, ra, precision=precision, R=R, round_stochastic=sr)
     if block:
         params.block_x, params.block_y = block
     cav = S.Cavity(params, stream=stream)
@@ -302,8 +302,10 @@ def precision_study(steps=10_000, log=print):
     ry = torch.from_numpy(ref["y64"].astype(np.float64)).cuda()
     rz = torch.from_numpy(ref["z64"].astype(np.float64)).cuda()
     out, full = {}, {}
-    for prec in ("fp32", "fp16"):
-        cav = S.Cavity(S.make_params(512, 1e6, precision=prec, **W.STABLE_RATES))
+    for prec in ("fp32", "fp16", "fp16_sr"):
+        sr = 1 if prec == "fp16_sr" else 0
+        cav = S.Cavity(S.make_params(512, 1e6, precision=prec[:4], round_stochastic=sr,
+                                     **W.STABLE_RATES))
         t0 = time.perf_counter()
         done = 0
         while done < steps:
@@ -327,6 +329,8 @@ def precision_study(steps=10_000, log=print):
         log(f"precision study {prec}: vs 128^3 oracle {out[prec]['vs_oracle128']}")
     d = field_errors(full["fp16"], full["fp32"])
     out["fp16_vs_fp32"] = d
+    out["fp16_sr_vs_fp32"] = field_errors(full["fp16_sr"], full["fp32"])
+    log(f"precision study: fp16 (stochastic rounding) vs fp32 {out['fp16_sr_vs_fp32']}")
     log(f"precision study: fp16 vs fp32 over all cells {d}")
     out["workload"] = ("512^3, Ra 1e6, D3Q7, from rest, 10,000 steps, stable rate set; reference "
                        "128^3 FP64 oracle, 2,500 steps (same t u0 / L), mid-planes y = 64, z = 64 "
@@ -481,6 +485,9 @@ def main():
     f16_steps = args.fp16_steps if args.fp16_steps is not None else args.steps
     f16 = time_variant(args.n, args.Ra, "fp16", f16_steps, args.warmup, block, log)
     log(json.dumps(f16))
+    f16sr = time_variant(args.n, args.Ra, "fp16", min(f16_steps, 2000), args.warmup, block, log,
+                         sr=1)
+    log(json.dumps(f16sr))
     src = None
     if args.source_steps > 0:
         src = time_variant(args.n, args.Ra, "fp32", args.source_steps, args.warmup, block, log,
@@ -528,6 +535,10 @@ def main():
                          "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": round(f16["frac_hbm_peak"], 4),
                          "traffic": recorded_traffic(args.n, "fp16")},
+            "stochastic_rounding": {"value": round(f16sr["mlups"], 1), "unit": "MLUPS",
+                                    "steps": min(f16_steps, 2000),
+                                    "ms_per_step": f16sr["ms_per_step"],
+                                    "frac": round(f16sr["frac_hbm_peak"], 4)},
         },
         "heat_source": None if src is None else {
             "value": round(src["mlups"], 1), "unit": "MLUPS", "steps": args.source_steps,

@@ -86,7 +86,10 @@ typedef struct lbm_params {
                                L = nx; 1: take nu, alpha, gbeta below as given */
     int32_t block_x;        /* threads per block along x (0 = default) */
     int32_t block_y;        /* threads per block along y (0 = default) */
-    int32_t reserved0;
+    int32_t round_stochastic; /* FP16 storage only: 0 = round to nearest even
+                                 (default), 1 = stochastic rounding (unbiased,
+                                 keyed by step, population and cell; not in
+                                 batches) */
     double nu, alpha, gbeta; /* used only when lattice_units == 1 */
 } lbm_params;
 

@@ -23,7 +23,7 @@ class lbm_params(ctypes.Structure):
         ("omega_bulk", ctypes.c_double), ("omega_hi", ctypes.c_double),
         ("omega_hi_T", ctypes.c_double), ("R", ctypes.c_double),
         ("lattice_units", ctypes.c_int32), ("block_x", ctypes.c_int32),
-        ("block_y", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+        ("block_y", ctypes.c_int32), ("round_stochastic", ctypes.c_int32),
         ("nu", ctypes.c_double), ("alpha", ctypes.c_double), ("gbeta", ctypes.c_double),
     ]
 

@@ -90,6 +90,10 @@ bool validate(const lbm_params* p, lbm_lattice* L, std::string* why) {
         *why = "unknown precision";
         return false;
     }
+    if (p->round_stochastic != 0 && (p->round_stochastic != 1 || p->precision != LBM_FP32_S16)) {
+        *why = "round_stochastic is 0, or 1 with FP16 storage";
+        return false;
+    }
     if (!std::isfinite(p->R)) {
         *why = "the scalar source R must be finite";
         return false;
@@ -201,6 +205,8 @@ lbm_status make_handle(const lbm_params* p, void* workspace, size_t bytes, void*
     h->c.src = p->R;
     h->c.alpha = L.alpha;
     h->c.fourth_maxwell = p->fourth_maxwell;
+    h->c.sr = p->round_stochastic;
+    h->c.seed = 0;
     int bx = p->block_x, by = p->block_y;
     if (!bx || !by) default_block(p->nx, &bx, &by);
     set_geom(h, bx, by);
@@ -321,6 +327,7 @@ lbm_status lbm_step(lbm_handle* h, int64_t nsteps) {
     if (nsteps < 0) return fail(LBM_ERR_ARG, "nsteps must be >= 0");
     const Prec pr = (Prec)h->p.precision;
     for (int64_t i = 0; i < nsteps; ++i) {
+        h->c.seed = (uint32_t)h->steps;
         hipError_t e = launch_step(pr, h->p.thermal_q, h->general, h->geom, h->lay.ps,
                                    h->buf(h->cur), h->buf(1 - h->cur), h->c, h->stream);
         if (e != hipSuccess) return hip_fail(e, "step");

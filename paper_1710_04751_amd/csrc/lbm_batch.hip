@@ -184,6 +184,10 @@ bool batch_layout(const lbm_params* p, int n, BatchLayout* L, std::string* why) 
                    "(higher-order rates other than 1 or a scalar source)";
             return false;
         }
+        if (p[i].round_stochastic) {
+            *why = "stochastic rounding is not available in batches";
+            return false;
+        }
         if (p[i].nx > 1024 || p[i].nz > 1023 || p[i].ny > 16383) {
             *why = "batch members need nx <= 1024, ny <= 16383, nz <= 1023";
             return false;
@@ -254,6 +258,8 @@ void fill_kcoef(const lbm_handle* h, KCoef<R>* k) {
     k->t.omega_hiT = (R)h->c.omega_hiT;
     k->t.cs2 = (R)h->c.cs2;
     k->t.src = (R)h->c.src;
+    k->sr = 0;  // batches refuse stochastic rounding
+    k->seed = 0;
     k->T_hot = (R)h->c.T_hot;
     k->T_cold = (R)h->c.T_cold;
     const double cs2 = h->c.cs2;

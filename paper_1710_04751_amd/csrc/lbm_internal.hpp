@@ -23,6 +23,8 @@ struct Coefs {
     double src;                          // uniform scalar source R
     double alpha;                        // for the Nusselt number
     int32_t fourth_maxwell;
+    int32_t sr;                          // FP16 storage: stochastic rounding
+    uint32_t seed;                       // step index, the random stream's key
 };
 
 // One stored state (A or B): populations a of cell c at base[a*ps + c].

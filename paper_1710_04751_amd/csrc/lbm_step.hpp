@@ -7,6 +7,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "lbm_device.hpp"
 #include "lbm_internal.hpp"
 
@@ -50,6 +52,34 @@ struct Store<_Float16> {
         __builtin_nontemporal_store((_Float16)v, p);  // round to nearest even
     }
 };
+
+// Stochastic rounding to FP16: v goes to the FP16 neighbour below or above
+// with probabilities proportional to its distance from the other, so the
+// rounding is unbiased.  ulp = 2^(e - 10) with e the exponent of |v|
+// (at least -14: FP16 subnormals); |v| / ulp and the floor are exact in
+// FP32, and the result is an FP16 value.  rnd: 16 random bits (the
+// probabilities are resolved to 2^-16 of an ulp).
+__device__ __forceinline__ _Float16 half_stochastic(float v, uint32_t rnd) {
+    int e = (int)((__float_as_uint(v) >> 23) & 0xffu) - 127;
+    e = e < -14 ? -14 : e;
+    const float ulp = __uint_as_float((uint32_t)(e - 10 + 127) << 23);
+    const float inv = __uint_as_float((uint32_t)(10 - e + 127) << 23);
+    const float u = (float)(rnd & 0xffffu) * (1.0f / 65536.0f);
+    const float r = floorf(fabsf(v) * inv + u) * ulp;
+    return (_Float16)copysignf(r, v);
+}
+
+// 32-bit integer mix (the "lowbias32" finaliser of C. Wellons' hash
+// prospector): the random stream of stochastic rounding, keyed by step,
+// population and cell.
+__device__ __forceinline__ uint32_t mix32(uint32_t x) {
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
 
 // Range-checked population access.  Every load and store of the step kernel
 // goes through a raw buffer resource whose record count is the byte size of
@@ -105,6 +135,8 @@ struct KCoef {
     ThermCoef<R> t;
     R T_hot, T_cold;
     R w_face, w_corner;  // rest weights of the scalar (anti-bounce-back)
+    int32_t sr;          // FP16 storage: stochastic rounding
+    uint32_t seed;       // step index
 };
 
 template <typename R>
@@ -120,6 +152,8 @@ KCoef<R> make_kcoef(const Coefs& c, int qt) {
     k.t.omega_hiT = (R)c.omega_hiT;
     k.t.cs2 = (R)c.cs2;
     k.t.src = (R)c.src;
+    k.sr = c.sr;
+    k.seed = c.seed;
     k.T_hot = (R)c.T_hot;
     k.T_cold = (R)c.T_cold;
     if (qt == 7) {
@@ -193,6 +227,24 @@ __device__ __forceinline__ void update_cell(const S* __restrict__ Fi, const S* _
     else
         collide_thermal15<R, HG>(gq, ux, uy, uz, k.t);
 
+    if constexpr (std::is_same<S, _Float16>::value) {
+        if (k.sr) {
+            // one 32-bit draw gives the 16 random bits of two stores
+            const uint32_t key = mix32(k.seed * 0x9e3779b9u ^ cell);
+            uint32_t rnd[(15 + QT + 1) / 2];
+#pragma unroll
+            for (int j = 0; j < (15 + QT + 1) / 2; ++j) rnd[j] = mix32(key + (uint32_t)j * 0x85ebca77u);
+#pragma unroll
+            for (int a = 0; a < 15; ++a)
+                Buf<S>::st(pop_rsrc(Fo + a * ps, pb), cell,
+                           (float)half_stochastic(d[a], rnd[a >> 1] >> (16 * (a & 1))));
+#pragma unroll
+            for (int a = 0; a < QT; ++a)
+                Buf<S>::st(pop_rsrc(Go + a * ps, pb), cell,
+                           (float)half_stochastic(gq[a], rnd[(a + 15) >> 1] >> (16 * ((a + 15) & 1))));
+            return;
+        }
+    }
 #pragma unroll
     for (int a = 0; a < 15; ++a) Buf<S>::st(pop_rsrc(Fo + a * ps, pb), cell, d[a]);
 #pragma unroll

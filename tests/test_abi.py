@@ -55,6 +55,7 @@ def test_params_defaults_and_lattice_mapping(capi):
     ("nx", 3, ">= 4"), ("thermal_q", 9, "7 or 15"), ("R", float("inf"), "source"),
     ("u0", 0.2, "0.3"), ("omega_hi", 2.0, "(0, 2)"), ("precision", 7, "precision"),
     ("block_x", 48, "multiple of 64"), ("Pr", -1.0, "positive"),
+    ("round_stochastic", 1, "round_stochastic"),
 ])
 def test_invalid_parameters_are_rejected(capi, field, value, msg):
     p = capi.lbm_params_init(16, 1e3)

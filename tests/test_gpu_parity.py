@@ -71,6 +71,22 @@ def test_small_cavity_fp16_storage(solver, small_case_oracle):
     cav.close()
 
 
+def test_small_cavity_fp16_stochastic_rounding(solver, small_case_oracle):
+    """FP16 storage with stochastic rounding: each store errs by less than one
+    FP16 ulp, without bias, so the per-step errors of T (7 populations,
+    |g| <= 0.08) random-walk exactly as the round-to-nearest estimate above
+    assumes; the same bound applies (T 3e-2, u 1e-2, rho 1e-4)."""
+    p, F, G, mac = small_case_oracle
+    log("case: 16^3 Ra=1e3 D3Q7 2000 steps fp16 storage, stochastic rounding")
+    cav = solver.Cavity(solver.make_params(16, 1e3, precision="fp16", round_stochastic=1))
+    cav.step(2000)
+    m = {k: to_np(v) for k, v in cav.macros(fp64=True).items()}
+    err = field_errors(m, mac)
+    log("fp16 stochastic", err)
+    assert err["T"] <= 3e-2 and err["rho"] <= 1e-4 and err["u"] <= 1e-2
+    cav.close()
+
+
 def _lattice_params(solver, oracle_p, prec, qt, **extra):
     """GPU parameters with the oracle's lattice values (lattice units)."""
     nu = (1 / oracle_p.omega_nu - 0.5) / 3
