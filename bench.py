@@ -454,6 +454,8 @@ def main():
     ap.add_argument("--batched-steps", type=int, default=2000)
     ap.add_argument("--block", type=str, default=None, help="bx,by of the step kernel")
     ap.add_argument("--no-nn", action="store_true", help="skip the network throughput leg")
+    ap.add_argument("--sr-steps", type=int, default=2000,
+                    help="timed steps of the FP16 stochastic-rounding line; 0 skips it")
     ap.add_argument("--source-steps", type=int, default=1000,
                     help="timed steps of the heat-source line (general kernels); 0 skips it")
     ap.add_argument("--no-precision", action="store_true",
@@ -485,9 +487,10 @@ def main():
     f16_steps = args.fp16_steps if args.fp16_steps is not None else args.steps
     f16 = time_variant(args.n, args.Ra, "fp16", f16_steps, args.warmup, block, log)
     log(json.dumps(f16))
-    f16sr = time_variant(args.n, args.Ra, "fp16", min(f16_steps, 2000), args.warmup, block, log,
-                         sr=1)
-    log(json.dumps(f16sr))
+    f16sr = None
+    if args.sr_steps > 0:
+        f16sr = time_variant(args.n, args.Ra, "fp16", args.sr_steps, args.warmup, block, log, sr=1)
+        log(json.dumps(f16sr))
     src = None
     if args.source_steps > 0:
         src = time_variant(args.n, args.Ra, "fp32", args.source_steps, args.warmup, block, log,
@@ -535,10 +538,9 @@ def main():
                          "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": round(f16["frac_hbm_peak"], 4),
                          "traffic": recorded_traffic(args.n, "fp16")},
-            "stochastic_rounding": {"value": round(f16sr["mlups"], 1), "unit": "MLUPS",
-                                    "steps": min(f16_steps, 2000),
-                                    "ms_per_step": f16sr["ms_per_step"],
-                                    "frac": round(f16sr["frac_hbm_peak"], 4)},
+            "stochastic_rounding": None if f16sr is None else {
+                "value": round(f16sr["mlups"], 1), "unit": "MLUPS", "steps": args.sr_steps,
+                "ms_per_step": f16sr["ms_per_step"], "frac": round(f16sr["frac_hbm_peak"], 4)},
         },
         "heat_source": None if src is None else {
             "value": round(src["mlups"], 1), "unit": "MLUPS", "steps": args.source_steps,
