@@ -197,3 +197,27 @@ def test_batch_with_source_equals_single_runs(solver):
         assert torch.equal(Fs, Fb) and torch.equal(Gs, Gb), i
         cav.close()
     batch.close()
+
+
+def test_source_conduction_converges_to_the_parabola(solver):
+    """No flow (g beta = 0), both walls at T = 0, uniform source: the steady
+    profile across the box is T = R xi (L - xi) / (2 alpha), xi = x + 1/2
+    (the adiabatic side walls keep it one-dimensional).  FP64 runs to the
+    steady rule on L = 16, 32 and 64: the relative error falls 4x per
+    doubling (second order) and is below 3e-4 at L = 64."""
+    R, errs = 1e-4, []
+    for n in (16, 32, 64):
+        p = solver.make_params(nx=n, ny=4, nz=4, precision="fp64", lattice_units=1,
+                               nu=0.1, alpha=1 / 6, gbeta=0.0, T_hot=0.0, T_cold=0.0, R=R)
+        cav = solver.Cavity(p)
+        steps, how, res = cav.run_to_steady(tol=1e-13, check_every=500,
+                                            max_steps=int(40 * n * n))
+        T = to_np(cav.macros(fp64=True)["T"])
+        cav.close()
+        xi = np.arange(n) + 0.5
+        exact = R * xi * (n - xi) / (2 * (1 / 6))
+        err = np.max(np.abs(T - exact[None, None, :])) / np.max(exact)
+        log(f"L {n}: steps {steps} ({how}), residual {res:.1e}, rel err {err:.3e}")
+        errs.append(err)
+    assert errs[-1] < 3e-4
+    assert 3.5 < errs[0] / errs[1] < 4.5 and 3.5 < errs[1] / errs[2] < 4.5

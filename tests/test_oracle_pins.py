@@ -493,3 +493,24 @@ def test_source_heat_balance_in_the_cavity(oracle, qt):
         F, G, mac = oracle.run(p, 1, F, G)
         assert abs(mac[4].sum() - s0 - (p.R * V + q_in)) < 1e-12
         assert abs(q_in) > 1e-3  # the walls do carry heat here
+
+
+@pytest.mark.parametrize("qt", [7, 15])
+def test_source_conduction_converges_to_the_parabola(oracle, qt):
+    """Steady conduction with a uniform source between two walls at T = 0
+    (walls at xi = 0 and N, xi = x + 1/2, no flow): the CDE's solution is
+    T = R xi (N - xi) / (2 alpha).  The scheme converges to it at second
+    order: the absolute error stays near a fixed multiple of R while T
+    grows as N^2, so the relative error drops 4x per doubling of N."""
+    errs = []
+    for n in (8, 16, 32):
+        p = oracle.Params(nx=n, ny=1, nz=1, qt=qt, periodic=6, omega_nu=1.2, omega_T=1.0,
+                          gbeta=0.0, T_hot=0.0, T_cold=0.0, R=1e-4)
+        alpha = p.cs2T * (1 / p.omega_T - 0.5)
+        F, G = oracle.rest_state(p)
+        F, G, mac = oracle.run(p, int(14 * n * n / (math.pi ** 2 * alpha)), F, G)
+        xi = np.arange(n) + 0.5
+        exact = p.R * xi * (n - xi) / (2 * alpha)
+        errs.append(np.max(np.abs(mac[4][0, 0] - exact)) / np.max(exact))
+    assert errs[-1] < 2e-3
+    assert 3.5 < errs[0] / errs[1] < 4.5 and 3.5 < errs[1] / errs[2] < 4.5
