@@ -53,12 +53,12 @@ def algorithmic_bytes_per_cell(precision, qt=7):
     return 2 * (15 + qt) * vb
 
 
-def time_variant(n, ra, precision, steps, warmup, block=None, log=print, R=0.0, sr=0):
+def time_variant(n, ra, precision, steps, warmup, block=None, log=print, R=0.0, sr=0, qt=7):
     import torch
     from paper_1710_04751_amd import solver as S
 
     stream = torch.cuda.Stream()
-    params = S.make_params(n, ra, precision=precision, R=R, round_stochastic=sr)
+    params = S.make_params(n, ra, precision=precision, R=R, round_stochastic=sr, thermal_q=qt)
     if block:
         params.block_x, params.block_y = block
     cav = S.Cavity(params, stream=stream)
@@ -95,7 +95,7 @@ def time_variant(n, ra, precision, steps, warmup, block=None, log=print, R=0.0, 
     ncell = n ** 3
     launch_ms = ms / steps
     mlups = ncell * steps / (ms * 1e-3) / 1e6
-    bpc = algorithmic_bytes_per_cell(precision)
+    bpc = algorithmic_bytes_per_cell(precision, qt)
     achieved = bpc * ncell / (launch_ms * 1e-3) / 1e9
     out = {
         "precision": precision, "kernel": kname, "steps": steps, "warmup": warmup,
@@ -456,6 +456,8 @@ def main():
     ap.add_argument("--no-nn", action="store_true", help="skip the network throughput leg")
     ap.add_argument("--sr-steps", type=int, default=2000,
                     help="timed steps of the FP16 stochastic-rounding line; 0 skips it")
+    ap.add_argument("--q15-steps", type=int, default=1000,
+                    help="timed steps of the D3Q15-scalar line; 0 skips it")
     ap.add_argument("--source-steps", type=int, default=1000,
                     help="timed steps of the heat-source line (general kernels); 0 skips it")
     ap.add_argument("--no-precision", action="store_true",
@@ -491,6 +493,10 @@ def main():
     if args.sr_steps > 0:
         f16sr = time_variant(args.n, args.Ra, "fp16", args.sr_steps, args.warmup, block, log, sr=1)
         log(json.dumps(f16sr))
+    q15 = None
+    if args.q15_steps > 0:
+        q15 = time_variant(args.n, args.Ra, "fp32", args.q15_steps, args.warmup, block, log, qt=15)
+        log(json.dumps(q15))
     src = None
     if args.source_steps > 0:
         src = time_variant(args.n, args.Ra, "fp32", args.source_steps, args.warmup, block, log,
@@ -541,6 +547,15 @@ def main():
             "stochastic_rounding": None if f16sr is None else {
                 "value": round(f16sr["mlups"], 1), "unit": "MLUPS", "steps": args.sr_steps,
                 "ms_per_step": f16sr["ms_per_step"], "frac": round(f16sr["frac_hbm_peak"], 4)},
+        },
+        "thermal_d3q15": None if q15 is None else {
+            "value": round(q15["mlups"], 1), "unit": "MLUPS", "steps": args.q15_steps,
+            "storage": "fp32", "ms_per_step": q15["ms_per_step"], "kernel": q15["kernel"],
+            "bytes_per_cell_update": q15["bytes_per_cell_update"],
+            "roofline": {"bound": "hbm", "achieved": round(q15["achieved_GBs"], 1),
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(q15["frac_hbm_peak"], 4),
+                         "traffic": recorded_traffic(args.n, "fp32_q15")},
         },
         "heat_source": None if src is None else {
             "value": round(src["mlups"], 1), "unit": "MLUPS", "steps": args.source_steps,
