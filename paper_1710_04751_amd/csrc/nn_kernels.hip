@@ -333,74 +333,82 @@ __global__ void __launch_bounds__(256) k_wgrad_brick(WgradArgs a, int64_t bricks
 #pragma unroll
         for (int m = 0; m < RS; ++m) acc[j][m] = floatx4{0.f, 0.f, 0.f, 0.f};
     float bsum = 0.f;
-    for (int64_t b = b0; b < b1; ++b) {
+    // Roles: threads 0-95 load input halo rows, the next 32 * RS the output
+    // gradient.  The global loads of brick b + 1 are issued into registers
+    // before the matrix-core phase of brick b, so their latency is hidden.
+    const int cgx = tid / 48, remx = tid - cgx * 48;
+    const int kx = remx & 1, hyx = (remx >> 1) % 6, hzx = (remx >> 1) / 6;
+    const int td = tid - 96, vgd = td & 15, cgd = td >> 4, sd = vgd >> 2;
+    bf16x8 reg[10];
+    auto fetch = [&](int64_t b) __attribute__((always_inline)) {
         const int x0 = (int)(b % nbx) * 16;
         int64_t rest = b / nbx;
         const int y0 = (int)(rest % nby) * 4;
         rest /= nby;
         const int z0 = (int)(rest % nbz) * 2;
         const int smp = (int)(rest / nbz);
+#pragma unroll
+        for (int m = 0; m < 10; ++m)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) reg[m][e] = (__bf16)0.f;
         if (tid < 96) {
             // input halo row (hz, hy), x cells 8k .. 8k+9, channel group cg
             // (the channel group is the slowest index, so the 8 lanes one LDS
             // store cycle serves hit 8 different 4-bank groups)
-            const int cg = tid / 48, rem = tid - cg * 48;
-            const int k = rem & 1, hy = (rem >> 1) % 6, hz = (rem >> 1) / 6;
-            const int yy = y0 + hy - 1, zz = z0 + hz - 1, cc = c0 + cg * 8;
+            const int yy = y0 + hyx - 1, zz = z0 + hzx - 1, cc = c0 + cgx * 8;
             const bool row_ok = cc < a.cin && (unsigned)yy < (unsigned)G && (unsigned)zz < (unsigned)G;
-            bf16x8 v[10];
 #pragma unroll
             for (int m = 0; m < 10; ++m) {
-                const int xx = x0 + 8 * k + m - 1;
-#pragma unroll
-                for (int e = 0; e < 8; ++e) v[m][e] = (__bf16)0.f;
+                const int xx = x0 + 8 * kx + m - 1;
                 if (row_ok && (unsigned)xx < (unsigned)G) {
                     if (cc < a.c1s) {
                         const int64_t vi = ((((int64_t)smp << lg) + zz) << (2 * lg)) +
                                            ((int64_t)yy << lg) + xx;
-                        v[m] = *(const bf16x8*)(a.x1 + vi * a.c1s + cc);
+                        reg[m] = *(const bf16x8*)(a.x1 + vi * a.c1s + cc);
                     } else {
                         const int h = lg - 1;
                         const int64_t vi = ((((int64_t)smp << h) + (zz >> 1)) << (2 * h)) +
                                            ((int64_t)(yy >> 1) << h) + (xx >> 1);
-                        v[m] = *(const bf16x8*)(a.x2 + vi * a.c2 + (cc - a.c1s));
+                        reg[m] = *(const bf16x8*)(a.x2 + vi * a.c2 + (cc - a.c1s));
                     }
                 }
             }
-            const int row = (hz * 6 + hy) * 16 + 8 * k;
+        } else if (tid < 96 + 32 * RS) {
+            // output gradient: 8 cells (one k group) x 8 channels
+            const int yy = y0 + (sd & 1) * 2 + ((vgd & 3) >> 1), zz = z0 + (sd >> 1);
+            const int xb = x0 + (vgd & 1) * 8;
+            const int64_t v0 = ((((int64_t)smp << lg) + zz) << (2 * lg)) + ((int64_t)yy << lg) + xb;
+            if (cgd * 8 < a.ys) {
+#pragma unroll
+                for (int m = 0; m < 8; ++m) reg[m] = *(const bf16x8*)(a.dy + (v0 + m) * a.ys + cgd * 8);
+            }
+        }
+    };
+    if (b0 < b1) fetch(b0);
+    for (int64_t b = b0; b < b1; ++b) {
+        // transposed LDS stores of the fetched brick
+        if (tid < 96) {
+            const int row = (hzx * 6 + hyx) * 16 + 8 * kx;
 #pragma unroll
             for (int d = 0; d < 3; ++d)
 #pragma unroll
                 for (int e = 0; e < 8; ++e) {
                     bf16x8 w;
 #pragma unroll
-                    for (int j = 0; j < 8; ++j) w[j] = v[j + d][e];
-                    *(bf16x8*)&xs[(d * 16 + cg * 8 + e) * kBrickRow + row] = w;
+                    for (int j = 0; j < 8; ++j) w[j] = reg[j + d][e];
+                    *(bf16x8*)&xs[(d * 16 + cgx * 8 + e) * kBrickRow + row] = w;
                 }
         } else if (tid < 96 + 32 * RS) {
-            // output gradient: 8 cells (one k group) x 8 channels
-            const int t = tid - 96;
-            const int vg = t & 15, cg = t >> 4;
-            const int s = vg >> 2;  // k step
-            const int yy = y0 + (s & 1) * 2 + ((vg & 3) >> 1), zz = z0 + (s >> 1);
-            const int xb = x0 + (vg & 1) * 8;
-            const int64_t v0 = ((((int64_t)smp << lg) + zz) << (2 * lg)) + ((int64_t)yy << lg) + xb;
-            bf16x8 d[8];
-#pragma unroll
-            for (int m = 0; m < 8; ++m) {
-#pragma unroll
-                for (int e = 0; e < 8; ++e) d[m][e] = (__bf16)0.f;
-                if (cg * 8 < a.ys) d[m] = *(const bf16x8*)(a.dy + (v0 + m) * a.ys + cg * 8);
-            }
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
                 bf16x8 w;
 #pragma unroll
-                for (int j = 0; j < 8; ++j) w[j] = d[j][e];
-                *(bf16x8*)&dT[cg * 8 + e][vg * 8] = w;
+                for (int j = 0; j < 8; ++j) w[j] = reg[j][e];
+                *(bf16x8*)&dT[cgd * 8 + e][vgd * 8] = w;
             }
         }
         __syncthreads();
+        if (b + 1 < b1) fetch(b + 1);
         if (blockIdx.x == 0 && tid < RS * 16) {
 #pragma unroll 8
             for (int i = 0; i < 128; ++i) bsum += (float)dT[tid][i];
