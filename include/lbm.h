@@ -272,7 +272,11 @@ lbm_status lbm_gather_cells(lbm_handle* h, const int64_t* cells, int64_t n, doub
                             int check);
 
 /* Device buffers of the current state, for inspection: F and G base
- * pointers, elements between two populations, bytes per stored value. */
+ * pointers, elements between two populations of one x-row, bytes per stored
+ * value.  The state interleaves rows: population a of cell (x, y, z) is
+ * F[((z*ny + y)*(15 + q) + a)*nx + x] (flow, a < 15) or
+ * G[((z*ny + y)*(15 + q) + a)*nx + x] (scalar, a < q), G = F + 15 nx;
+ * pop_stride = nx. */
 lbm_status lbm_state_info(const lbm_handle* h, const void** F, const void** G,
                           int64_t* pop_stride, int32_t* value_bytes);
 

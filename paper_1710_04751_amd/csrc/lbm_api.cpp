@@ -122,10 +122,13 @@ bool validate(const lbm_params* p, lbm_lattice* L, std::string* why) {
     }
     const int64_t ncell = (int64_t)p->nx * p->ny * p->nz;
     const int vb = value_bytes((Prec)p->precision);
-    const uint64_t pop_bytes = align_up((size_t)ncell, 256) * (uint64_t)vb;
-    if (pop_bytes >= (1ull << 32) || ncell >= (1ll << 31)) {
-        // one population array must fit a 32-bit buffer offset
-        *why = "grid too large for 32-bit per-population offsets";
+    // The step kernel addresses a window of 3 ny + 2 rows (the rows of a
+    // tile and one plane plus one row on either side) with 32-bit byte
+    // offsets; cell indices are 32-bit.
+    const uint64_t window = (uint64_t)(3 * (int64_t)p->ny + 2) * (15 + p->thermal_q) *
+                            (uint64_t)p->nx * (uint64_t)vb;
+    if (window >= (1ull << 32) || ncell >= (1ll << 31)) {
+        *why = "grid too large for 32-bit cell indices and step-window offsets";
         return false;
     }
     return true;
@@ -134,9 +137,10 @@ bool validate(const lbm_params* p, lbm_lattice* L, std::string* why) {
 Layout layout_of(const lbm_params* p) {
     Layout l;
     l.ncell = (int64_t)p->nx * p->ny * p->nz;
-    l.ps = (int64_t)align_up((size_t)l.ncell, 256);
+    l.pl.nx = p->nx;
+    l.pl.rq = 15 + p->thermal_q;
     const int vb = value_bytes((Prec)p->precision);
-    l.state_bytes = align_up((size_t)(15 + p->thermal_q) * (size_t)l.ps * vb, kAlign);
+    l.state_bytes = align_up((size_t)(15 + p->thermal_q) * (size_t)l.ncell * vb, kAlign);
     l.off_A = 0;
     l.off_B = l.state_bytes;
     l.off_snap = 2 * l.state_bytes;
@@ -296,7 +300,7 @@ lbm_status lbm_init_rest(lbm_handle* h) {
     if (!h) return fail(LBM_ERR_ARG, "null handle");
     if (h->owner && !batch_allows_reinit(h->owner))
         return fail(LBM_ERR_STATE, "batch member re-initialised at an odd batch step");
-    hipError_t e = launch_init_rest((Prec)h->p.precision, h->p.thermal_q, h->geom, h->lay.ps,
+    hipError_t e = launch_init_rest((Prec)h->p.precision, h->p.thermal_q, h->geom, h->lay.pl,
                                     h->ws + h->lay.off_A, h->lay.state_bytes, h->buf(0), h->c,
                                     h->stream);
     if (e != hipSuccess) return hip_fail(e, "init_rest");
@@ -312,7 +316,7 @@ lbm_status lbm_init_macros(lbm_handle* h, const float* ux, const float* uy, cons
     if (h->owner && !batch_allows_reinit(h->owner))
         return fail(LBM_ERR_STATE, "batch member re-initialised at an odd batch step");
     // red()[10..13]: scratch of the staggered momentum sums
-    hipError_t e = launch_init_macros((Prec)h->p.precision, h->p.thermal_q, h->geom, h->lay.ps,
+    hipError_t e = launch_init_macros((Prec)h->p.precision, h->p.thermal_q, h->geom, h->lay.pl,
                                       h->buf(0), ux, uy, uz, T, h->red() + 10, h->c, h->stream);
     if (e != hipSuccess) return hip_fail(e, "init_macros");
     h->cur = 0;
@@ -328,7 +332,7 @@ lbm_status lbm_step(lbm_handle* h, int64_t nsteps) {
     const Prec pr = (Prec)h->p.precision;
     for (int64_t i = 0; i < nsteps; ++i) {
         h->c.seed = (uint32_t)h->steps;
-        hipError_t e = launch_step(pr, h->p.thermal_q, h->general, h->geom, h->lay.ps,
+        hipError_t e = launch_step(pr, h->p.thermal_q, h->general, h->geom,
                                    h->buf(h->cur), h->buf(1 - h->cur), h->c, h->stream);
         if (e != hipSuccess) return hip_fail(e, "step");
         h->cur = 1 - h->cur;
@@ -339,7 +343,7 @@ lbm_status lbm_step(lbm_handle* h, int64_t nsteps) {
 
 lbm_status lbm_macros(lbm_handle* h, void* rho, void* ux, void* uy, void* uz, void* T, int fp64) {
     if (!h) return fail(LBM_ERR_ARG, "null handle");
-    hipError_t e = launch_macros((Prec)h->p.precision, h->p.thermal_q, h->geom, h->lay.ps,
+    hipError_t e = launch_macros((Prec)h->p.precision, h->p.thermal_q, h->geom, h->lay.pl,
                                  h->buf(h->cur), rho, ux, uy, uz, T, fp64 != 0, h->c, h->stream);
     if (e != hipSuccess) return hip_fail(e, "macros");
     return LBM_OK;
@@ -347,7 +351,7 @@ lbm_status lbm_macros(lbm_handle* h, void* rho, void* ux, void* uy, void* uz, vo
 
 lbm_status lbm_nusselt(lbm_handle* h, lbm_nu* out, double* local_hot, double* local_cold) {
     if (!h || !out) return fail(LBM_ERR_ARG, "null argument");
-    hipError_t e = launch_nusselt((Prec)h->p.precision, h->p.thermal_q, h->geom, h->lay.ps,
+    hipError_t e = launch_nusselt((Prec)h->p.precision, h->p.thermal_q, h->geom, h->lay.pl,
                                   h->buf(h->cur), h->nu_hot(), h->nu_cold(), h->red(), h->c,
                                   h->stream);
     if (e != hipSuccess) return hip_fail(e, "nusselt");
@@ -386,7 +390,7 @@ lbm_status lbm_residual(lbm_handle* h, double* max_dT) {
     unsigned int* bad = (unsigned int*)(h->red() + 9);
     hipError_t e = launch_fill_zero(mb, 16, h->stream);
     if (e != hipSuccess) return hip_fail(e, "residual clear");
-    e = launch_residual((Prec)h->p.precision, h->p.thermal_q, h->geom, h->lay.ps, h->buf(h->cur),
+    e = launch_residual((Prec)h->p.precision, h->p.thermal_q, h->geom, h->lay.pl, h->buf(h->cur),
                         h->ws + h->lay.off_snap, h->snap_valid, mb, bad, h->stream);
     if (e != hipSuccess) return hip_fail(e, "residual");
     unsigned long long r[2];
@@ -431,7 +435,7 @@ lbm_status lbm_centerlines(lbm_handle* h, double* u_line, double* w_line, lbm_pe
     if (!h) return fail(LBM_ERR_ARG, "null handle");
     double* uu = h->nu_hot();  // scratch for the profiles
     double* ww = uu + h->p.nz;
-    hipError_t e = launch_centerlines((Prec)h->p.precision, h->p.thermal_q, h->geom, h->lay.ps,
+    hipError_t e = launch_centerlines((Prec)h->p.precision, h->p.thermal_q, h->geom, h->lay.pl,
                                       h->buf(h->cur), uu, ww, h->c, h->p.u0, h->stream);
     if (e != hipSuccess) return hip_fail(e, "centerlines");
     if (u_line) {
@@ -501,7 +505,7 @@ lbm_status lbm_run_to_steady(lbm_handle* h, double tol, int64_t check_every, int
 
 lbm_status lbm_get_populations(lbm_handle* h, double* F, double* G) {
     if (!h) return fail(LBM_ERR_ARG, "null handle");
-    hipError_t e = launch_get_pops((Prec)h->p.precision, h->p.thermal_q, h->geom, h->lay.ps,
+    hipError_t e = launch_get_pops((Prec)h->p.precision, h->p.thermal_q, h->geom, h->lay.pl,
                                    h->buf(h->cur), F, G, h->stream);
     if (e != hipSuccess) return hip_fail(e, "get_populations");
     return LBM_OK;
@@ -511,7 +515,7 @@ lbm_status lbm_set_populations(lbm_handle* h, const double* F, const double* G) 
     if (!h || !F || !G) return fail(LBM_ERR_ARG, "null argument");
     if (h->owner && !batch_allows_reinit(h->owner))
         return fail(LBM_ERR_STATE, "batch member re-initialised at an odd batch step");
-    hipError_t e = launch_set_pops((Prec)h->p.precision, h->p.thermal_q, h->geom, h->lay.ps,
+    hipError_t e = launch_set_pops((Prec)h->p.precision, h->p.thermal_q, h->geom, h->lay.pl,
                                    h->buf(0), F, G, h->stream);
     if (e != hipSuccess) return hip_fail(e, "set_populations");
     h->cur = 0;
@@ -533,7 +537,7 @@ lbm_status lbm_gather_cells(lbm_handle* h, const int64_t* cells, int64_t n, doub
             if (v < 0 || v >= h->lay.ncell) return fail(LBM_ERR_ARG, "cell index out of range");
     }
     hipError_t e = launch_gather_cells((Prec)h->p.precision, h->p.thermal_q, h->lay.ncell,
-                                       h->lay.ps, h->buf(h->cur), cells, n, F, G, h->stream);
+                                       h->lay.pl, h->buf(h->cur), cells, n, F, G, h->stream);
     if (e != hipSuccess) return hip_fail(e, "gather_cells");
     return LBM_OK;
 }
@@ -544,7 +548,7 @@ lbm_status lbm_state_info(const lbm_handle* h, const void** F, const void** G,
     StateBuf b = h->buf(h->cur);
     if (F) *F = b.F;
     if (G) *G = b.G;
-    if (pop_stride) *pop_stride = h->lay.ps;
+    if (pop_stride) *pop_stride = h->lay.pl.nx;
     if (vbytes) *vbytes = value_bytes((Prec)h->p.precision);
     return LBM_OK;
 }

@@ -27,10 +27,10 @@ namespace kern {
 
 // Device table entry of one member.
 struct DevCav {
-    void* F[2];      // state A / B
+    void* F[2];      // state A / B (flow runs; the scalar runs follow 15 runs later)
     void* G[2];
     void* snap;      // temperature snapshot of the residual
-    int64_t ps;      // elements between two populations
+    PopLay pl;
     int32_t nx, ny, nz;
     int32_t rows;    // x-rows per tile
     int32_t ytiles;  // tiles per z-plane
@@ -66,10 +66,8 @@ k_batch_step(const DevCav* __restrict__ cavs, const uint32_t* __restrict__ tiles
         const int x = (int)threadIdx.x - r * C.nx;
         const int y = yt * C.rows + r;
         if (r >= C.rows || y >= C.ny) continue;
-        const uint32_t cell = ((uint32_t)z * (uint32_t)C.ny + (uint32_t)y) * (uint32_t)C.nx + (uint32_t)x;
-        update_cell<R, S, QT, HG>((const S*)C.F[parity], (const S*)C.G[parity],
-                                  (S*)C.F[1 - parity], (S*)C.G[1 - parity], C.ps, cell, x, y, z,
-                                  C.nx, C.ny, C.nz, coef_of<R>(C));
+        update_cell<R, S, QT, HG>((const S*)C.F[parity], (S*)C.F[1 - parity], x, y, z,
+                                  yt * C.rows, C.nx, C.ny, C.nz, coef_of<R>(C));
     }
 }
 
@@ -97,7 +95,7 @@ k_batch_residual(const DevCav* __restrict__ cavs, const uint32_t* __restrict__ t
             const S* G = (const S*)C.G[parity];
             double T = 0;
 #pragma unroll
-            for (int a = 0; a < QT; ++a) T += Store<S>::template ld<double>(G + a * C.ps + cell);
+            for (int a = 0; a < QT; ++a) T += Store<S>::template ld<double>(G + pop_at(C.pl, a, cell));
             Snap* snap = (Snap*)C.snap;
             const Snap Ts = (Snap)T;
             if (!isfinite(T)) atomicOr(bad + c, 1u);
@@ -284,7 +282,7 @@ lbm_status upload_table(lbm_batch* b) {
         d.F[1] = B.F;
         d.G[1] = B.G;
         d.snap = h->ws + h->lay.off_snap;
-        d.ps = h->lay.ps;
+        d.pl = h->lay.pl;
         d.nx = h->p.nx;
         d.ny = h->p.ny;
         d.nz = h->p.nz;

@@ -13,7 +13,8 @@
 namespace lbm {
 
 struct Layout {
-    int64_t ncell, ps;
+    int64_t ncell;
+    PopLay pl;            // rows interleaved: (15 + q) runs of nx values per x-row
     size_t state_bytes;   // one of A, B
     size_t off_A, off_B, off_snap, off_nu, off_red, total;
 };
@@ -51,7 +52,7 @@ struct lbm_handle {
     lbm::StateBuf buf(int which) const {
         char* base = ws + (which ? lay.off_B : lay.off_A);
         const int vb = lbm::value_bytes((lbm::Prec)p.precision);
-        return lbm::StateBuf{base, base + (size_t)15 * lay.ps * vb};
+        return lbm::StateBuf{base, base + (size_t)15 * lay.pl.nx * vb};
     }
     double* nu_hot() const { return (double*)(ws + lay.off_nu); }
     double* nu_cold() const { return nu_hot() + (size_t)p.ny * p.nz; }

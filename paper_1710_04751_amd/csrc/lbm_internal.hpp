@@ -27,7 +27,17 @@ struct Coefs {
     uint32_t seed;                       // step index, the random stream's key
 };
 
-// One stored state (A or B): populations a of cell c at base[a*ps + c].
+// Layout of one stored state (A or B), rows interleaved: the cells of the
+// x-row (y, z) are stored as rq = 15 + q consecutive runs of nx values, one
+// run per population (flow 0..14, then scalar 0..q-1).  Flow population a
+// of cell (x, y, z) sits at F[((z*ny + y)*rq + a)*nx + x]; G points 15 runs
+// past F, so scalar population a sits at G[((z*ny + y)*rq + a)*nx + x].
+struct PopLay {
+    int32_t nx;  // values per run
+    int32_t rq;  // runs per row: 15 + q
+};
+
+// One stored state: base of the flow runs and of the scalar runs.
 struct StateBuf {
     void* F;
     void* G;
@@ -37,36 +47,36 @@ enum class Prec : int32_t { FP64 = 0, FP32 = 1, FP32_S16 = 2 };
 
 int value_bytes(Prec p);
 
-hipError_t launch_step(Prec p, int qt, bool general, const Geom& g, int64_t ps, StateBuf in,
+hipError_t launch_step(Prec p, int qt, bool general, const Geom& g, StateBuf in,
                        StateBuf out, const Coefs& c, hipStream_t s);
 hipError_t launch_fill_zero(void* ptr, size_t bytes, hipStream_t s);
 // Rest state: zero-fills state_bytes at state (both buffers), then, with a
 // scalar source, writes the scalar equilibrium at T = -R/2 into st.
-hipError_t launch_init_rest(Prec p, int qt, const Geom& g, int64_t ps, void* state,
+hipError_t launch_init_rest(Prec p, int qt, const Geom& g, PopLay pl, void* state,
                             size_t state_bytes, StateBuf st, const Coefs& c, hipStream_t s);
 // stag: device scratch of 4 doubles (16-byte aligned) for the staggered sums
-hipError_t launch_init_macros(Prec p, int qt, const Geom& g, int64_t ps, StateBuf st,
+hipError_t launch_init_macros(Prec p, int qt, const Geom& g, PopLay pl, StateBuf st,
                               const float* ux, const float* uy, const float* uz, const float* T,
                               double* stag, const Coefs& c, hipStream_t s);
-hipError_t launch_macros(Prec p, int qt, const Geom& g, int64_t ps, StateBuf st, void* rho,
+hipError_t launch_macros(Prec p, int qt, const Geom& g, PopLay pl, StateBuf st, void* rho,
                          void* ux, void* uy, void* uz, void* T, bool fp64, const Coefs& c,
                          hipStream_t s);
-hipError_t launch_nusselt(Prec p, int qt, const Geom& g, int64_t ps, StateBuf st,
+hipError_t launch_nusselt(Prec p, int qt, const Geom& g, PopLay pl, StateBuf st,
                           double* local_hot, double* local_cold, double* result,
                           const Coefs& c, hipStream_t s);
-hipError_t launch_centerlines(Prec p, int qt, const Geom& g, int64_t ps, StateBuf st,
+hipError_t launch_centerlines(Prec p, int qt, const Geom& g, PopLay pl, StateBuf st,
                               double* u_line, double* w_line, const Coefs& c, double u0,
                               hipStream_t s);
 hipError_t launch_symmetrize(const Geom& g, float* ux, float* uy, float* uz, float* T, double T0,
                              hipStream_t s);
-hipError_t launch_residual(Prec p, int qt, const Geom& g, int64_t ps, StateBuf st, void* snapshot,
+hipError_t launch_residual(Prec p, int qt, const Geom& g, PopLay pl, StateBuf st, void* snapshot,
                            bool compare, unsigned long long* max_bits, unsigned int* bad_flag,
                            hipStream_t s);
-hipError_t launch_get_pops(Prec p, int qt, const Geom& g, int64_t ps, StateBuf st, double* F,
+hipError_t launch_get_pops(Prec p, int qt, const Geom& g, PopLay pl, StateBuf st, double* F,
                            double* G, hipStream_t s);
-hipError_t launch_set_pops(Prec p, int qt, const Geom& g, int64_t ps, StateBuf st,
+hipError_t launch_set_pops(Prec p, int qt, const Geom& g, PopLay pl, StateBuf st,
                            const double* F, const double* G, hipStream_t s);
-hipError_t launch_gather_cells(Prec p, int qt, int64_t ncell, int64_t ps, StateBuf st,
+hipError_t launch_gather_cells(Prec p, int qt, int64_t ncell, PopLay pl, StateBuf st,
                                const int64_t* cells, int64_t n, double* F, double* G,
                                hipStream_t s);
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);

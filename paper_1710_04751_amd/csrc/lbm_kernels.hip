@@ -67,7 +67,7 @@ __global__ void __launch_bounds__(256) k_stagger_sums(const float* ux, const flo
 // lose their staggered sums and uz gets sum (-1)^z uz = S/2 (uniform
 // (-1)^x, (-1)^y, (-1)^z corrections).
 template <typename R, typename S, int QT>
-__global__ void k_init_macros(S* __restrict__ F, S* __restrict__ G, int64_t ps, Geom geo,
+__global__ void k_init_macros(S* __restrict__ F, S* __restrict__ G, PopLay pl, Geom geo,
                               const float* ux, const float* uy, const float* uz, const float* T,
                               const double* __restrict__ stag, double gbeta, R cs2, R src) {
     const int64_t ncell = (int64_t)geo.nx * geo.ny * geo.nz;
@@ -87,50 +87,50 @@ __global__ void k_init_macros(S* __restrict__ F, S* __restrict__ G, int64_t ps, 
     R d[15];
     flow_equilibrium<R>(R(0), u, v, w, d);
 #pragma unroll
-    for (int a = 0; a < 15; ++a) F[a * ps + c] = (S)d[a];
+    for (int a = 0; a < 15; ++a) F[pop_at(pl, a, c)] = (S)d[a];
     R g[QT];
     if constexpr (QT == 7)
         thermal_equilibrium7<R>(t, u, v, w, cs2, g);
     else
         thermal_equilibrium15<R>(t, u, v, w, cs2, g);
 #pragma unroll
-    for (int a = 0; a < QT; ++a) G[a * ps + c] = (S)g[a];
+    for (int a = 0; a < QT; ++a) G[pop_at(pl, a, c)] = (S)g[a];
 }
 
 // Rest state with a scalar source: flow at rest (deviations 0) and the
 // scalar equilibrium at T = -R/2 with u = 0, so that the first step sees
 // T = sum gbar + R/2 = 0 (eq. 25).
 template <typename R, typename S, int QT>
-__global__ void k_init_rest_source(S* __restrict__ F, S* __restrict__ G, int64_t ps,
+__global__ void k_init_rest_source(S* __restrict__ F, S* __restrict__ G, PopLay pl,
                                    int64_t ncell, R cs2, R src) {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ncell) return;
 #pragma unroll
-    for (int a = 0; a < 15; ++a) F[a * ps + c] = (S)0;
+    for (int a = 0; a < 15; ++a) F[pop_at(pl, a, c)] = (S)0;
     R g[QT];
     if constexpr (QT == 7)
         thermal_equilibrium7<R>(R(-0.5) * src, R(0), R(0), R(0), cs2, g);
     else
         thermal_equilibrium15<R>(R(-0.5) * src, R(0), R(0), R(0), cs2, g);
 #pragma unroll
-    for (int a = 0; a < QT; ++a) G[a * ps + c] = (S)g[a];
+    for (int a = 0; a < QT; ++a) G[pop_at(pl, a, c)] = (S)g[a];
 }
 
 // Macroscopic fields from the stored post-collision populations: the
 // collision conserves rho, adds F to the momentum and R to the scalar sum,
 // so u = (sum f~ e - F/2) / rho and T = sum g~ - R/2 (eq. 25).
 template <typename R, typename S, int QT, typename O>
-__global__ void k_macros(const S* __restrict__ F, const S* __restrict__ G, int64_t ps,
+__global__ void k_macros(const S* __restrict__ F, const S* __restrict__ G, PopLay pl,
                          int64_t ncell, O* rho, O* ux, O* uy, O* uz, O* To, R gbeta, R T_ref,
                          R src) {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ncell) return;
     R d[15];
 #pragma unroll
-    for (int a = 0; a < 15; ++a) d[a] = Store<S>::template ld<R>(F + a * ps + c);
+    for (int a = 0; a < 15; ++a) d[a] = Store<S>::template ld<R>(F + pop_at(pl, a, c));
     R T = 0;
 #pragma unroll
-    for (int a = 0; a < QT; ++a) T += Store<S>::template ld<R>(G + a * ps + c);
+    for (int a = 0; a < QT; ++a) T += Store<S>::template ld<R>(G + pop_at(pl, a, c));
     T -= R(0.5) * src;
     const Raw15<R> r = raw15(d);
     const R rh = R(1) + r.m0;
@@ -143,32 +143,32 @@ __global__ void k_macros(const S* __restrict__ F, const S* __restrict__ G, int64
 }
 
 template <typename S, int QT>
-__global__ void k_get_pops(const S* __restrict__ F, const S* __restrict__ G, int64_t ps,
+__global__ void k_get_pops(const S* __restrict__ F, const S* __restrict__ G, PopLay pl,
                            int64_t ncell, double* Fo, double* Go) {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ncell) return;
     if (Fo)
 #pragma unroll
         for (int a = 0; a < 15; ++a)
-            Fo[a * ncell + c] = flow_weight(a) + Store<S>::template ld<double>(F + a * ps + c);
+            Fo[a * ncell + c] = flow_weight(a) + Store<S>::template ld<double>(F + pop_at(pl, a, c));
     if (Go)
 #pragma unroll
-        for (int a = 0; a < QT; ++a) Go[a * ncell + c] = Store<S>::template ld<double>(G + a * ps + c);
+        for (int a = 0; a < QT; ++a) Go[a * ncell + c] = Store<S>::template ld<double>(G + pop_at(pl, a, c));
 }
 
 template <typename S, int QT>
-__global__ void k_set_pops(S* __restrict__ F, S* __restrict__ G, int64_t ps, int64_t ncell,
+__global__ void k_set_pops(S* __restrict__ F, S* __restrict__ G, PopLay pl, int64_t ncell,
                            const double* Fi, const double* Gi) {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ncell) return;
 #pragma unroll
-    for (int a = 0; a < 15; ++a) F[a * ps + c] = (S)(Fi[a * ncell + c] - flow_weight(a));
+    for (int a = 0; a < 15; ++a) F[pop_at(pl, a, c)] = (S)(Fi[a * ncell + c] - flow_weight(a));
 #pragma unroll
-    for (int a = 0; a < QT; ++a) G[a * ps + c] = (S)Gi[a * ncell + c];
+    for (int a = 0; a < QT; ++a) G[pop_at(pl, a, c)] = (S)Gi[a * ncell + c];
 }
 
 template <typename S, int QT>
-__global__ void k_gather_cells(const S* __restrict__ F, const S* __restrict__ G, int64_t ps,
+__global__ void k_gather_cells(const S* __restrict__ F, const S* __restrict__ G, PopLay pl,
                                const int64_t* cells, int64_t n, double* Fo, double* Go) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -176,10 +176,10 @@ __global__ void k_gather_cells(const S* __restrict__ F, const S* __restrict__ G,
     if (Fo)
 #pragma unroll
         for (int a = 0; a < 15; ++a)
-            Fo[i * 15 + a] = flow_weight(a) + Store<S>::template ld<double>(F + a * ps + c);
+            Fo[i * 15 + a] = flow_weight(a) + Store<S>::template ld<double>(F + pop_at(pl, a, c));
     if (Go)
 #pragma unroll
-        for (int a = 0; a < QT; ++a) Go[i * QT + a] = Store<S>::template ld<double>(G + a * ps + c);
+        for (int a = 0; a < QT; ++a) Go[i * QT + a] = Store<S>::template ld<double>(G + pop_at(pl, a, c));
 }
 
 // ---------------------------------------------------------------------------
@@ -190,7 +190,7 @@ __global__ void k_gather_cells(const S* __restrict__ F, const S* __restrict__ G,
 // 2 (w_a T_hot - G_opp(a)(0, y, z)); cold wall (x = nx - 1/2): sum over links
 // leaving it (e_x > 0) of 2 (G_a(nx-1, y, z) - w_a T_cold).
 template <typename S, int QT>
-__global__ void k_nusselt_local(const S* __restrict__ G, int64_t ps, Geom g, double* nu_hot,
+__global__ void k_nusselt_local(const S* __restrict__ G, PopLay pl, Geom g, double* nu_hot,
                                 double* nu_cold, double T_hot, double T_cold, double wf,
                                 double wc, double scale) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -198,7 +198,7 @@ __global__ void k_nusselt_local(const S* __restrict__ G, int64_t ps, Geom g, dou
     if (i >= n) return;
     const int64_t row = i * g.nx;  // cell (0, y, z) with i = z*ny + y
     const int64_t hot = row, cold = row + g.nx - 1;
-    auto ld = [&](int a, int64_t c) { return Store<S>::template ld<double>(G + a * ps + c); };
+    auto ld = [&](int a, int64_t c) { return Store<S>::template ld<double>(G + pop_at(pl, a, c)); };
     double qh = 2.0 * (wf * T_hot - ld(2, hot));
     double qc = 2.0 * (ld(1, cold) - wf * T_cold);
     if (QT == 15) {
@@ -274,7 +274,7 @@ k_nusselt_reduce(const double* __restrict__ nh, const double* __restrict__ nc, i
 // ---------------------------------------------------------------------------
 template <typename S, int QT, typename Snap>
 __global__ void __launch_bounds__(256)
-k_residual(const S* __restrict__ G, int64_t ps, int64_t ncell, Snap* __restrict__ snap,
+k_residual(const S* __restrict__ G, PopLay pl, int64_t ncell, Snap* __restrict__ snap,
            int compare, unsigned long long* max_bits, unsigned int* bad) {
     __shared__ double s_red[4];
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -282,7 +282,7 @@ k_residual(const S* __restrict__ G, int64_t ps, int64_t ncell, Snap* __restrict_
     if (c < ncell) {
         double T = 0;
 #pragma unroll
-        for (int a = 0; a < QT; ++a) T += Store<S>::template ld<double>(G + a * ps + c);
+        for (int a = 0; a < QT; ++a) T += Store<S>::template ld<double>(G + pop_at(pl, a, c));
         const Snap Ts = (Snap)T;
         if (!isfinite(T)) atomicOr(bad, 1u);
         if (compare) dev = fabs((double)Ts - (double)snap[c]);
@@ -318,19 +318,19 @@ hipError_t launch_fill_zero(void* ptr, size_t bytes, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_init_rest(Prec p, int qt, const Geom& g, int64_t ps, void* state,
+hipError_t launch_init_rest(Prec p, int qt, const Geom& g, PopLay pl, void* state,
                             size_t state_bytes, StateBuf st, const Coefs& c, hipStream_t s) {
     hipError_t e = launch_fill_zero(state, state_bytes, s);
     if (e != hipSuccess || c.src == 0.0) return e;
     const int64_t ncell = (int64_t)g.nx * g.ny * g.nz;
     LBM_DISPATCH_PQ(p, qt, {
         hipLaunchKernelGGL((k_init_rest_source<R, S, Q>), dim3(blocks_for(ncell, 256)), dim3(256),
-                           0, s, (S*)st.F, (S*)st.G, ps, ncell, (R)c.cs2, (R)c.src);
+                           0, s, (S*)st.F, (S*)st.G, pl, ncell, (R)c.cs2, (R)c.src);
         return hipGetLastError();
     });
 }
 
-hipError_t launch_init_macros(Prec p, int qt, const Geom& g, int64_t ps, StateBuf st,
+hipError_t launch_init_macros(Prec p, int qt, const Geom& g, PopLay pl, StateBuf st,
                               const float* ux, const float* uy, const float* uz, const float* T,
                               double* stag, const Coefs& c, hipStream_t s) {
     const int64_t ncell = (int64_t)g.nx * g.ny * g.nz;
@@ -342,25 +342,25 @@ hipError_t launch_init_macros(Prec p, int qt, const Geom& g, int64_t ps, StateBu
     if (e != hipSuccess) return e;
     LBM_DISPATCH_PQ(p, qt, {
         hipLaunchKernelGGL((k_init_macros<R, S, Q>), dim3(blocks_for(ncell, 256)), dim3(256), 0, s,
-                           (S*)st.F, (S*)st.G, ps, g, ux, uy, uz, T, (const double*)stag,
+                           (S*)st.F, (S*)st.G, pl, g, ux, uy, uz, T, (const double*)stag,
                            c.gbeta, (R)c.cs2, (R)c.src);
         return hipGetLastError();
     });
 }
 
-hipError_t launch_macros(Prec p, int qt, const Geom& g, int64_t ps, StateBuf st, void* rho,
+hipError_t launch_macros(Prec p, int qt, const Geom& g, PopLay pl, StateBuf st, void* rho,
                          void* ux, void* uy, void* uz, void* T, bool fp64, const Coefs& c,
                          hipStream_t s) {
     const int64_t ncell = (int64_t)g.nx * g.ny * g.nz;
     LBM_DISPATCH_PQ(p, qt, {
         if (fp64) {
             hipLaunchKernelGGL((k_macros<R, S, Q, double>), dim3(blocks_for(ncell, 256)), dim3(256),
-                               0, s, (const S*)st.F, (const S*)st.G, ps, ncell, (double*)rho,
+                               0, s, (const S*)st.F, (const S*)st.G, pl, ncell, (double*)rho,
                                (double*)ux, (double*)uy, (double*)uz, (double*)T, (R)c.gbeta,
                                (R)c.T_ref, (R)c.src);
         } else {
             hipLaunchKernelGGL((k_macros<R, S, Q, float>), dim3(blocks_for(ncell, 256)), dim3(256),
-                               0, s, (const S*)st.F, (const S*)st.G, ps, ncell, (float*)rho,
+                               0, s, (const S*)st.F, (const S*)st.G, pl, ncell, (float*)rho,
                                (float*)ux, (float*)uy, (float*)uz, (float*)T, (R)c.gbeta,
                                (R)c.T_ref, (R)c.src);
         }
@@ -368,7 +368,7 @@ hipError_t launch_macros(Prec p, int qt, const Geom& g, int64_t ps, StateBuf st,
     });
 }
 
-hipError_t launch_nusselt(Prec p, int qt, const Geom& g, int64_t ps, StateBuf st,
+hipError_t launch_nusselt(Prec p, int qt, const Geom& g, PopLay pl, StateBuf st,
                           double* local_hot, double* local_cold, double* result,
                           const Coefs& c, hipStream_t s) {
     const int64_t n = (int64_t)g.ny * g.nz;
@@ -377,7 +377,7 @@ hipError_t launch_nusselt(Prec p, int qt, const Geom& g, int64_t ps, StateBuf st
     const double scale = (double)g.nx / (c.alpha * (c.T_hot - c.T_cold));
     LBM_DISPATCH_PQ(p, qt, {
         hipLaunchKernelGGL((k_nusselt_local<S, Q>), dim3(blocks_for(n, 256)), dim3(256), 0, s,
-                           (const S*)st.G, ps, g, local_hot, local_cold, c.T_hot, c.T_cold, wf, wc,
+                           (const S*)st.G, pl, g, local_hot, local_cold, c.T_hot, c.T_cold, wf, wc,
                            scale);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -387,42 +387,42 @@ hipError_t launch_nusselt(Prec p, int qt, const Geom& g, int64_t ps, StateBuf st
     });
 }
 
-hipError_t launch_residual(Prec p, int qt, const Geom& g, int64_t ps, StateBuf st, void* snapshot,
+hipError_t launch_residual(Prec p, int qt, const Geom& g, PopLay pl, StateBuf st, void* snapshot,
                            bool compare, unsigned long long* max_bits, unsigned int* bad_flag,
                            hipStream_t s) {
     const int64_t ncell = (int64_t)g.nx * g.ny * g.nz;
     LBM_DISPATCH_PQ(p, qt, {
         using Snap = typename std::conditional<std::is_same<S, double>::value, double, float>::type;
         hipLaunchKernelGGL((k_residual<S, Q, Snap>), dim3(blocks_for(ncell, 256)), dim3(256), 0, s,
-                           (const S*)st.G, ps, ncell, (Snap*)snapshot, compare ? 1 : 0, max_bits,
+                           (const S*)st.G, pl, ncell, (Snap*)snapshot, compare ? 1 : 0, max_bits,
                            bad_flag);
         return hipGetLastError();
     });
 }
 
-hipError_t launch_get_pops(Prec p, int qt, const Geom& g, int64_t ps, StateBuf st, double* F,
+hipError_t launch_get_pops(Prec p, int qt, const Geom& g, PopLay pl, StateBuf st, double* F,
                            double* G, hipStream_t s) {
     const int64_t ncell = (int64_t)g.nx * g.ny * g.nz;
     LBM_DISPATCH_PQ(p, qt, {
         (void)sizeof(R);
         hipLaunchKernelGGL((k_get_pops<S, Q>), dim3(blocks_for(ncell, 256)), dim3(256), 0, s,
-                           (const S*)st.F, (const S*)st.G, ps, ncell, F, G);
+                           (const S*)st.F, (const S*)st.G, pl, ncell, F, G);
         return hipGetLastError();
     });
 }
 
-hipError_t launch_set_pops(Prec p, int qt, const Geom& g, int64_t ps, StateBuf st,
+hipError_t launch_set_pops(Prec p, int qt, const Geom& g, PopLay pl, StateBuf st,
                            const double* F, const double* G, hipStream_t s) {
     const int64_t ncell = (int64_t)g.nx * g.ny * g.nz;
     LBM_DISPATCH_PQ(p, qt, {
         (void)sizeof(R);
         hipLaunchKernelGGL((k_set_pops<S, Q>), dim3(blocks_for(ncell, 256)), dim3(256), 0, s,
-                           (S*)st.F, (S*)st.G, ps, ncell, F, G);
+                           (S*)st.F, (S*)st.G, pl, ncell, F, G);
         return hipGetLastError();
     });
 }
 
-hipError_t launch_gather_cells(Prec p, int qt, int64_t ncell, int64_t ps, StateBuf st,
+hipError_t launch_gather_cells(Prec p, int qt, int64_t ncell, PopLay pl, StateBuf st,
                                const int64_t* cells, int64_t n, double* F, double* G,
                                hipStream_t s) {
     (void)ncell;
@@ -430,7 +430,7 @@ hipError_t launch_gather_cells(Prec p, int qt, int64_t ncell, int64_t ps, StateB
     LBM_DISPATCH_PQ(p, qt, {
         (void)sizeof(R);
         hipLaunchKernelGGL((k_gather_cells<S, Q>), dim3(blocks_for(n, 256)), dim3(256), 0, s,
-                           (const S*)st.F, (const S*)st.G, ps, cells, n, F, G);
+                           (const S*)st.F, (const S*)st.G, pl, cells, n, F, G);
         return hipGetLastError();
     });
 }

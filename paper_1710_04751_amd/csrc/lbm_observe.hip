@@ -18,14 +18,14 @@ namespace kern {
 // source the stored scalar sum exceeds T by R/2 (eq. 25); the caller folds
 // that into T_ref.
 template <typename S, int QT>
-__device__ void cell_velocity(const S* __restrict__ F, const S* __restrict__ G, int64_t ps,
+__device__ void cell_velocity(const S* __restrict__ F, const S* __restrict__ G, PopLay pl,
                               int64_t c, double gbeta, double T_ref, double* ux, double* uz) {
     double d[15];
 #pragma unroll
-    for (int a = 0; a < 15; ++a) d[a] = Store<S>::template ld<double>(F + a * ps + c);
+    for (int a = 0; a < 15; ++a) d[a] = Store<S>::template ld<double>(F + pop_at(pl, a, c));
     double T = 0;
 #pragma unroll
-    for (int a = 0; a < QT; ++a) T += Store<S>::template ld<double>(G + a * ps + c);
+    for (int a = 0; a < QT; ++a) T += Store<S>::template ld<double>(G + pop_at(pl, a, c));
     const Raw15<double> r = raw15(d);
     const double rh = 1.0 + r.m0;
     *ux = r.x / rh;
@@ -36,7 +36,7 @@ __device__ void cell_velocity(const S* __restrict__ F, const S* __restrict__ G, 
 // x = L/2, thread t < nx gives u_z/u0 at x = t on z = L/2; an even count of
 // cells across a line averages the two middle cells.
 template <typename S, int QT>
-__global__ void k_centerlines(const S* __restrict__ F, const S* __restrict__ G, int64_t ps,
+__global__ void k_centerlines(const S* __restrict__ F, const S* __restrict__ G, PopLay pl,
                               Geom g, double gbeta, double T_ref, double inv_u0, double* u_line,
                               double* w_line) {
     const int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
@@ -48,7 +48,7 @@ __global__ void k_centerlines(const S* __restrict__ F, const S* __restrict__ G, 
         for (int y = y0; y <= y1; ++y)
             for (int x = x0; x <= x1; ++x) {
                 double ux, uz;
-                cell_velocity<S, QT>(F, G, ps, ((int64_t)t * g.ny + y) * g.nx + x, gbeta, T_ref,
+                cell_velocity<S, QT>(F, G, pl, ((int64_t)t * g.ny + y) * g.nx + x, gbeta, T_ref,
                                      &ux, &uz);
                 acc -= ux;
                 ++n;
@@ -62,7 +62,7 @@ __global__ void k_centerlines(const S* __restrict__ F, const S* __restrict__ G, 
         for (int z = z0; z <= z1; ++z)
             for (int y = y0; y <= y1; ++y) {
                 double ux, uz;
-                cell_velocity<S, QT>(F, G, ps, ((int64_t)z * g.ny + y) * g.nx + t, gbeta, T_ref,
+                cell_velocity<S, QT>(F, G, pl, ((int64_t)z * g.ny + y) * g.nx + t, gbeta, T_ref,
                                      &ux, &uz);
                 acc += uz;
                 ++n;
@@ -72,11 +72,11 @@ __global__ void k_centerlines(const S* __restrict__ F, const S* __restrict__ G, 
 }
 
 template <typename S, int QT>
-hipError_t centerlines_impl(const Geom& g, int64_t ps, StateBuf st, double* u_line,
+hipError_t centerlines_impl(const Geom& g, PopLay pl, StateBuf st, double* u_line,
                             double* w_line, const Coefs& c, double u0, hipStream_t s) {
     const int n = std::max(g.nx, g.nz);
     hipLaunchKernelGGL((k_centerlines<S, QT>), dim3((n + 255) / 256), dim3(256), 0, s,
-                       (const S*)st.F, (const S*)st.G, ps, g, c.gbeta, c.T_ref + 0.5 * c.src, 1.0 / u0, u_line,
+                       (const S*)st.F, (const S*)st.G, pl, g, c.gbeta, c.T_ref + 0.5 * c.src, 1.0 / u0, u_line,
                        w_line);
     return hipGetLastError();
 }
@@ -131,21 +131,21 @@ hipError_t launch_symmetrize(const Geom& g, float* ux, float* uy, float* uz, flo
     return hipGetLastError();
 }
 
-hipError_t launch_centerlines(Prec p, int qt, const Geom& g, int64_t ps, StateBuf st,
+hipError_t launch_centerlines(Prec p, int qt, const Geom& g, PopLay pl, StateBuf st,
                               double* u_line, double* w_line, const Coefs& c, double u0,
                               hipStream_t s) {
     using namespace kern;
     const bool q7 = qt == 7;
     switch (p) {
         case Prec::FP64:
-            return q7 ? centerlines_impl<double, 7>(g, ps, st, u_line, w_line, c, u0, s)
-                      : centerlines_impl<double, 15>(g, ps, st, u_line, w_line, c, u0, s);
+            return q7 ? centerlines_impl<double, 7>(g, pl, st, u_line, w_line, c, u0, s)
+                      : centerlines_impl<double, 15>(g, pl, st, u_line, w_line, c, u0, s);
         case Prec::FP32:
-            return q7 ? centerlines_impl<float, 7>(g, ps, st, u_line, w_line, c, u0, s)
-                      : centerlines_impl<float, 15>(g, ps, st, u_line, w_line, c, u0, s);
+            return q7 ? centerlines_impl<float, 7>(g, pl, st, u_line, w_line, c, u0, s)
+                      : centerlines_impl<float, 15>(g, pl, st, u_line, w_line, c, u0, s);
         case Prec::FP32_S16:
-            return q7 ? centerlines_impl<_Float16, 7>(g, ps, st, u_line, w_line, c, u0, s)
-                      : centerlines_impl<_Float16, 15>(g, ps, st, u_line, w_line, c, u0, s);
+            return q7 ? centerlines_impl<_Float16, 7>(g, pl, st, u_line, w_line, c, u0, s)
+                      : centerlines_impl<_Float16, 15>(g, pl, st, u_line, w_line, c, u0, s);
     }
     return hipErrorInvalidValue;
 }

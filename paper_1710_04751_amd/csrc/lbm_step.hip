@@ -6,8 +6,10 @@
 //     x - e_a in the previous post-collision state; each value is read once
 //     and written once, so the kernel moves (15 + q) values in and out per
 //     cell and is bound by HBM bandwidth;
-//   * SoA layout, x fastest: a wave reads 64 consecutive cells of one
-//     population, shifted by at most one element, so loads are coalesced;
+//   * rows interleaved: each x-row holds one run of nx values per
+//     population, x fastest, so a wave reads 64 consecutive cells of one
+//     population, shifted by at most one element (coalesced), and the
+//     streams of one block lie close together in memory;
 //   * walls (Sec. 3): a link whose source lies outside the box takes the
 //     opposite population of the cell itself (half-way bounce-back for the
 //     flow; anti-bounce-back -g + 2 w T_wall across the two Dirichlet walls,
@@ -40,8 +42,7 @@ __device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t nb) {
 }
 
 struct CellPos {
-    int x, y, z;
-    uint32_t cell;
+    int x, y, z, y0;  // y0: first row of the block's tile
     bool ok;
 };
 
@@ -56,41 +57,39 @@ __device__ __forceinline__ CellPos tile_cell(const Geom& g) {
     c.x = (int)(tx * blockDim.x + threadIdx.x);
     c.y = (int)(ty * blockDim.y + threadIdx.y);
     c.z = (int)tz;
+    c.y0 = (int)(ty * blockDim.y);
     c.ok = c.x < g.nx && c.y < g.ny;
-    c.cell = ((uint32_t)c.z * (uint32_t)g.ny + (uint32_t)c.y) * (uint32_t)g.nx + (uint32_t)c.x;
     return c;
 }
 
 // Single cavity: one thread per cell, blocks of bx * by cells of one plane.
 template <typename R, typename S, int QT, bool HG>
 __global__ void __launch_bounds__(1024)
-k_step(const S* __restrict__ Fi, const S* __restrict__ Gi, S* __restrict__ Fo,
-       S* __restrict__ Go, int64_t ps, Geom g, KCoef<R> k) {
+k_step(const S* __restrict__ in, S* __restrict__ out, Geom g, KCoef<R> k) {
     const CellPos p = tile_cell(g);
     if (!p.ok) return;
-    update_cell<R, S, QT, HG>(Fi, Gi, Fo, Go, ps, p.cell, p.x, p.y, p.z, g.nx, g.ny, g.nz, k);
+    update_cell<R, S, QT, HG>(in, out, p.x, p.y, p.z, p.y0, g.nx, g.ny, g.nz, k);
 }
 
 template <typename R, typename S, int QT, bool HG>
-hipError_t step_impl(const Geom& g, int64_t ps, StateBuf in, StateBuf out, const Coefs& c,
-                     hipStream_t s) {
+hipError_t step_impl(const Geom& g, StateBuf in, StateBuf out, const Coefs& c, hipStream_t s) {
     const KCoef<R> k = make_kcoef<R>(c, QT);
     const dim3 block(g.bx, g.by, 1);
     const dim3 grid((unsigned)((int64_t)g.tiles_x * g.tiles_y * g.nz), 1, 1);
-    hipLaunchKernelGGL((k_step<R, S, QT, HG>), grid, block, 0, s, (const S*)in.F, (const S*)in.G,
-                       (S*)out.F, (S*)out.G, ps, g, k);
+    hipLaunchKernelGGL((k_step<R, S, QT, HG>), grid, block, 0, s, (const S*)in.F, (S*)out.F, g,
+                       k);
     return hipGetLastError();
 }
 
 }  // namespace kern
 using namespace kern;
 
-hipError_t launch_step(Prec p, int qt, bool general, const Geom& g, int64_t ps, StateBuf in,
+hipError_t launch_step(Prec p, int qt, bool general, const Geom& g, StateBuf in,
                        StateBuf out, const Coefs& c, hipStream_t s) {
     if (general) {
-        LBM_DISPATCH_PQ(p, qt, return (step_impl<R, S, Q, true>(g, ps, in, out, c, s)));
+        LBM_DISPATCH_PQ(p, qt, return (step_impl<R, S, Q, true>(g, in, out, c, s)));
     } else {
-        LBM_DISPATCH_PQ(p, qt, return (step_impl<R, S, Q, false>(g, ps, in, out, c, s)));
+        LBM_DISPATCH_PQ(p, qt, return (step_impl<R, S, Q, false>(g, in, out, c, s)));
     }
 }
 

@@ -81,11 +81,20 @@ __device__ __forceinline__ uint32_t mix32(uint32_t x) {
     return x;
 }
 
+// Position of population a of cell c = (z*ny + y)*nx + x in a state
+// (c < 2^31; the flow base for a < 15, the scalar base for scalar a).
+__device__ __forceinline__ int64_t pop_at(PopLay L, int a, int64_t c) {
+    const uint32_t row = (uint32_t)c / (uint32_t)L.nx;
+    const uint32_t x = (uint32_t)c - row * (uint32_t)L.nx;
+    return ((int64_t)row * L.rq + a) * L.nx + x;
+}
+
 // Range-checked population access.  Every load and store of the step kernel
-// goes through a raw buffer resource whose record count is the byte size of
-// one population array: the hardware returns 0 for a load and drops a store
-// outside it, so no index, however computed, can touch memory beyond the
-// array.  Offsets are 32-bit byte offsets from a scalar base.
+// goes through a raw buffer resource over a window of the state that starts
+// at a row of the block's own tile or before it and ends at or before the
+// state's end: the hardware returns 0 for a load and drops a store outside
+// it, so no index, however computed, can touch memory beyond the state.
+// Offsets are 32-bit byte offsets from the window's (scalar) base.
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t pop_rsrc(const void* base, uint32_t bytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes,
                                              0x00020000);
@@ -171,26 +180,35 @@ KCoef<R> make_kcoef(const Coefs& c, int qt) {
 // the batched kernels, so both compute bit-identical results)
 // ---------------------------------------------------------------------------
 template <typename R, typename S, int QT, bool HG>
-__device__ __forceinline__ void update_cell(const S* __restrict__ Fi, const S* __restrict__ Gi,
-                                            S* __restrict__ Fo, S* __restrict__ Go, int64_t ps,
-                                            uint32_t cell, int x, int y, int z, int nxi, int nyi,
-                                            int nzi, const KCoef<R>& k) {
-    const uint32_t nx = (uint32_t)nxi, nxy = (uint32_t)nxi * (uint32_t)nyi;
+__device__ __forceinline__ void update_cell(const S* __restrict__ in, S* __restrict__ out, int x,
+                                            int y, int z, int y0, int nxi, int nyi, int nzi,
+                                            const KCoef<R>& k) {
+    constexpr uint32_t RQ = 15 + QT;
+    const uint32_t nx = (uint32_t)nxi, ny = (uint32_t)nyi;
+    const uint32_t rowlen = RQ * nx;  // values per x-row
     const bool xlo = x == 0, xhi = x == nxi - 1;
     const bool ylo = y == 0, yhi = y == nyi - 1;
     const bool zlo = z == 0, zhi = z == nzi - 1;
-    const uint32_t pb = (uint32_t)(ps * (int64_t)sizeof(S));  // bytes of one population array
+    // Window: from row (z-1, y0-1), the first row a cell of a tile starting
+    // at row (z, y0) can pull from, clamped at 0, to the end of the state.
+    // y0 and z are uniform over the block, so the base is a scalar.
+    const uint32_t r0 = (uint32_t)z * ny + (uint32_t)y0;
+    const uint32_t lo = r0 > ny ? r0 - ny - 1 : 0u;
+    const uint64_t wbytes = (uint64_t)(ny * (uint32_t)nzi - lo) * rowlen * sizeof(S);
+    const uint32_t wb = wbytes > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)wbytes;
+    const __amdgpu_buffer_rsrc_t ri = pop_rsrc(in + (size_t)lo * rowlen, wb);
+    const __amdgpu_buffer_rsrc_t ro = pop_rsrc(out + (size_t)lo * rowlen, wb);
+    const uint32_t own = ((uint32_t)z * ny + (uint32_t)y - lo) * rowlen + (uint32_t)x;
     R d[15];
 #pragma unroll
     for (int a = 0; a < 15; ++a) {
         const int ex = EX15[a], ey = EY15[a], ez = EZ15[a];
-        const bool out = (ex > 0 && xlo) || (ex < 0 && xhi) || (ey > 0 && ylo) || (ey < 0 && yhi) ||
-                         (ez > 0 && zlo) || (ez < 0 && zhi);
-        const int32_t off = ex + ey * (int32_t)nx + ez * (int32_t)nxy;
-        // wall lanes take the opposite population of their own cell
-        R v = Buf<S>::template ld<R>(pop_rsrc(Fi + a * ps, pb), out ? cell : cell - off);
-        if (out) v = Buf<S>::template ld<R>(pop_rsrc(Fi + OPP15[a] * ps, pb), cell);
-        d[a] = v;
+        const bool o = (ex > 0 && xlo) || (ex < 0 && xhi) || (ey > 0 && ylo) || (ey < 0 && yhi) ||
+                       (ez > 0 && zlo) || (ez < 0 && zhi);
+        const int32_t sh = ex + (ey + ez * (int32_t)ny) * (int32_t)rowlen;
+        // wall links take the opposite population of their own cell
+        d[a] = Buf<S>::template ld<R>(ri, o ? own + (uint32_t)OPP15[a] * nx
+                                            : own - (uint32_t)sh + (uint32_t)a * nx);
     }
     R gq[QT];
 #pragma unroll
@@ -201,16 +219,14 @@ __device__ __forceinline__ void update_cell(const S* __restrict__ Fi, const S* _
         const int ob = QT == 7 ? OPP7[a] : OPP15[a];
         const bool outx = (ex > 0 && xlo) || (ex < 0 && xhi);
         const bool outyz = (ey > 0 && ylo) || (ey < 0 && yhi) || (ez > 0 && zlo) || (ez < 0 && zhi);
-        const int32_t off = ex + ey * (int32_t)nx + ez * (int32_t)nxy;
-        const bool out = outx || outyz;
-        R v = Buf<S>::template ld<R>(pop_rsrc(Gi + a * ps, pb), out ? cell : cell - off);
-        if (out) {
-            v = Buf<S>::template ld<R>(pop_rsrc(Gi + ob * ps, pb), cell);
-            if (ex != 0 && outx) {
-                const R w = (ey == 0 && ez == 0) ? k.w_face : k.w_corner;
-                const R tw = ex > 0 ? k.T_hot : k.T_cold;  // source beyond x = -1/2 or nx - 1/2
-                v = R(2) * w * tw - v;
-            }
+        const int32_t sh = ex + (ey + ez * (int32_t)ny) * (int32_t)rowlen;
+        const bool o = outx || outyz;
+        R v = Buf<S>::template ld<R>(ri, o ? own + (uint32_t)(15 + ob) * nx
+                                           : own - (uint32_t)sh + (uint32_t)(15 + a) * nx);
+        if (o && ex != 0 && outx) {
+            const R w = (ey == 0 && ez == 0) ? k.w_face : k.w_corner;
+            const R tw = ex > 0 ? k.T_hot : k.T_cold;  // source beyond x = -1/2 or nx - 1/2
+            v = R(2) * w * tw - v;
         }
         gq[a] = v;
     }
@@ -230,25 +246,26 @@ __device__ __forceinline__ void update_cell(const S* __restrict__ Fi, const S* _
     if constexpr (std::is_same<S, _Float16>::value) {
         if (k.sr) {
             // one 32-bit draw gives the 16 random bits of two stores
+            const uint32_t cell = ((uint32_t)z * ny + (uint32_t)y) * nx + (uint32_t)x;
             const uint32_t key = mix32(k.seed * 0x9e3779b9u ^ cell);
             uint32_t rnd[(15 + QT + 1) / 2];
 #pragma unroll
             for (int j = 0; j < (15 + QT + 1) / 2; ++j) rnd[j] = mix32(key + (uint32_t)j * 0x85ebca77u);
 #pragma unroll
             for (int a = 0; a < 15; ++a)
-                Buf<S>::st(pop_rsrc(Fo + a * ps, pb), cell,
+                Buf<S>::st(ro, own + (uint32_t)a * nx,
                            (float)half_stochastic(d[a], rnd[a >> 1] >> (16 * (a & 1))));
 #pragma unroll
             for (int a = 0; a < QT; ++a)
-                Buf<S>::st(pop_rsrc(Go + a * ps, pb), cell,
+                Buf<S>::st(ro, own + (uint32_t)(15 + a) * nx,
                            (float)half_stochastic(gq[a], rnd[(a + 15) >> 1] >> (16 * ((a + 15) & 1))));
             return;
         }
     }
 #pragma unroll
-    for (int a = 0; a < 15; ++a) Buf<S>::st(pop_rsrc(Fo + a * ps, pb), cell, d[a]);
+    for (int a = 0; a < 15; ++a) Buf<S>::st(ro, own + (uint32_t)a * nx, d[a]);
 #pragma unroll
-    for (int a = 0; a < QT; ++a) Buf<S>::st(pop_rsrc(Go + a * ps, pb), cell, gq[a]);
+    for (int a = 0; a < QT; ++a) Buf<S>::st(ro, own + (uint32_t)(15 + a) * nx, gq[a]);
 }
 
 }  // namespace kern

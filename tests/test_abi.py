@@ -69,6 +69,23 @@ def test_invalid_parameters_are_rejected(capi, field, value, msg):
     assert e.value.status == capi.LBM_ERR_ARG
 
 
+def test_grid_size_limits(capi):
+    # 32-bit cell indices: 1291^3 > 2^31 cells is refused
+    p = capi.lbm_params_init(1291, 1e6)
+    assert capi.lib().lbm_workspace_bytes(ctypes.byref(p)) == 0
+    assert "too large" in capi.lbm_last_error()
+    # the step kernel's window of 3 ny + 2 rows must fit 32-bit byte offsets
+    p = capi.lbm_params_init(16, 1e3)
+    p.nx, p.ny, p.nz = 8192, 8192, 4
+    p.precision = capi.LBM_FP64
+    assert capi.lib().lbm_workspace_bytes(ctypes.byref(p)) == 0
+    assert "too large" in capi.lbm_last_error()
+    # 1024^3 in FP32 (two states of 22 populations: 189 GB) fits one MI355X
+    p = capi.lbm_params_init(1024, 1e6)
+    n = capi.lbm_workspace_bytes(p)
+    assert n >= 2 * 22 * 4 * 1024 ** 3
+
+
 def test_workspace_checks_before_any_device_work(capi):
     p = capi.lbm_params_init(16, 1e3)
     nbytes = capi.lbm_workspace_bytes(p)
