@@ -272,11 +272,14 @@ lbm_status lbm_gather_cells(lbm_handle* h, const int64_t* cells, int64_t n, doub
                             int check);
 
 /* Device buffers of the current state, for inspection: F and G base
- * pointers, elements between two populations of one x-row, bytes per stored
- * value.  The state interleaves rows: population a of cell (x, y, z) is
- * F[((z*ny + y)*(15 + q) + a)*nx + x] (flow, a < 15) or
- * G[((z*ny + y)*(15 + q) + a)*nx + x] (scalar, a < q), G = F + 15 nx;
- * pop_stride = nx. */
+ * pointers, elements between two populations of one cell (pop_stride), bytes
+ * per stored value.  The state interleaves groups of Rg = pop_stride / nx
+ * consecutive x-rows (Rg a power of two, chosen so that one population's
+ * run of a group spans about 32 KB): with r = z*ny + y, population a of
+ * cell (x, y, z) is
+ *   F[((r / Rg)*(15 + q) + a)*pop_stride + (r % Rg)*nx + x]  (flow, a < 15),
+ *   G[((r / Rg)*(15 + q) + a)*pop_stride + (r % Rg)*nx + x]  (scalar, a < q),
+ * with G = F + 15 pop_stride. */
 lbm_status lbm_state_info(const lbm_handle* h, const void** F, const void** G,
                           int64_t* pop_stride, int32_t* value_bytes);
 

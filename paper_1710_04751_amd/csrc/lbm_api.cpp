@@ -122,10 +122,11 @@ bool validate(const lbm_params* p, lbm_lattice* L, std::string* why) {
     }
     const int64_t ncell = (int64_t)p->nx * p->ny * p->nz;
     const int vb = value_bytes((Prec)p->precision);
-    // The step kernel addresses a window of 3 ny + 2 rows (the rows of a
-    // tile and one plane plus one row on either side) with 32-bit byte
-    // offsets; cell indices are 32-bit.
-    const uint64_t window = (uint64_t)(3 * (int64_t)p->ny + 2) * (15 + p->thermal_q) *
+    // The step kernel addresses a window of at most 3 ny + 2 rows (the rows
+    // of a tile and one plane plus one row on either side) widened to whole
+    // row groups, with 32-bit byte offsets; cell indices are 32-bit.
+    const int64_t grp = (int64_t)1 << run_rows_log2(p);
+    const uint64_t window = (uint64_t)(3 * (int64_t)p->ny + 2 + 2 * grp) * (15 + p->thermal_q) *
                             (uint64_t)p->nx * (uint64_t)vb;
     if (window >= (1ull << 32) || ncell >= (1ll << 31)) {
         *why = "grid too large for 32-bit cell indices and step-window offsets";
@@ -134,13 +135,25 @@ bool validate(const lbm_params* p, lbm_lattice* L, std::string* why) {
     return true;
 }
 
+int run_rows_log2(const lbm_params* p) {
+    const int64_t row_bytes = (int64_t)p->nx * value_bytes((Prec)p->precision);
+    const int64_t nrows = (int64_t)p->ny * p->nz;
+    int gs = 0;
+    while ((row_bytes << (gs + 1)) <= 32768 && ((int64_t)2 << gs) <= nrows) ++gs;
+    return gs;
+}
+
 Layout layout_of(const lbm_params* p) {
     Layout l;
     l.ncell = (int64_t)p->nx * p->ny * p->nz;
     l.pl.nx = p->nx;
     l.pl.rq = 15 + p->thermal_q;
+    l.pl.gs = run_rows_log2(p);
     const int vb = value_bytes((Prec)p->precision);
-    l.state_bytes = align_up((size_t)(15 + p->thermal_q) * (size_t)l.ncell * vb, kAlign);
+    // whole row groups: the last one is padded when the rows do not fill it
+    const int64_t grp = (int64_t)1 << l.pl.gs;
+    const int64_t rows = ((int64_t)p->ny * p->nz + grp - 1) / grp * grp;
+    l.state_bytes = align_up((size_t)(15 + p->thermal_q) * (size_t)rows * p->nx * vb, kAlign);
     l.off_A = 0;
     l.off_B = l.state_bytes;
     l.off_snap = 2 * l.state_bytes;
@@ -171,6 +184,7 @@ void set_geom(lbm_handle* h, int bx, int by) {
     h->geom.by = by;
     h->geom.tiles_x = (h->p.nx + bx - 1) / bx;
     h->geom.tiles_y = (h->p.ny + by - 1) / by;
+    h->geom.gs = h->lay.pl.gs;
 }
 
 lbm_status make_handle(const lbm_params* p, void* workspace, size_t bytes, void* stream,
@@ -548,7 +562,7 @@ lbm_status lbm_state_info(const lbm_handle* h, const void** F, const void** G,
     StateBuf b = h->buf(h->cur);
     if (F) *F = b.F;
     if (G) *G = b.G;
-    if (pop_stride) *pop_stride = h->lay.pl.nx;
+    if (pop_stride) *pop_stride = (int64_t)h->lay.pl.nx << h->lay.pl.gs;
     if (vbytes) *vbytes = value_bytes((Prec)h->p.precision);
     return LBM_OK;
 }

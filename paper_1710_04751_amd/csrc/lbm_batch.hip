@@ -67,7 +67,7 @@ k_batch_step(const DevCav* __restrict__ cavs, const uint32_t* __restrict__ tiles
         const int y = yt * C.rows + r;
         if (r >= C.rows || y >= C.ny) continue;
         update_cell<R, S, QT, HG>((const S*)C.F[parity], (S*)C.F[1 - parity], x, y, z,
-                                  yt * C.rows, C.nx, C.ny, C.nz, coef_of<R>(C));
+                                  yt * C.rows, C.nx, C.ny, C.nz, C.pl.gs, coef_of<R>(C));
     }
 }
 

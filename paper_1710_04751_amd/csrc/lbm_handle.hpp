@@ -14,7 +14,7 @@ namespace lbm {
 
 struct Layout {
     int64_t ncell;
-    PopLay pl;            // rows interleaved: (15 + q) runs of nx values per x-row
+    PopLay pl;            // row groups interleaved: (15 + q) runs per group of rows
     size_t state_bytes;   // one of A, B
     size_t off_A, off_B, off_snap, off_nu, off_red, total;
 };
@@ -28,6 +28,9 @@ inline bool uses_general_path(const lbm_params* p) {
     return p->omega_hi != 1.0 || p->omega_hi_T != 1.0 || p->R != 0.0;
 }
 Layout layout_of(const lbm_params* p);
+// log2 of the rows per population run: the largest power of two R with
+// R*nx values of one population within 32 KB, and R no more than the rows.
+int run_rows_log2(const lbm_params* p);
 void default_block(int nx, int* bx, int* by);
 // Create a handle over caller memory without touching the device.
 lbm_status make_handle(const lbm_params* p, void* workspace, size_t bytes, void* stream,
@@ -52,7 +55,7 @@ struct lbm_handle {
     lbm::StateBuf buf(int which) const {
         char* base = ws + (which ? lay.off_B : lay.off_A);
         const int vb = lbm::value_bytes((lbm::Prec)p.precision);
-        return lbm::StateBuf{base, base + (size_t)15 * lay.pl.nx * vb};
+        return lbm::StateBuf{base, base + ((size_t)15 * lay.pl.nx * vb << lay.pl.gs)};
     }
     double* nu_hot() const { return (double*)(ws + lay.off_nu); }
     double* nu_cold() const { return nu_hot() + (size_t)p.ny * p.nz; }

@@ -12,6 +12,7 @@ struct Geom {
     int32_t nx, ny, nz;
     int32_t bx, by;           // threads per block along x, y
     int32_t tiles_x, tiles_y; // blocks per row / per plane
+    int32_t gs;               // log2 of the rows per population run (PopLay)
 };
 
 // Lattice-unit coefficients, in double; launchers convert to the arithmetic
@@ -27,14 +28,18 @@ struct Coefs {
     uint32_t seed;                       // step index, the random stream's key
 };
 
-// Layout of one stored state (A or B), rows interleaved: the cells of the
-// x-row (y, z) are stored as rq = 15 + q consecutive runs of nx values, one
-// run per population (flow 0..14, then scalar 0..q-1).  Flow population a
-// of cell (x, y, z) sits at F[((z*ny + y)*rq + a)*nx + x]; G points 15 runs
-// past F, so scalar population a sits at G[((z*ny + y)*rq + a)*nx + x].
+// Layout of one stored state (A or B), row groups interleaved.  The x-rows
+// r = z*ny + y are taken in groups of R = 2^gs consecutive rows; a group is
+// stored as rq = 15 + q runs of R*nx values, one run per population (flow
+// 0..14, then scalar 0..q-1), each run holding its R rows one after another,
+// x fastest.  Flow population a of cell (x, y, z) sits at
+// F[((r >> gs)*rq + a)*R*nx + (r & (R-1))*nx + x]; G points 15 runs past F,
+// so scalar population a sits at the same position from G.  The state is
+// padded to a whole number of groups.
 struct PopLay {
-    int32_t nx;  // values per run
-    int32_t rq;  // runs per row: 15 + q
+    int32_t nx;  // values per row
+    int32_t rq;  // runs per group: 15 + q
+    int32_t gs;  // log2 of the rows per group
 };
 
 // One stored state: base of the flow runs and of the scalar runs.

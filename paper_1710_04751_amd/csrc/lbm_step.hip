@@ -6,10 +6,10 @@
 //     x - e_a in the previous post-collision state; each value is read once
 //     and written once, so the kernel moves (15 + q) values in and out per
 //     cell and is bound by HBM bandwidth;
-//   * rows interleaved: each x-row holds one run of nx values per
-//     population, x fastest, so a wave reads 64 consecutive cells of one
-//     population, shifted by at most one element (coalesced), and the
-//     streams of one block lie close together in memory;
+//   * row groups interleaved: each group of consecutive x-rows holds one
+//     run per population, x fastest, so a wave reads 64 consecutive cells
+//     of one population, shifted by at most one element (coalesced), and
+//     the streams of one block lie within a few runs of ~32 KB;
 //   * walls (Sec. 3): a link whose source lies outside the box takes the
 //     opposite population of the cell itself (half-way bounce-back for the
 //     flow; anti-bounce-back -g + 2 w T_wall across the two Dirichlet walls,
@@ -68,7 +68,7 @@ __global__ void __launch_bounds__(1024)
 k_step(const S* __restrict__ in, S* __restrict__ out, Geom g, KCoef<R> k) {
     const CellPos p = tile_cell(g);
     if (!p.ok) return;
-    update_cell<R, S, QT, HG>(in, out, p.x, p.y, p.z, p.y0, g.nx, g.ny, g.nz, k);
+    update_cell<R, S, QT, HG>(in, out, p.x, p.y, p.z, p.y0, g.nx, g.ny, g.nz, g.gs, k);
 }
 
 template <typename R, typename S, int QT, bool HG>

@@ -86,7 +86,8 @@ __device__ __forceinline__ uint32_t mix32(uint32_t x) {
 __device__ __forceinline__ int64_t pop_at(PopLay L, int a, int64_t c) {
     const uint32_t row = (uint32_t)c / (uint32_t)L.nx;
     const uint32_t x = (uint32_t)c - row * (uint32_t)L.nx;
-    return ((int64_t)row * L.rq + a) * L.nx + x;
+    const uint32_t grp = row >> L.gs, sub = row & ((1u << L.gs) - 1u);
+    return ((((int64_t)grp * L.rq + a) << L.gs) + sub) * L.nx + x;
 }
 
 // Range-checked population access.  Every load and store of the step kernel
@@ -182,33 +183,40 @@ KCoef<R> make_kcoef(const Coefs& c, int qt) {
 template <typename R, typename S, int QT, bool HG>
 __device__ __forceinline__ void update_cell(const S* __restrict__ in, S* __restrict__ out, int x,
                                             int y, int z, int y0, int nxi, int nyi, int nzi,
-                                            const KCoef<R>& k) {
+                                            int gs, const KCoef<R>& k) {
     constexpr uint32_t RQ = 15 + QT;
     const uint32_t nx = (uint32_t)nxi, ny = (uint32_t)nyi;
-    const uint32_t rowlen = RQ * nx;  // values per x-row
+    const uint32_t gmask = (1u << gs) - 1u;
+    const uint32_t run = nx << gs;    // values per population run (one group of rows)
+    const uint32_t glen = RQ * run;   // values per group
     const bool xlo = x == 0, xhi = x == nxi - 1;
     const bool ylo = y == 0, yhi = y == nyi - 1;
     const bool zlo = z == 0, zhi = z == nzi - 1;
-    // Window: from row (z-1, y0-1), the first row a cell of a tile starting
-    // at row (z, y0) can pull from, clamped at 0, to the end of the state.
-    // y0 and z are uniform over the block, so the base is a scalar.
+    // Window: from the group of row (z-1, y0-1), the first row a cell of a
+    // tile starting at row (z, y0) can pull from (clamped at 0), to the end
+    // of the state.  y0 and z are uniform over the block, so the base is a
+    // scalar.
     const uint32_t r0 = (uint32_t)z * ny + (uint32_t)y0;
-    const uint32_t lo = r0 > ny ? r0 - ny - 1 : 0u;
-    const uint64_t wbytes = (uint64_t)(ny * (uint32_t)nzi - lo) * rowlen * sizeof(S);
+    const uint32_t g0 = (r0 > ny ? r0 - ny - 1 : 0u) >> gs;
+    const uint32_t ngroups = (ny * (uint32_t)nzi + gmask) >> gs;
+    const uint64_t wbytes = (uint64_t)(ngroups - g0) * glen * sizeof(S);
     const uint32_t wb = wbytes > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)wbytes;
-    const __amdgpu_buffer_rsrc_t ri = pop_rsrc(in + (size_t)lo * rowlen, wb);
-    const __amdgpu_buffer_rsrc_t ro = pop_rsrc(out + (size_t)lo * rowlen, wb);
-    const uint32_t own = ((uint32_t)z * ny + (uint32_t)y - lo) * rowlen + (uint32_t)x;
+    const __amdgpu_buffer_rsrc_t ri = pop_rsrc(in + (size_t)g0 * glen, wb);
+    const __amdgpu_buffer_rsrc_t ro = pop_rsrc(out + (size_t)g0 * glen, wb);
+    // offset of row r's first value in population run 0, from the window base
+    auto row_at = [&](uint32_t r) { return ((r >> gs) - g0) * glen + (r & gmask) * nx; };
+    const uint32_t r = (uint32_t)z * ny + (uint32_t)y;
+    const uint32_t own = row_at(r) + (uint32_t)x;
     R d[15];
 #pragma unroll
     for (int a = 0; a < 15; ++a) {
         const int ex = EX15[a], ey = EY15[a], ez = EZ15[a];
         const bool o = (ex > 0 && xlo) || (ex < 0 && xhi) || (ey > 0 && ylo) || (ey < 0 && yhi) ||
                        (ez > 0 && zlo) || (ez < 0 && zhi);
-        const int32_t sh = ex + (ey + ez * (int32_t)ny) * (int32_t)rowlen;
+        const uint32_t src = row_at(r - (uint32_t)(ey + ez * (int32_t)ny)) + (uint32_t)(x - ex);
         // wall links take the opposite population of their own cell
-        d[a] = Buf<S>::template ld<R>(ri, o ? own + (uint32_t)OPP15[a] * nx
-                                            : own - (uint32_t)sh + (uint32_t)a * nx);
+        d[a] = Buf<S>::template ld<R>(ri, o ? own + (uint32_t)OPP15[a] * run
+                                            : src + (uint32_t)a * run);
     }
     R gq[QT];
 #pragma unroll
@@ -219,10 +227,10 @@ __device__ __forceinline__ void update_cell(const S* __restrict__ in, S* __restr
         const int ob = QT == 7 ? OPP7[a] : OPP15[a];
         const bool outx = (ex > 0 && xlo) || (ex < 0 && xhi);
         const bool outyz = (ey > 0 && ylo) || (ey < 0 && yhi) || (ez > 0 && zlo) || (ez < 0 && zhi);
-        const int32_t sh = ex + (ey + ez * (int32_t)ny) * (int32_t)rowlen;
+        const uint32_t src = row_at(r - (uint32_t)(ey + ez * (int32_t)ny)) + (uint32_t)(x - ex);
         const bool o = outx || outyz;
-        R v = Buf<S>::template ld<R>(ri, o ? own + (uint32_t)(15 + ob) * nx
-                                           : own - (uint32_t)sh + (uint32_t)(15 + a) * nx);
+        R v = Buf<S>::template ld<R>(ri, o ? own + (uint32_t)(15 + ob) * run
+                                           : src + (uint32_t)(15 + a) * run);
         if (o && ex != 0 && outx) {
             const R w = (ey == 0 && ez == 0) ? k.w_face : k.w_corner;
             const R tw = ex > 0 ? k.T_hot : k.T_cold;  // source beyond x = -1/2 or nx - 1/2
@@ -253,19 +261,19 @@ __device__ __forceinline__ void update_cell(const S* __restrict__ in, S* __restr
             for (int j = 0; j < (15 + QT + 1) / 2; ++j) rnd[j] = mix32(key + (uint32_t)j * 0x85ebca77u);
 #pragma unroll
             for (int a = 0; a < 15; ++a)
-                Buf<S>::st(ro, own + (uint32_t)a * nx,
+                Buf<S>::st(ro, own + (uint32_t)a * run,
                            (float)half_stochastic(d[a], rnd[a >> 1] >> (16 * (a & 1))));
 #pragma unroll
             for (int a = 0; a < QT; ++a)
-                Buf<S>::st(ro, own + (uint32_t)(15 + a) * nx,
+                Buf<S>::st(ro, own + (uint32_t)(15 + a) * run,
                            (float)half_stochastic(gq[a], rnd[(a + 15) >> 1] >> (16 * ((a + 15) & 1))));
             return;
         }
     }
 #pragma unroll
-    for (int a = 0; a < 15; ++a) Buf<S>::st(ro, own + (uint32_t)a * nx, d[a]);
+    for (int a = 0; a < 15; ++a) Buf<S>::st(ro, own + (uint32_t)a * run, d[a]);
 #pragma unroll
-    for (int a = 0; a < QT; ++a) Buf<S>::st(ro, own + (uint32_t)(15 + a) * nx, gq[a]);
+    for (int a = 0; a < QT; ++a) Buf<S>::st(ro, own + (uint32_t)(15 + a) * run, gq[a]);
 }
 
 }  // namespace kern

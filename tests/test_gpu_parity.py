@@ -171,15 +171,16 @@ def test_init_macros_matches_oracle_equilibrium(solver, oracle):
     cav.close()
 
 
-@pytest.mark.parametrize("prec", ["fp32", "fp16"])
-def test_full_size_sampled_one_step(solver, oracle, prec):
+@pytest.mark.parametrize("n,prec", [(512, "fp32"), (512, "fp16"), (1024, "fp32")])
+def test_full_size_sampled_one_step(solver, oracle, n, prec):
     """512^3, Ra = 1e6, D3Q7, in the launch configuration the benchmark
-    times: one step from a non-trivial state, checked on 3000 sampled cells
-    (all corners, edges and faces included) that the oracle updates one by
-    one from the same neighbourhood values."""
+    times, and the largest FP32 cavity one GPU holds here (1024^3: two
+    states of 94 GB, populations at byte offsets far beyond 4 GiB): one
+    step from a non-trivial state, checked on 3000 sampled cells (all
+    corners, edges and faces included) that the oracle updates one by one
+    from the same neighbourhood values."""
     from paper_1710_04751_amd import workloads as W
-    n = 512
-    log(f"case: 512^3 sampled one-step {prec}")
+    log(f"case: {n}^3 sampled one-step {prec}")
     p = oracle.cavity_params(n, 1e6)
     cav = solver.Cavity(solver.make_params(n, 1e6, precision=prec))
     g = torch.Generator(device="cuda").manual_seed(7)
