@@ -53,25 +53,24 @@ struct Store<_Float16> {
     }
 };
 
-// Stochastic rounding to FP16: v goes to the FP16 neighbour below or above
-// with probabilities proportional to its distance from the other, so the
-// rounding is unbiased.  ulp = 2^(e - 10) with e the exponent of |v|
-// (at least -14: FP16 subnormals); |v| / ulp and the floor are exact in
-// FP32, and the result is an FP16 value.  rnd: 16 random bits (the
-// probabilities are resolved to 2^-16 of an ulp).
+// Stochastic rounding to FP16 with the gfx950 conversion instruction: v goes
+// to the FP16 neighbour below or above it in magnitude, the upper one with
+// probability equal to v's distance from the lower one in ulps, so the
+// rounding is unbiased.  The instruction takes its random bits from the high
+// 16 bits of rnd and resolves the probability to 2^-13 of an ulp (the 13
+// FP32 mantissa bits below an FP16 normal's last place): for inputs of
+// either sign, normal and subnormal in FP16, the share of round-ups over all
+// 2^16 values of the high half equals that distance truncated to 13 bits.
 __device__ __forceinline__ _Float16 half_stochastic(float v, uint32_t rnd) {
-    int e = (int)((__float_as_uint(v) >> 23) & 0xffu) - 127;
-    e = e < -14 ? -14 : e;
-    const float ulp = __uint_as_float((uint32_t)(e - 10 + 127) << 23);
-    const float inv = __uint_as_float((uint32_t)(10 - e + 127) << 23);
-    const float u = (float)(rnd & 0xffffu) * (1.0f / 65536.0f);
-    const float r = floorf(fabsf(v) * inv + u) * ulp;
-    return (_Float16)copysignf(r, v);
+    typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+    h2 o = {0, 0};
+    o = __builtin_amdgcn_cvt_sr_f16_f32(o, v, rnd, false);
+    return o[0];
 }
 
 // 32-bit integer mix (the "lowbias32" finaliser of C. Wellons' hash
-// prospector): the random stream of stochastic rounding, keyed by step,
-// population and cell.
+// prospector): the seed of stochastic rounding's random stream, keyed by
+// step and cell.
 __device__ __forceinline__ uint32_t mix32(uint32_t x) {
     x ^= x >> 16;
     x *= 0x7feb352du;
@@ -253,20 +252,29 @@ __device__ __forceinline__ void update_cell(const S* __restrict__ in, S* __restr
 
     if constexpr (std::is_same<S, _Float16>::value) {
         if (k.sr) {
-            // one 32-bit draw gives the 16 random bits of two stores
+            // The cell's random stream: a hash of (step, cell) seeds a
+            // xorshift32 generator (shifts 13, 17, 5; state never 0); each
+            // 32-bit word gives the 16 random bits of two stores.
             const uint32_t cell = ((uint32_t)z * ny + (uint32_t)y) * nx + (uint32_t)x;
-            const uint32_t key = mix32(k.seed * 0x9e3779b9u ^ cell);
+            uint32_t xs = mix32(k.seed * 0x9e3779b9u ^ cell);
+            xs = xs ? xs : 0x9e3779b9u;
             uint32_t rnd[(15 + QT + 1) / 2];
 #pragma unroll
-            for (int j = 0; j < (15 + QT + 1) / 2; ++j) rnd[j] = mix32(key + (uint32_t)j * 0x85ebca77u);
+            for (int j = 0; j < (15 + QT + 1) / 2; ++j) {
+                xs ^= xs << 13;
+                xs ^= xs >> 17;
+                xs ^= xs << 5;
+                rnd[j] = xs;
+            }
+            // value 2j takes the high half of word j, value 2j + 1 the low half
 #pragma unroll
             for (int a = 0; a < 15; ++a)
                 Buf<S>::st(ro, own + (uint32_t)a * run,
-                           (float)half_stochastic(d[a], rnd[a >> 1] >> (16 * (a & 1))));
+                           (float)half_stochastic(d[a], rnd[a >> 1] << (16 * (a & 1))));
 #pragma unroll
             for (int a = 0; a < QT; ++a)
                 Buf<S>::st(ro, own + (uint32_t)(15 + a) * run,
-                           (float)half_stochastic(gq[a], rnd[(a + 15) >> 1] >> (16 * ((a + 15) & 1))));
+                           (float)half_stochastic(gq[a], rnd[(a + 15) >> 1] << (16 * ((a + 15) & 1))));
             return;
         }
     }
