@@ -33,7 +33,9 @@
  *     as void*; NULL is the default stream).  Only functions documented as
  *     synchronising wait for the device.
  *   - Field layout: one value per cell, x fastest: index (z*ny + y)*nx + x.
- *   - Population arrays: population a of cell c at [a*ncell + c].
+ *   - Population arrays exchanged with the caller: population a of cell c
+ *     at [a*ncell + c].  The stored state itself groups rows (see
+ *     lbm_state_info).
  */
 #ifndef LBM_H_
 #define LBM_H_
