@@ -357,8 +357,10 @@ lbm_status lbm_batch_run_to_steady(lbm_batch* b, double tol, int64_t check_every
                                    double* last_residual);
 
 /* Launch shape: threads per block (a multiple of 64, >= the largest nx, at
- * most 1024), blocks per compute unit (1..32), steps per captured graph
- * (even, 0 disables graphs). */
+ * most 1024), blocks per compute unit (1..32: a persistent grid whose blocks
+ * walk the tile list; 0: one block per tile of the whole batch, blocks past
+ * the active tiles returning at once), steps per captured graph (even, 0
+ * disables graphs). */
 lbm_status lbm_batch_set_launch(lbm_batch* b, int32_t threads, int32_t blocks_per_cu,
                                 int32_t graph_steps);
 

@@ -225,6 +225,7 @@ struct lbm_batch {
     bool general;
     int64_t gsteps;     // steps taken by the batch (global parity)
     int threads, bpc, graph_steps, cu_count;
+    int64_t tiles_all;  // tiles of all members at the current block size
     hipGraphExec_t graph;
     bool graph_ok;
     std::vector<DevCav> table;
@@ -273,6 +274,7 @@ void fill_kcoef(const lbm_handle* h, KCoef<R>* k) {
 // Rebuild the host table for the current launch shape and upload it, then
 // rebuild the device tile list.
 lbm_status upload_table(lbm_batch* b) {
+    b->tiles_all = 0;
     for (int i = 0; i < b->n; ++i) {
         const lbm_handle* h = b->mem[i];
         DevCav& d = b->table[i];
@@ -288,6 +290,7 @@ lbm_status upload_table(lbm_batch* b) {
         d.nz = h->p.nz;
         d.rows = std::max(1, b->threads / h->p.nx);
         d.ytiles = (h->p.ny + d.rows - 1) / d.rows;
+        b->tiles_all += (int64_t)d.nz * d.ytiles;
         d.magic = (uint32_t)(((1u << 20) + (uint32_t)h->p.nx - 1) / (uint32_t)h->p.nx);
         // the row index must be exact for every lane of the block
         for (uint32_t lane = 0; lane < (uint32_t)b->threads; ++lane)
@@ -329,8 +332,15 @@ lbm_status upload_table(lbm_batch* b) {
         }                                                                              \
     } while (0)
 
+// Grid of the batched kernels: bpc blocks per compute unit walking the tile
+// list, or (bpc = 0) one block per tile of the whole batch; blocks beyond the
+// active tiles return at once, so the grid stays valid as members retire.
+unsigned batch_grid(const lbm_batch* b) {
+    return (unsigned)(b->bpc > 0 ? (int64_t)b->cu_count * b->bpc : std::max<int64_t>(1, b->tiles_all));
+}
+
 hipError_t launch_one_step(lbm_batch* b, int parity) {
-    const dim3 grid((unsigned)(b->cu_count * b->bpc)), block((unsigned)b->threads);
+    const dim3 grid(batch_grid(b)), block((unsigned)b->threads);
     LBM_BATCH_DISPATCH(b->prec, b->qt, b->general, {
         hipLaunchKernelGGL((k_batch_step<R, S, Q, G>), grid, block, 0, b->stream, b->d_table(),
                            b->d_tiles(), b->d_ntiles(), parity);
@@ -499,7 +509,7 @@ lbm_status lbm_batch_residuals(lbm_batch* b, double* max_dT, int32_t* status) {
     if (e != hipSuccess) return hip_fail(e, "residual flags");
     hipLaunchKernelGGL(k_zero_u64, dim3((2 * b->n + 255) / 256), dim3(256), 0, b->stream,
                        b->d_maxbits(), 2 * b->n);
-    const dim3 grid((unsigned)(b->cu_count * b->bpc)), block((unsigned)b->threads);
+    const dim3 grid(batch_grid(b)), block((unsigned)b->threads);
     const int parity = (int)(b->gsteps & 1);
     if (b->prec == Prec::FP64) {
         if (b->qt == 7)
@@ -627,7 +637,8 @@ lbm_status lbm_batch_set_launch(lbm_batch* b, int32_t threads, int32_t bpc, int3
     for (lbm_handle* h : b->mem) maxnx = std::max(maxnx, h->p.nx);
     if (threads <= 0 || threads % 64 || threads > 1024 || threads < maxnx)
         return fail(LBM_ERR_ARG, "threads must be a multiple of 64 in [max nx, 1024]");
-    if (bpc < 1 || bpc > 32) return fail(LBM_ERR_ARG, "blocks per compute unit must be 1..32");
+    if (bpc < 0 || bpc > 32)
+        return fail(LBM_ERR_ARG, "blocks per compute unit must be 0 (one block per tile) or 1..32");
     if (graph_steps < 0 || (graph_steps & 1)) return fail(LBM_ERR_ARG, "graph_steps must be even");
     if (graph_steps > 0 && !b->stream)
         return fail(LBM_ERR_ARG, "graphs need a batch created on a non-default stream");
@@ -648,7 +659,7 @@ lbm_status lbm_batch_autotune(lbm_batch* b, int32_t steps_per_trial, int32_t* ou
     int maxnx = 0;
     for (lbm_handle* h : b->mem) maxnx = std::max(maxnx, h->p.nx);
     static const int cand_t[] = {128, 192, 256, 320, 384, 512, 768, 1024};
-    static const int cand_b[] = {2, 4, 8, 16};
+    static const int cand_b[] = {0, 2, 4, 8, 16};  // 0: one block per tile
     const int gsteps_keep = b->graph_steps;
     hipEvent_t e0, e1;
     hipError_t e = hipEventCreate(&e0);
@@ -691,7 +702,7 @@ lbm_status lbm_batch_launch_info(lbm_batch* b, int32_t* threads, int32_t* grid_b
                                  int32_t* active_tiles, int32_t* graph_steps, int64_t* steps) {
     if (!b) return fail(LBM_ERR_ARG, "null batch");
     if (threads) *threads = b->threads;
-    if (grid_blocks) *grid_blocks = b->cu_count * b->bpc;
+    if (grid_blocks) *grid_blocks = (int32_t)batch_grid(b);
     if (graph_steps) *graph_steps = b->graph_ok ? b->graph_steps : 0;
     if (steps) *steps = b->gsteps;
     if (active_tiles) {

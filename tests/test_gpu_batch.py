@@ -72,12 +72,45 @@ def test_retired_member_freezes_and_rejoins(solver):
     batch.close()
 
 
+@pytest.mark.parametrize("bpc", [0, 3])
+def test_launch_shapes_with_graphs_and_retirement(solver, bpc):
+    """One block per tile of the whole batch (bpc = 0; blocks past the active
+    tiles return at once) or a persistent grid of 3 blocks per compute unit,
+    replayed from graphs of 20 steps while two members retire and rejoin:
+    every member bit-identical to the same cavity run alone."""
+    log(f"case: batch launch bpc={bpc}, graphs of 20 steps, retirement")
+    params = _members(solver, "fp32", 7, SIZES, RAS)
+    batch = solver.Batch(params)
+    batch.set_launch(256, bpc, 20)
+    info = batch.launch_info()
+    assert info["threads"] == 256 and info["graph_steps"] == 20
+    if bpc == 0:
+        # tiles of 256 // nx whole x-rows of one plane
+        tiles = sum(nz * -(-ny // max(1, 256 // nx)) for nx, ny, nz in SIZES)
+        assert info["grid_blocks"] == tiles == info["active_tiles"]
+    batch.step(40)
+    batch.set_active([1, 0, 1, 1, 0])
+    batch.step(60)
+    batch.set_active([1, 1, 1, 1, 1])
+    batch.step(20)
+    expect = [120, 60, 120, 120, 60]
+    for i, p in enumerate(params):
+        assert batch.members[i].steps_done() == expect[i]
+        cav = solver.Cavity(p)
+        cav.step(expect[i])
+        Fs, Gs = cav.populations()
+        Fb, Gb = batch.members[i].populations()
+        assert torch.equal(Fs, Fb) and torch.equal(Gs, Gb), i
+        cav.close()
+    batch.close()
+
+
 def test_autotuned_shape_gives_identical_results(solver):
     params = _members(solver, "fp32", 7, SIZES, RAS)
     batch = solver.Batch(params)
     threads, bpc = batch.autotune(steps_per_trial=4)
     log("case: batch autotune ->", threads, bpc)
-    assert threads % 64 == 0 and threads >= 96 and 1 <= bpc <= 32
+    assert threads % 64 == 0 and threads >= 96 and 0 <= bpc <= 32
     done = batch.launch_info()["steps"]
     assert done % 2 == 0
     batch.step(100)
