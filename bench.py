@@ -460,6 +460,8 @@ def main():
                     help="timed steps of the D3Q15-scalar line; 0 skips it")
     ap.add_argument("--source-steps", type=int, default=1000,
                     help="timed steps of the heat-source line (general kernels); 0 skips it")
+    ap.add_argument("--fp64-steps", type=int, default=500,
+                    help="timed steps of the FP64 line (352 B per update); 0 skips it")
     ap.add_argument("--no-precision", action="store_true",
                     help="skip the 512^3 FP32/FP16 comparison with the 128^3 oracle reference")
     ap.add_argument("--warm-start", action="store_true",
@@ -502,6 +504,10 @@ def main():
         src = time_variant(args.n, args.Ra, "fp32", args.source_steps, args.warmup, block, log,
                            R=SOURCE_R)
         log(json.dumps(src))
+    f64 = None
+    if args.fp64_steps > 0:
+        f64 = time_variant(args.n, args.Ra, "fp64", args.fp64_steps, args.warmup, block, log)
+        log(json.dumps(f64))
     batched = None if args.no_batched else time_batched(args.batched_steps, log=log)
     if batched is not None and args.batched_steady:
         batched["to_steady"] = time_batched_steady(log=log)
@@ -565,6 +571,15 @@ def main():
                          "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": round(src["frac_hbm_peak"], 4),
                          "traffic": recorded_traffic(args.n, "fp32_source")},
+        },
+        "fp64": None if f64 is None else {
+            "value": round(f64["mlups"], 1), "unit": "MLUPS", "steps": args.fp64_steps,
+            "storage": "fp64", "ms_per_step": f64["ms_per_step"], "kernel": f64["kernel"],
+            "bytes_per_cell_update": f64["bytes_per_cell_update"],
+            "roofline": {"bound": "hbm", "achieved": round(f64["achieved_GBs"], 1),
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(f64["frac_hbm_peak"], 4),
+                         "traffic": recorded_traffic(args.n, "fp64")},
         },
         "batched": batched,
         "network": nn,
