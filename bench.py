@@ -53,12 +53,17 @@ def algorithmic_bytes_per_cell(precision, qt=7):
     return 2 * (15 + qt) * vb
 
 
-def time_variant(n, ra, precision, steps, warmup, block=None, log=print, R=0.0, sr=0, qt=7):
+def time_variant(n, ra, precision, steps, warmup, block=None, log=print, R=0.0, sr=0, qt=7,
+                 shape=None):
+    """Time the step on an n^3 cavity, or on an nx x ny x nz box when shape
+    is given (the lattice parameters of the n^3 cavity either way)."""
     import torch
     from paper_1710_04751_amd import solver as S
 
     stream = torch.cuda.Stream()
     params = S.make_params(n, ra, precision=precision, R=R, round_stochastic=sr, thermal_q=qt)
+    if shape:
+        params.nx, params.ny, params.nz = shape
     if block:
         params.block_x, params.block_y = block
     cav = S.Cavity(params, stream=stream)
@@ -92,7 +97,7 @@ def time_variant(n, ra, precision, steps, warmup, block=None, log=print, R=0.0, 
     status, _ = cav.residual()
     s2, dT = cav.residual()
     nu = cav.nusselt()
-    ncell = n ** 3
+    ncell = params.nx * params.ny * params.nz
     launch_ms = ms / steps
     mlups = ncell * steps / (ms * 1e-3) / 1e6
     bpc = algorithmic_bytes_per_cell(precision, qt)
@@ -462,6 +467,9 @@ def main():
                     help="timed steps of the heat-source line (general kernels); 0 skips it")
     ap.add_argument("--fp64-steps", type=int, default=500,
                     help="timed steps of the FP64 line (352 B per update); 0 skips it")
+    ap.add_argument("--slab-steps", type=int, default=0,
+                    help="timed FP32 steps on one z-slab of an 8-way split of the n^3 cavity "
+                         "(n x n x n/8, the share of one GPU); 0 (default) skips it")
     ap.add_argument("--no-precision", action="store_true",
                     help="skip the 512^3 FP32/FP16 comparison with the 128^3 oracle reference")
     ap.add_argument("--warm-start", action="store_true",
@@ -508,6 +516,11 @@ def main():
     if args.fp64_steps > 0:
         f64 = time_variant(args.n, args.Ra, "fp64", args.fp64_steps, args.warmup, block, log)
         log(json.dumps(f64))
+    slab = None
+    if args.slab_steps > 0:
+        slab = time_variant(args.n, args.Ra, "fp32", args.slab_steps, args.warmup, block, log,
+                            shape=(args.n, args.n, args.n // 8))
+        log(json.dumps(slab))
     batched = None if args.no_batched else time_batched(args.batched_steps, log=log)
     if batched is not None and args.batched_steady:
         batched["to_steady"] = time_batched_steady(log=log)
@@ -580,6 +593,17 @@ def main():
                          "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": round(f64["frac_hbm_peak"], 4),
                          "traffic": recorded_traffic(args.n, "fp64")},
+        },
+        "slab": None if slab is None else {
+            "shape": [args.n, args.n, args.n // 8], "value": round(slab["mlups"], 1),
+            "unit": "MLUPS", "steps": args.slab_steps, "storage": "fp32",
+            "ms_per_step": slab["ms_per_step"], "block": slab["block"],
+            "roofline": {"bound": "hbm", "achieved": round(slab["achieved_GBs"], 1),
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(slab["frac_hbm_peak"], 4), "traffic": None},
+            # populations with e_z = +1 or -1 that cross one slab face per step
+            # (5 flow + 1 scalar), FP32: what each neighbour exchange would carry
+            "face_bytes_per_step": 6 * args.n * args.n * 4,
         },
         "batched": batched,
         "network": nn,
