@@ -692,9 +692,9 @@ __global__ void k_cf_to_cl(const float* __restrict__ x, int n, int64_t V, int c,
 
 // Forward / input-gradient convolution on LDS-staged bricks (3x3x3 taps,
 // BF16 output, grids of at least 16 cells, input channels a multiple of
-// 16).  A block of 4 waves computes 16 x 4 x 4 output voxels (wave w the
+// 16).  A block of 8 waves computes 16 x 4 x 8 output voxels (wave w the
 // plane z0 + w, its four 16-voxel row tiles y0 .. y0 + 3) for NSUB * 16
-// output channels.  Per 16 input channels the block stages the 18 x 6 x 6
+// output channels.  Per 16 input channels the block stages the 18 x 6 x 10
 // input halo channels-last in LDS (48 bytes per voxel: 16 channels and 8 of
 // padding, which puts the 16-byte reads of 8 consecutive lanes on distinct
 // banks), so every A fragment (8 channels of one voxel for one tap) is one
@@ -702,22 +702,23 @@ __global__ void k_cf_to_cl(const float* __restrict__ x, int n, int64_t V, int c,
 // of the 16 channels; B fragments are read from the packed weight ([co][k],
 // k = tap * cin + channel) and serve the four row tiles.
 constexpr int kCvVox = 24;                  // LDS elements per voxel
-constexpr int kCvHalo = 18 * 6 * 6;         // halo voxels
+constexpr int kCvPlanes = 8;                // output planes (waves) per block
+constexpr int kCvHalo = 18 * 6 * (kCvPlanes + 2);  // halo voxels
 
 template <int NSUB>
-__global__ void __launch_bounds__(256) k_conv_brick(ConvArgs a) {
+__global__ void __launch_bounds__(64 * kCvPlanes) k_conv_brick(ConvArgs a) {
     __shared__ __attribute__((aligned(16))) __bf16 xs[kCvHalo * kCvVox];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r = lane & 15, q = lane >> 4;
     const int lg = a.lg, G = 1 << lg;
-    const int nbx = G >> 4, nby = G >> 2;
+    const int nbx = G >> 4, nby = G >> 2, nbz = G / kCvPlanes;
     int64_t bid = blockIdx.x;
     const int x0 = (int)(bid % nbx) * 16;
     bid /= nbx;
     const int y0 = (int)(bid % nby) * 4;
     bid /= nby;
-    const int z0 = (int)(bid % nby) * 4;
-    const int smp = (int)(bid / nby);
+    const int z0 = (int)(bid % nbz) * kCvPlanes;
+    const int smp = (int)(bid / nbz);
     const int cobase = blockIdx.y * NSUB * 16;
     floatx4 acc[4][NSUB];
 #pragma unroll
@@ -726,7 +727,7 @@ __global__ void __launch_bounds__(256) k_conv_brick(ConvArgs a) {
         for (int j = 0; j < NSUB; ++j) acc[m][j] = floatx4{0.f, 0.f, 0.f, 0.f};
     const int ch = (q & 1) * 8;
     for (int c0 = 0; c0 < a.cin; c0 += 16) {
-        for (int t = tid; t < 2 * kCvHalo; t += 256) {
+        for (int t = tid; t < 2 * kCvHalo; t += 64 * kCvPlanes) {
             const int half = t & 1, hv = t >> 1;
             const int hx = hv % 18, hy = (hv / 18) % 6, hz = hv / 108;
             const int xx = x0 + hx - 1, yy = y0 + hy - 1, zz = z0 + hz - 1;
@@ -836,12 +837,13 @@ hipError_t launch_conv(const ConvArgs& a, int coutp, hipStream_t s) {
         // on the 16-cell grid one output-channel group per block, for blocks
         const int64_t G = (int64_t)1 << a.lg;
         const int nb = a.lg >= 5 ? nsub : 1;
-        const dim3 grid((unsigned)((G / 16) * (G / 4) * (G / 4) * a.n), sub / nb);
+        const dim3 grid((unsigned)((G / 16) * (G / 4) * (G / kCvPlanes) * a.n), sub / nb);
+        const dim3 block(64 * kCvPlanes);
         switch (nb) {
-            case 4: hipLaunchKernelGGL(k_conv_brick<4>, grid, dim3(256), 0, s, a); break;
-            case 3: hipLaunchKernelGGL(k_conv_brick<3>, grid, dim3(256), 0, s, a); break;
-            case 2: hipLaunchKernelGGL(k_conv_brick<2>, grid, dim3(256), 0, s, a); break;
-            default: hipLaunchKernelGGL(k_conv_brick<1>, grid, dim3(256), 0, s, a); break;
+            case 4: hipLaunchKernelGGL(k_conv_brick<4>, grid, block, 0, s, a); break;
+            case 3: hipLaunchKernelGGL(k_conv_brick<3>, grid, block, 0, s, a); break;
+            case 2: hipLaunchKernelGGL(k_conv_brick<2>, grid, block, 0, s, a); break;
+            default: hipLaunchKernelGGL(k_conv_brick<1>, grid, block, 0, s, a); break;
         }
         return hipGetLastError();
     }
