@@ -204,10 +204,17 @@ lbm_status lbm_step(lbm_handle* h, int64_t nsteps);
  * Asynchronous. */
 lbm_status lbm_macros(lbm_handle* h, void* rho, void* ux, void* uy, void* uz, void* T, int fp64);
 
-/* Wall Nusselt numbers of the current state (FP64 reduction on the device).
- * out: host pointer.  Synchronises the stream.  Optional profiles (device
- * pointers, double, may be NULL): local Nu of the hot and cold walls,
- * [nz][ny] each. */
+/* Wall Nusselt numbers of the current state (FP64 reduction on the device),
+ * after the definition of Sec. 3 of the paper: the local Nusselt number is
+ * the wall-normal temperature gradient at a Dirichlet wall scaled by L/dT
+ * (the paper prints it with its axes mixed up), its average over the wall
+ * the mean Nusselt number, and Table 1 reports its mean, maximum and minimum
+ * on the symmetry plane.  The gradient is taken as the lattice's heat flux
+ * through the wall (see lbm_nu), which equals alpha times the gradient for
+ * pure conduction exactly.  out: host pointer.  Synchronises the stream.
+ * Optional profiles (device pointers, double, may be NULL): local Nu of the
+ * hot and cold walls, [nz][ny] each.  Returns LBM_ERR_UNSTABLE if a result
+ * is not finite. */
 lbm_status lbm_nusselt(lbm_handle* h, lbm_nu* out, double* local_hot, double* local_cold);
 
 /* Steady-state residual: max over cells of |T_now - T_snapshot| (host

@@ -49,7 +49,7 @@ extern "C" {
 typedef struct lbm_nn lbm_nn;
 
 typedef struct lbm_nn_config {
-    int32_t grid;          /* edge G of the cubic grid: a multiple of 8, 8..256 */
+    int32_t grid;          /* edge G of the cubic grid: a power of two, 8..256 */
     int32_t batch;         /* most samples per call (1..64) */
     float lr;              /* Adam step size */
     float beta1, beta2;    /* Adam moment decay rates (0.9, 0.999) */
@@ -83,21 +83,23 @@ lbm_status lbm_nn_forward(lbm_nn* nn, int32_t n, const float* log10_ra, float* o
                           const float* out_scale);
 
 /* Loss and gradient without a parameter update: targets (device, FP32)
- * hold samples of [4][G][G][G] values target_stride floats apart; sample i
- * of the call uses targets[target_index[i]] (host array of n).  Loss = mean
- * over n * 4 * G^3 of (output - target * target_scale)^2.  grad (device,
- * FP32, parameter layout) receives the gradient when not NULL; *loss (host)
- * the loss.  Synchronises. */
+ * hold target_count samples of [4][G][G][G] values target_stride floats
+ * apart (target_stride >= 4 G^3); sample i of the call uses
+ * targets[target_index[i]] (host array of n).  An index outside
+ * [0, target_count) is LBM_ERR_ARG before any launch.  Loss = mean over
+ * n * 4 * G^3 of (output - target * target_scale)^2.  grad (device, FP32,
+ * parameter layout) receives the gradient when not NULL; *loss (host) the
+ * loss.  Synchronises. */
 lbm_status lbm_nn_gradient(lbm_nn* nn, int32_t n, const float* log10_ra, const float* targets,
-                           const int32_t* target_index, int64_t target_stride, float* grad,
-                           double* loss);
+                           int64_t target_count, const int32_t* target_index,
+                           int64_t target_stride, float* grad, double* loss);
 
 /* One training step: forward, loss, backward and an Adam update of every
  * parameter, on the same arguments as lbm_nn_gradient.  loss (host) may be
  * NULL; when given the call synchronises to return it. */
 lbm_status lbm_nn_train_step(lbm_nn* nn, int32_t n, const float* log10_ra,
-                             const float* targets, const int32_t* target_index,
-                             int64_t target_stride, double* loss);
+                             const float* targets, int64_t target_count,
+                             const int32_t* target_index, int64_t target_stride, double* loss);
 
 /* Change the Adam step size for later training steps (learning-rate
  * schedules); lr > 0. */

@@ -130,11 +130,11 @@ _SIGS = {
     "lbm_nn_forward": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_float), vp,
                                       ctypes.POINTER(ctypes.c_float)]),
     "lbm_nn_gradient": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_float), vp,
-                                       ctypes.POINTER(ctypes.c_int32), ctypes.c_int64, vp,
-                                       ctypes.POINTER(ctypes.c_double)]),
+                                       ctypes.c_int64, ctypes.POINTER(ctypes.c_int32),
+                                       ctypes.c_int64, vp, ctypes.POINTER(ctypes.c_double)]),
     "lbm_nn_train_step": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_float), vp,
-                                         ctypes.POINTER(ctypes.c_int32), ctypes.c_int64,
-                                         ctypes.POINTER(ctypes.c_double)]),
+                                         ctypes.c_int64, ctypes.POINTER(ctypes.c_int32),
+                                         ctypes.c_int64, ctypes.POINTER(ctypes.c_double)]),
     "lbm_nn_set_lr": (ctypes.c_int, [vp, ctypes.c_float]),
     "lbm_nn_activation": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.c_int32, vp]),
     "lbm_nn_flops": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
@@ -437,18 +437,20 @@ def lbm_nn_forward(h, log10_ra, out_ptr, out_scale=None):
     return check(lib().lbm_nn_forward(h, len(log10_ra), _floats(log10_ra), out_ptr, sc))
 
 
-def lbm_nn_gradient(h, log10_ra, targets_ptr, target_index, target_stride, grad_ptr=None):
+def lbm_nn_gradient(h, log10_ra, targets_ptr, target_count, target_index, target_stride,
+                    grad_ptr=None):
     loss = ctypes.c_double()
     check(lib().lbm_nn_gradient(h, len(log10_ra), _floats(log10_ra), targets_ptr,
-                                _ints(target_index), int(target_stride), grad_ptr,
-                                ctypes.byref(loss)))
+                                int(target_count), _ints(target_index), int(target_stride),
+                                grad_ptr, ctypes.byref(loss)))
     return loss.value
 
 
-def lbm_nn_train_step(h, log10_ra, targets_ptr, target_index, target_stride, want_loss=True):
+def lbm_nn_train_step(h, log10_ra, targets_ptr, target_count, target_index, target_stride,
+                      want_loss=True):
     loss = ctypes.c_double()
     check(lib().lbm_nn_train_step(h, len(log10_ra), _floats(log10_ra), targets_ptr,
-                                  _ints(target_index), int(target_stride),
+                                  int(target_count), _ints(target_index), int(target_stride),
                                   ctypes.byref(loss) if want_loss else None))
     return loss.value if want_loss else None
 

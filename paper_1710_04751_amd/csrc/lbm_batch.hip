@@ -570,13 +570,12 @@ lbm_status lbm_batch_residuals(lbm_batch* b, double* max_dT, int32_t* status) {
 
 lbm_status lbm_batch_set_active(lbm_batch* b, const int32_t* active) {
     if (!b || !active) return fail(LBM_ERR_ARG, "null argument");
-    for (int i = 0; i < b->n; ++i) {
-        const int a = active[i] ? 1 : 0;
-        if (a && !b->active[i] && b->mem[i]->cur != (int)(b->gsteps & 1))
+    // validate the whole request first, so a refused call leaves the batch as it was
+    for (int i = 0; i < b->n; ++i)
+        if (active[i] && !b->active[i] && b->mem[i]->cur != (int)(b->gsteps & 1))
             return fail(LBM_ERR_STATE, "member " + std::to_string(i) +
                                            " cannot rejoin at this step parity");
-        b->active[i] = a;
-    }
+    for (int i = 0; i < b->n; ++i) b->active[i] = active[i] ? 1 : 0;
     return upload_table(b);
 }
 

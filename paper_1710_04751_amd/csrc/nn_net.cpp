@@ -296,12 +296,14 @@ lbm_status check_call(lbm_nn* nn, int n, const float* lra) {
     return LBM_OK;
 }
 
-lbm_status check_targets(const float* targets, const int32_t* idx, int n, int64_t stride,
-                         int64_t need) {
+lbm_status check_targets(const float* targets, int64_t count, const int32_t* idx, int n,
+                         int64_t stride, int64_t need) {
     if (!targets || !idx) return lbm::fail(LBM_ERR_ARG, "null targets");
     if (stride < need) return lbm::fail(LBM_ERR_ARG, "target_stride below 4 G^3");
+    if (count < 1) return lbm::fail(LBM_ERR_ARG, "target_count must be positive");
     for (int i = 0; i < n; ++i)
-        if (idx[i] < 0) return lbm::fail(LBM_ERR_ARG, "negative target index");
+        if (idx[i] < 0 || idx[i] >= count)
+            return lbm::fail(LBM_ERR_ARG, "target index outside [0, target_count)");
     return LBM_OK;
 }
 
@@ -405,11 +407,12 @@ lbm_status lbm_nn_forward(lbm_nn* nn, int32_t n, const float* log10_ra, float* o
 }
 
 lbm_status lbm_nn_gradient(lbm_nn* nn, int32_t n, const float* log10_ra, const float* targets,
-                           const int32_t* target_index, int64_t target_stride, float* grad,
-                           double* loss) {
+                           int64_t target_count, const int32_t* target_index,
+                           int64_t target_stride, float* grad, double* loss) {
     lbm_status st = check_call(nn, n, log10_ra);
     if (st != LBM_OK) return st;
-    st = check_targets(targets, target_index, n, target_stride, (int64_t)4 << (3 * nn->lg0));
+    st = check_targets(targets, target_count, target_index, n, target_stride,
+                       (int64_t)4 << (3 * nn->lg0));
     if (st != LBM_OK) return st;
     if (!loss) return lbm::fail(LBM_ERR_ARG, "null loss");
     st = loss_and_backward(nn, n, log10_ra, targets, target_index, target_stride);
@@ -422,11 +425,12 @@ lbm_status lbm_nn_gradient(lbm_nn* nn, int32_t n, const float* log10_ra, const f
 }
 
 lbm_status lbm_nn_train_step(lbm_nn* nn, int32_t n, const float* log10_ra,
-                             const float* targets, const int32_t* target_index,
-                             int64_t target_stride, double* loss) {
+                             const float* targets, int64_t target_count,
+                             const int32_t* target_index, int64_t target_stride, double* loss) {
     lbm_status st = check_call(nn, n, log10_ra);
     if (st != LBM_OK) return st;
-    st = check_targets(targets, target_index, n, target_stride, (int64_t)4 << (3 * nn->lg0));
+    st = check_targets(targets, target_count, target_index, n, target_stride,
+                       (int64_t)4 << (3 * nn->lg0));
     if (st != LBM_OK) return st;
     st = loss_and_backward(nn, n, log10_ra, targets, target_index, target_stride);
     if (st != LBM_OK) return st;

@@ -89,24 +89,27 @@ class WarmStartNet:
         return out
 
     def _targets(self, targets):
-        if targets.dtype != torch.float32 or not targets.is_contiguous():
-            raise ValueError("targets must be a contiguous float32 tensor [N][4][G][G][G]")
-        return targets.data_ptr(), 4 * self.grid ** 3
+        g = self.grid
+        if (targets.dtype != torch.float32 or not targets.is_contiguous() or targets.dim() != 5
+                or tuple(targets.shape[1:]) != (4, g, g, g) or targets.device != self.device):
+            raise ValueError(f"targets must be a contiguous float32 device tensor [N][4][{g}]"
+                             f"[{g}][{g}]")
+        return targets.data_ptr(), targets.shape[0], 4 * g ** 3
 
     def gradient(self, log10_ra, targets, index):
         """(loss, gradient [P]) for samples targets[index[i]] (no update)."""
-        ptr, stride = self._targets(targets)
+        ptr, count, stride = self._targets(targets)
         g = torch.empty(self.P, dtype=torch.float32, device=self.device)
         self._ready()
-        loss = capi.lbm_nn_gradient(self.h, list(log10_ra), ptr, list(index), stride,
+        loss = capi.lbm_nn_gradient(self.h, list(log10_ra), ptr, count, list(index), stride,
                                     g.data_ptr())
         self._done()
         return loss, g
 
     def train_step(self, log10_ra, targets, index, want_loss=True):
-        ptr, stride = self._targets(targets)
+        ptr, count, stride = self._targets(targets)
         self._ready()
-        loss = capi.lbm_nn_train_step(self.h, list(log10_ra), ptr, list(index), stride,
+        loss = capi.lbm_nn_train_step(self.h, list(log10_ra), ptr, count, list(index), stride,
                                       want_loss)
         self._done()
         return loss

@@ -514,3 +514,106 @@ def test_source_conduction_converges_to_the_parabola(oracle, qt):
         errs.append(np.max(np.abs(mac[4][0, 0] - exact)) / np.max(exact))
     assert errs[-1] < 2e-3
     assert 3.5 < errs[0] / errs[1] < 4.5 and 3.5 < errs[1] / errs[2] < 4.5
+
+
+# --------------------------------------------------------------------------
+# The Maxwellian fourth-order option of the flow collision, and the
+# per-cell entry point used by the sampled full-size checks
+# --------------------------------------------------------------------------
+
+def _central(f, u, px, py, pz):
+    """Central moment sum_a f_a (e_ax - ux)^px (e_ay - uy)^py (e_az - uz)^pz by
+    direct summation."""
+    return float(np.sum(f * (EX15 - u[0]) ** px * (EY15 - u[1]) ** py * (EZ15 - u[2]) ** pz))
+
+
+@pytest.mark.parametrize("fourth_maxwell", [0, 1])
+@pytest.mark.parametrize("seed", range(4))
+def test_moving_flow_equilibrium_is_a_fixed_point(oracle, fourth_maxwell, seed):
+    """Appendix A relaxes every non-conserved central moment toward its
+    equilibrium value; the equilibrium itself (rho != 1, u != 0, no force)
+    must therefore come out of the collision unchanged for any rates, with
+    either fourth-order equilibrium (kxx~ kyy~ / rho or the Maxwellian
+    rho/9).  The state used is checked first to have the discrete Maxwellian
+    central moments (rho; 0; rho/3 on the diagonal, 0 off it; 0 at third
+    order; rho/9 for xxyy), by direct summation, so a wrong constant in
+    either branch breaks the fixed point."""
+    rng = np.random.default_rng(4000 + seed)
+    rho = 1 + 0.2 * rng.uniform(-1, 1)
+    u = 0.1 * rng.uniform(-1, 1, 3)
+    f, _ = oracle.equilibrium(7, rho, u, 0.0)
+    cm = lambda *p: _central(f, u, *p)
+    assert abs(cm(0, 0, 0) - rho) < 1e-14
+    for p in [(1, 0, 0), (0, 1, 0), (0, 0, 1), (1, 1, 0), (1, 0, 1), (0, 1, 1),
+              (1, 2, 0), (2, 1, 0), (2, 0, 1), (1, 1, 1)]:
+        assert abs(cm(*p)) < 1e-14, p
+    for p in [(2, 0, 0), (0, 2, 0), (0, 0, 2)]:
+        assert abs(cm(*p) - rho / 3) < 1e-14, p
+    assert abs(cm(2, 2, 0) - rho / 9) < 1e-14
+    w = np.concatenate([np.zeros(4), rng.uniform(0.1, 1.95, 11)])
+    out, r, uo = oracle.collide_flow(f, [0, 0, 0], w, fourth_maxwell=fourth_maxwell)
+    assert abs(r - rho) < 1e-14 and np.allclose(uo, u, rtol=0, atol=1e-15)
+    assert np.allclose(out, f, rtol=0, atol=2e-15)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_fourth_order_central_moment_relaxation(oracle, seed):
+    """Post-collision xxyy central moment, by direct summation about
+    u = (sum f e + F/2)/rho (eq. 3): the source carries the force in its
+    first-order central moments only, so xxyy relaxes from the pre-collision
+    value as (1 - w14) c14 + w14 c14_eq, with c14_eq = rho/9 (Maxwellian
+    option) or kxx~ kyy~ / rho, kxx~ and kyy~ the post-collision diagonal
+    second-order central moments (Appendix A)."""
+    rng = np.random.default_rng(4100 + seed)
+    f = W15 * (1 + 0.1 * rng.standard_normal(15)) * (1 + 0.1 * rng.uniform(-1, 1))
+    F = 1e-3 * rng.standard_normal(3)
+    w = np.concatenate([np.zeros(4), rng.uniform(0.1, 1.95, 11)])
+    rho = f.sum()
+    u = (E15.T @ f + F / 2) / rho
+    c14 = _central(f, u, 2, 2, 0)
+    for fm in (0, 1):
+        out, _, _ = oracle.collide_flow(f, F, w, fourth_maxwell=fm)
+        kxx, kyy = _central(out, u, 2, 0, 0), _central(out, u, 0, 2, 0)
+        eq = rho / 9 if fm else kxx * kyy / rho
+        assert abs(_central(out, u, 2, 2, 0) - ((1 - w[14]) * c14 + w[14] * eq)) < 1e-14
+    # the two options differ unless kxx~ kyy~ = rho^2 / 9
+    a, _, _ = oracle.collide_flow(f, F, w, fourth_maxwell=0)
+    b, _, _ = oracle.collide_flow(f, F, w, fourth_maxwell=1)
+    assert np.max(np.abs(a - b)) > 1e-8
+
+
+@pytest.mark.parametrize("qt,shape,rates", [
+    (7, (5, 4, 3), {}),
+    (15, (4, 6, 5), {}),
+    (7, (6, 5, 4), {"omega_bulk": 1.0, "fourth_maxwell": 1, "cs2T": 0.25, "R": 1e-3}),
+    (15, (5, 3, 4), {"omega_hi": 1.3, "omega_hiT": 0.8}),
+])
+def test_step_cells_equals_one_step_of_run(oracle, qt, shape, rates):
+    """The per-cell entry point (one update of listed cells from their
+    3x3x3 neighbourhoods, entries outside the box set to NaN) gives, for
+    every cell of a ragged walled box, exactly what one step of the whole
+    box gives: the same populations and the same macroscopic fields."""
+    from paper_1710_04751_amd import workloads as W
+    nx, ny, nz = shape
+    p = oracle.cavity_params(nx, 3e3, u0=0.1, qt=qt, ny=ny, nz=nz, **rates)
+    F, G = oracle.rest_state(p)
+    F = F + W.perturbation(F.shape[1:], 15, 21, 1e-3)
+    G = G + W.perturbation(G.shape[1:], qt, 22, 5e-2)
+    F1, G1, mac1 = oracle.run(p, 1, F, G)
+    pos = np.array([(x, y, z) for z in range(nz) for y in range(ny) for x in range(nx)],
+                   dtype=np.int32)
+    nb = np.full((len(pos), 27, 15 + qt), np.nan)
+    for i, (x, y, z) in enumerate(pos):
+        for dz in (-1, 0, 1):
+            for dy in (-1, 0, 1):
+                for dx in (-1, 0, 1):
+                    sx, sy, sz = x + dx, y + dy, z + dz
+                    if 0 <= sx < nx and 0 <= sy < ny and 0 <= sz < nz:
+                        k = (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1)
+                        nb[i, k, :15] = F[:, sz, sy, sx]
+                        nb[i, k, 15:] = G[:, sz, sy, sx]
+    fo, go, mac = oracle.step_cells(p, nb, pos)
+    xs, ys, zs = pos[:, 0], pos[:, 1], pos[:, 2]
+    assert np.array_equal(fo, F1[:, zs, ys, xs].T)
+    assert np.array_equal(go, G1[:, zs, ys, xs].T)
+    assert np.array_equal(mac, mac1[:, zs, ys, xs].T)
