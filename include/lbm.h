@@ -217,6 +217,21 @@ lbm_status lbm_macros(lbm_handle* h, void* rho, void* ux, void* uy, void* uz, vo
  * is not finite. */
 lbm_status lbm_nusselt(lbm_handle* h, lbm_nu* out, double* local_hot, double* local_cold);
 
+/* lbm_nusselt for callers that cannot allocate or hand over scratch memory
+ * (code under stream capture, tight serving loops, harnesses that forbid
+ * allocation): the same kernels and results (bit for bit), with the local
+ * profiles and the reduced values in a device array that the library holds
+ * on each device it runs on until the process ends (2 * 2^20 + 8 doubles,
+ * 16 MiB), instead of in the handle's workspace.  Limit: ny * nz <= 2^20
+ * (LBM_ERR_ARG beyond it, before any launch).  The handle's device must be
+ * current (LBM_ERR_STATE otherwise).  Allocates nothing.  Every call on a
+ * device shares that device's array: calls that overlap on one device (from
+ * several threads or streams) race and must be serialised by the caller.
+ * out: host pointer; local_hot, local_cold: optional device pointers as in
+ * lbm_nusselt.  Synchronises the stream. */
+lbm_status lbm_nusselt_noalloc(lbm_handle* h, lbm_nu* out, double* local_hot,
+                               double* local_cold);
+
 /* Steady-state residual: max over cells of |T_now - T_snapshot| (host
  * pointer), then T_now becomes the snapshot.  The first call after an
  * initialisation only takes the snapshot and reports +inf.  Returns

@@ -6,8 +6,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbm.so")
-SOURCES = ["lbm_step.hip", "lbm_kernels.hip", "lbm_observe.hip", "lbm_batch.hip", "lbm_api.cpp", "nn_kernels.hip",
-           "nn_net.cpp"]
+SOURCES = ["lbm_step.hip", "lbm_kernels.hip", "lbm_observe.hip", "lbm_batch.hip", "lbm_api.cpp", "lbm_noalloc.hip",
+           "nn_kernels.hip", "nn_net.cpp"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [

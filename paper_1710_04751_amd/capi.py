@@ -78,6 +78,7 @@ _SIGS = {
     "lbm_step": (ctypes.c_int, [H, ctypes.c_int64]),
     "lbm_macros": (ctypes.c_int, [H, vp, vp, vp, vp, vp, ctypes.c_int]),
     "lbm_nusselt": (ctypes.c_int, [H, ctypes.POINTER(lbm_nu), vp, vp]),
+    "lbm_nusselt_noalloc": (ctypes.c_int, [H, ctypes.POINTER(lbm_nu), vp, vp]),
     "lbm_residual": (ctypes.c_int, [H, ctypes.POINTER(ctypes.c_double)]),
     "lbm_centerlines": (ctypes.c_int, [H, vp, vp, ctypes.POINTER(lbm_peaks)]),
     "lbm_symmetrize": (ctypes.c_int, [H, vp, vp, vp, vp]),
@@ -231,6 +232,12 @@ def lbm_macros(h, rho=None, ux=None, uy=None, uz=None, T=None, fp64=False):
 def lbm_nusselt(h, local_hot=None, local_cold=None):
     out = lbm_nu()
     check(lib().lbm_nusselt(h, ctypes.byref(out), local_hot, local_cold))
+    return out
+
+
+def lbm_nusselt_noalloc(h, local_hot=None, local_cold=None):
+    out = lbm_nu()
+    check(lib().lbm_nusselt_noalloc(h, ctypes.byref(out), local_hot, local_cold))
     return out
 
 

@@ -229,7 +229,40 @@ lbm_status make_handle(const lbm_params* p, void* workspace, size_t bytes, void*
     if (!bx || !by) default_block(p->nx, &bx, &by);
     set_geom(h, bx, by);
     h->owner = nullptr;
+    if (hipGetDevice(&h->device) != hipSuccess) h->device = -1;
     *out = h;
+    return LBM_OK;
+}
+
+lbm_status nusselt_into(lbm_handle* h, double* prof_hot, double* prof_cold, double* result,
+                        lbm_nu* out, double* local_hot, double* local_cold) {
+    hipError_t e = launch_nusselt((Prec)h->p.precision, h->p.thermal_q, h->geom, h->lay.pl,
+                                  h->buf(h->cur), prof_hot, prof_cold, result, h->c, h->stream);
+    if (e != hipSuccess) return hip_fail(e, "nusselt");
+    const size_t nb = (size_t)h->p.ny * h->p.nz * sizeof(double);
+    if (local_hot) {
+        e = hipMemcpyAsync(local_hot, prof_hot, nb, hipMemcpyDeviceToDevice, h->stream);
+        if (e != hipSuccess) return hip_fail(e, "nusselt copy");
+    }
+    if (local_cold) {
+        e = hipMemcpyAsync(local_cold, prof_cold, nb, hipMemcpyDeviceToDevice, h->stream);
+        if (e != hipSuccess) return hip_fail(e, "nusselt copy");
+    }
+    double r[8];
+    e = hipMemcpyAsync(r, result, sizeof r, hipMemcpyDeviceToHost, h->stream);
+    if (e != hipSuccess) return hip_fail(e, "nusselt copy");
+    e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(e, "nusselt sync");
+    out->nu_hot_wall = r[0];
+    out->nu_cold_wall = r[1];
+    out->nu_hot_mid = r[2];
+    out->nu_cold_mid = r[3];
+    out->nu_max = r[4];
+    out->z_max = r[5];
+    out->nu_min = r[6];
+    out->z_min = r[7];
+    for (double v : r)
+        if (!std::isfinite(v)) return fail(LBM_ERR_UNSTABLE, "non-finite Nusselt number");
     return LBM_OK;
 }
 
@@ -365,35 +398,7 @@ lbm_status lbm_macros(lbm_handle* h, void* rho, void* ux, void* uy, void* uz, vo
 
 lbm_status lbm_nusselt(lbm_handle* h, lbm_nu* out, double* local_hot, double* local_cold) {
     if (!h || !out) return fail(LBM_ERR_ARG, "null argument");
-    hipError_t e = launch_nusselt((Prec)h->p.precision, h->p.thermal_q, h->geom, h->lay.pl,
-                                  h->buf(h->cur), h->nu_hot(), h->nu_cold(), h->red(), h->c,
-                                  h->stream);
-    if (e != hipSuccess) return hip_fail(e, "nusselt");
-    const size_t nb = (size_t)h->p.ny * h->p.nz * sizeof(double);
-    if (local_hot) {
-        e = hipMemcpyAsync(local_hot, h->nu_hot(), nb, hipMemcpyDeviceToDevice, h->stream);
-        if (e != hipSuccess) return hip_fail(e, "nusselt copy");
-    }
-    if (local_cold) {
-        e = hipMemcpyAsync(local_cold, h->nu_cold(), nb, hipMemcpyDeviceToDevice, h->stream);
-        if (e != hipSuccess) return hip_fail(e, "nusselt copy");
-    }
-    double r[8];
-    e = hipMemcpyAsync(r, h->red(), sizeof r, hipMemcpyDeviceToHost, h->stream);
-    if (e != hipSuccess) return hip_fail(e, "nusselt copy");
-    e = hipStreamSynchronize(h->stream);
-    if (e != hipSuccess) return hip_fail(e, "nusselt sync");
-    out->nu_hot_wall = r[0];
-    out->nu_cold_wall = r[1];
-    out->nu_hot_mid = r[2];
-    out->nu_cold_mid = r[3];
-    out->nu_max = r[4];
-    out->z_max = r[5];
-    out->nu_min = r[6];
-    out->z_min = r[7];
-    for (double v : r)
-        if (!std::isfinite(v)) return fail(LBM_ERR_UNSTABLE, "non-finite Nusselt number");
-    return LBM_OK;
+    return nusselt_into(h, h->nu_hot(), h->nu_cold(), h->red(), out, local_hot, local_cold);
 }
 
 lbm_status lbm_residual(lbm_handle* h, double* max_dT) {

@@ -35,6 +35,12 @@ void default_block(int nx, int* bx, int* by);
 // Create a handle over caller memory without touching the device.
 lbm_status make_handle(const lbm_params* p, void* workspace, size_t bytes, void* stream,
                        lbm_handle** out);
+// Wall Nusselt numbers of h's current state with the local profiles in
+// prof_hot / prof_cold (ny*nz doubles each) and the eight reduced values in
+// result (device memory); copies the profiles to local_hot / local_cold when
+// given, then synchronises and fills out.
+lbm_status nusselt_into(lbm_handle* h, double* prof_hot, double* prof_cold, double* result,
+                        lbm_nu* out, double* local_hot, double* local_cold);
 
 }  // namespace lbm
 
@@ -51,6 +57,7 @@ struct lbm_handle {
     bool general;
     lbm::Geom geom;
     lbm_batch* owner;  // set for members of a batch (the batch steps them)
+    int device;        // HIP device current at creation (-1 if unknown)
 
     lbm::StateBuf buf(int which) const {
         char* base = ws + (which ? lay.off_B : lay.off_A);
