@@ -203,25 +203,28 @@ def time_batched(steps, log=print):
             "graph_steps": info["graph_steps"]}
 
 
-def time_batched_steady(log=print):
+def time_batched_steady(sequential=False, log=print):
     """Every cavity of the batch run to steady state (the steady rule of
-    workloads.STEADY_RULE): once in the batch, retiring members as they
-    converge, and once cavity after cavity with single-cavity launches.
-    Aggregate MLUPS = sum over cavities of cells x steps taken / wall time."""
+    workloads.STEADY_RULE, step limit 400,000) in the batch, retiring
+    members as they stop; optionally once more cavity after cavity with
+    single-cavity launches.  Aggregate MLUPS = sum over cavities of cells x
+    steps taken / wall time."""
     import torch
+    from paper_1710_04751_amd import capi
     from paper_1710_04751_amd import solver as S
     from paper_1710_04751_amd import workloads as W
 
     params = batched_params()
     cells = [p.nx * p.ny * p.nz for p in params]
     rule = dict(W.STEADY_RULE)
+    cap = 400_000
     batch = S.Batch(params)
     threads, bpc = batch.autotune(steps_per_trial=6)
     for m in batch.members:  # autotuning advanced the members: start from rest
         m.init_rest()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    steps_b, how_b, _ = batch.run_to_steady(max_steps=1_000_000, **rule)
+    steps_b, how_b, res_b = batch.run_to_steady(max_steps=cap, **rule)
     torch.cuda.synchronize()
     wall_b = time.perf_counter() - t0
     done_b = [m.steps_done() for m in batch.members]
@@ -229,14 +232,34 @@ def time_batched_steady(log=print):
     batch.close()
     del batch
     torch.cuda.empty_cache()
-    log(f"batched to steady: {wall_b:.1f} s, {upd_b / wall_b / 1e6:.0f} MLUPS")
+    names = {capi.LBM_STEADY_TOL: "tol", capi.LBM_STEADY_PLATEAU: "plateau",
+             capi.LBM_STEADY_MAX_STEPS: "max_steps", capi.LBM_STEADY_UNSTABLE: "unstable",
+             capi.LBM_STEADY_STALLED: "stalled"}
+    ended = [names[h] for h in how_b]
+    conv = [i for i, e in enumerate(ended) if e in ("tol", "plateau")]
+    stalled = [i for i, e in enumerate(ended) if e == "stalled"]
+    members = W.batched_cavities()
+    log(f"batched to steady: {wall_b:.1f} s, {upd_b / wall_b / 1e6:.0f} MLUPS, "
+        f"{len(conv)} steady, {len(stalled)} stalled")
+    out = {"value": round(upd_b / wall_b / 1e6, 1), "unit": "MLUPS", "wall_s": round(wall_b, 2),
+           "cell_updates": upd_b, "rule": rule, "max_steps": cap,
+           "ended": {e: ended.count(e) for e in sorted(set(ended))},
+           "steps_to_steady": steps_b, "steps_run": done_b,
+           "steady_members": [{"n": members[i][0], "Ra": round(members[i][1], 1),
+                               "steps": steps_b[i]} for i in conv],
+           "stalled_members": [{"n": members[i][0], "Ra": round(members[i][1], 1),
+                                "steps_run": done_b[i], "last_residual": res_b[i]}
+                               for i in stalled],
+           "threads": threads, "blocks_per_cu": bpc}
+    if not sequential:
+        return out
     stream = torch.cuda.Stream()
     wall_s, upd_s, steps_s = 0.0, 0, []
     for i, p in enumerate(params):
         cav = S.Cavity(p, stream=stream)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        st, how, _ = cav.run_to_steady(max_steps=1_000_000, **rule)
+        st, how, _ = cav.run_to_steady(max_steps=cap, **rule)
         torch.cuda.synchronize()
         wall_s += time.perf_counter() - t0
         upd_s += cells[i] * cav.steps_done()
@@ -244,15 +267,13 @@ def time_batched_steady(log=print):
         cav.close()
         if i % 8 == 7:
             log(f"sequential to steady: {i + 1}/{len(params)} cavities, {wall_s:.1f} s")
-    mb, ms = upd_b / wall_b / 1e6, upd_s / wall_s / 1e6
-    log(f"to steady: batched {mb:.0f} MLUPS ({wall_b:.1f} s) vs sequential {ms:.0f} MLUPS "
-        f"({wall_s:.1f} s)")
-    return {"value": round(mb, 1), "unit": "MLUPS", "wall_s": round(wall_b, 2),
-            "sequential_MLUPS": round(ms, 1), "sequential_wall_s": round(wall_s, 2),
-            "speedup_wall": round(wall_s / wall_b, 3), "cell_updates": upd_b,
-            "rule": rule, "ended": {str(h): how_b.count(h) for h in sorted(set(how_b))},
-            "steps_to_steady": steps_b, "steps_to_steady_sequential": steps_s,
-            "threads": threads, "blocks_per_cu": bpc}
+    ms = upd_s / wall_s / 1e6
+    log(f"to steady: batched {out['value']:.0f} MLUPS ({wall_b:.1f} s) vs sequential {ms:.0f} "
+        f"MLUPS ({wall_s:.1f} s)")
+    out.update({"sequential_MLUPS": round(ms, 1), "sequential_wall_s": round(wall_s, 2),
+                "speedup_wall": round(wall_s / wall_b, 3),
+                "steps_to_steady_sequential": steps_s})
+    return out
 
 
 GOLDEN_128 = os.path.join(ROOT, "tests", "golden", "cavity128_ra1e6_d3q7_2500.npz")
@@ -350,19 +371,32 @@ def warm_start(log=print):
     batched solver, GPU training of the network, then every test cavity
     solved from its prediction; steps to the steady rule warm vs cold."""
     from paper_1710_04751_amd import warmstart as WS
+    from paper_1710_04751_amd import workloads as W
+    t0 = time.perf_counter()
     r = WS.study(log=log)
-    keys = ("grid", "train", "test", "ra_range", "train_converged", "test_converged", "epochs",
-            "batch", "train_seconds", "train_tflops", "final_train_loss", "val_loss",
-            "cold_steps_median", "warm_steps_median", "cold_steps_mean", "warm_steps_mean",
-            "steps_ratio_median", "nu_rel_diff_max", "fallbacks", "cold_solve_s", "warm_solve_s")
+    keys = ("grid", "train", "test", "ra_range", "train_converged", "test_converged",
+            "cold_no_steady_state", "lowest_ra_without_steady_state", "highest_ra_converged",
+            "warm_converged_without_cold_steady_state", "epochs", "batch", "train_seconds",
+            "train_tflops", "final_train_loss", "val_loss", "cold_steps_median",
+            "warm_steps_median", "cold_steps_mean", "warm_steps_mean", "steps_ratio_median",
+            "nu_rel_diff_max", "fallbacks", "cold_solve_s", "warm_solve_s")
     out = {k: r[k] for k in keys}
-    out["workload"] = ("64^3 cavities, Ra log-uniform in [1e3, 1e5], 200 training (seed 17101) "
+    out["workload"] = ("64^3 cavities, Ra log-uniform in [1e3, 1e6], 200 training (seed 17101) "
                        "and 50 held-out (seed 17102) Rayleigh numbers, D3Q7, FP32 solver, "
-                       "stable rate set; network BF16/FP32-accumulate on the matrix cores")
+                       f"rate set {W.STABLE_RATES}, u0 0.05, steady rule {W.STEADY_RULE}, "
+                       "step limit 300,000; network BF16/FP32-accumulate on the matrix cores; "
+                       "steps medians over the held-out cavities whose cold solve meets the "
+                       "rule (fallbacks charged warm + cold steps)")
     out["unit"] = "steps to the steady rule"
+    out["no_steady_state_test"] = [
+        {"Ra": round(10 ** u["log10_ra"], 1), "cold": u["cold_how"],
+         "cold_steps_run": u["cold_steps_run"], "cold_last_residual": u["cold_last_residual"],
+         "warm": u["warm_how"]} for u in r["no_steady_state"]]
+    out["wall_s"] = round(time.perf_counter() - t0, 1)
     log(f"warm start: median steps {out['warm_steps_median']:.0f} warm vs "
         f"{out['cold_steps_median']:.0f} cold, max |dNu|/Nu {out['nu_rel_diff_max']:.1e}, "
-        f"training {out['train_tflops']:.1f} TFLOP/s")
+        f"{out['cold_no_steady_state']} of {out['train'] + out['test']} without a steady state "
+        f"from rest, training {out['train_tflops']:.1f} TFLOP/s")
     return out
 
 
@@ -472,11 +506,13 @@ def main():
                          "(n x n x n/8, the share of one GPU); 0 (default) skips it")
     ap.add_argument("--no-precision", action="store_true",
                     help="skip the 512^3 FP32/FP16 comparison with the 128^3 oracle reference")
-    ap.add_argument("--warm-start", action="store_true",
-                    help="also run the learned warm-start study at 64^3 (about 4 minutes)")
-    ap.add_argument("--batched-steady", action="store_true",
-                    help="also run every cavity of the batch to steady state, batched and "
-                         "sequentially (about 3 minutes)")
+    ap.add_argument("--no-warm-start", action="store_true",
+                    help="skip the learned warm-start study at 64^3 (about 3 minutes)")
+    ap.add_argument("--no-batched-steady", action="store_true",
+                    help="skip running every cavity of the batch to steady state")
+    ap.add_argument("--batched-steady-sequential", action="store_true",
+                    help="also run every cavity of the batch to steady state with "
+                         "single-cavity launches, one after another (a few minutes)")
     args = ap.parse_args()
 
     def log(*a):
@@ -522,11 +558,11 @@ def main():
                             shape=(args.n, args.n, args.n // 8))
         log(json.dumps(slab))
     batched = None if args.no_batched else time_batched(args.batched_steps, log=log)
-    if batched is not None and args.batched_steady:
-        batched["to_steady"] = time_batched_steady(log=log)
+    if batched is not None and not args.no_batched_steady:
+        batched["to_steady"] = time_batched_steady(args.batched_steady_sequential, log=log)
     nn = None if args.no_nn else nn_throughput(log=log)
     precision = None if args.no_precision else precision_study(log=log)
-    warm = warm_start(log=log) if args.warm_start else None
+    warm = None if args.no_warm_start else warm_start(log=log)
     cpu = None if args.no_cpu else cpu_baseline(args.n, args.Ra, log=log)
 
     rec = {

@@ -90,8 +90,15 @@ typedef struct lbm_params {
     int32_t block_y;        /* threads per block along y (0 = default) */
     int32_t round_stochastic; /* FP16 storage only: 0 = round to nearest even
                                  (default), 1 = stochastic rounding (unbiased,
-                                 keyed by step, population and cell; not in
-                                 batches) */
+                                 keyed by step, population and cell; a batch
+                                 member draws the bits a single run of it
+                                 draws) */
+    int32_t scalar_specular;  /* zero-gradient condition of the scalar on the
+                                 four adiabatic faces (Sec. 3): 0 = bounce-back
+                                 of g (default), 1 = specular reflection (the
+                                 crossed velocity components reversed, so each
+                                 link keeps its tangential flux; differs from
+                                 bounce-back only on D3Q15) */
     double nu, alpha, gbeta; /* used only when lattice_units == 1 */
 } lbm_params;
 
@@ -134,7 +141,11 @@ typedef enum {
     LBM_STEADY_PLATEAU = 1,   /* residual stopped falling above the tolerance
                                  (the precision's floor) */
     LBM_STEADY_MAX_STEPS = 2, /* step limit reached first */
-    LBM_STEADY_UNSTABLE = 3   /* NaN or Inf appeared */
+    LBM_STEADY_UNSTABLE = 3,  /* NaN or Inf appeared */
+    LBM_STEADY_STALLED = 4    /* residual stopped reaching new minima above the
+                                 plateau floor: the run approached a steady
+                                 state and then left it (a steady state that
+                                 the discrete dynamics does not hold) */
 } lbm_steady;
 
 typedef struct lbm_handle lbm_handle;
@@ -267,16 +278,20 @@ lbm_status lbm_symmetrize(lbm_handle* h, float* ux, float* uy, float* uz, float*
  * new minimum for plateau_checks checks in a row (LBM_STEADY_PLATEAU: the
  * state wanders at the storage precision's floor, e.g. FP32 stalls at a few
  * units in the last place of T; *steps is then the step at which the
- * minimum was first seen), or after max_steps (LBM_STEADY_MAX_STEPS).  A
- * residual that stalls above plateau_floor (a slowly oscillating approach)
- * keeps the run going.  The first check only takes the
- * snapshot.  Outputs (host pointers, may be NULL): steps taken to the
- * stopping criterion, how it ended (lbm_steady), the last residual.
- * Returns LBM_ERR_UNSTABLE (with *how = LBM_STEADY_UNSTABLE) on NaN/Inf.
- * Synchronises. */
+ * minimum was first seen), or when stall_checks > 0 and it has not reached
+ * a new minimum for stall_checks checks in a row while its smallest value
+ * stays at or above plateau_floor (LBM_STEADY_STALLED: the state came near
+ * a steady state and left it again), or after max_steps
+ * (LBM_STEADY_MAX_STEPS).  A residual that falls slowly with oscillations
+ * keeps the run going as long as new minima come within stall_checks
+ * checks.  The first check only takes the snapshot.  Outputs (host
+ * pointers, may be NULL): steps taken to the stopping criterion (-1 unless
+ * it ended with TOL or PLATEAU), how it ended (lbm_steady), the last
+ * residual.  Returns LBM_ERR_UNSTABLE (with *how = LBM_STEADY_UNSTABLE) on
+ * NaN/Inf.  Synchronises. */
 lbm_status lbm_run_to_steady(lbm_handle* h, double tol, int64_t check_every, int64_t max_steps,
-                             int32_t plateau_checks, double plateau_floor, int64_t* steps,
-                             int32_t* how, double* last_residual);
+                             int32_t plateau_checks, double plateau_floor, int32_t stall_checks,
+                             int64_t* steps, int32_t* how, double* last_residual);
 
 /* Full populations as FP64 (device pointers): F [15][ncell], G [q][ncell]
  * (f itself, not the stored deviation).  Either may be NULL.  Asynchronous. */
@@ -335,8 +350,8 @@ lbm_status lbm_copy_probe(void* dst, const void* src, size_t bytes, void* stream
  * ---------------------------------------------------------------------- */
 
 /* Bytes of device workspace for n cavities p[0..n-1] (host array); 0 if any
- * is invalid, if they differ in precision, thermal_q or in whether the
- * higher-order rates are 1, or if n is not in [1, 255]. */
+ * is invalid, if they differ in precision, thermal_q, round_stochastic or in
+ * whether the general collision kernels run, or if n is not in [1, 255]. */
 size_t lbm_batch_workspace_bytes(const lbm_params* p, int32_t n);
 
 /* Create a batch over caller device memory (256-byte aligned, borrowed
@@ -368,15 +383,15 @@ lbm_status lbm_batch_residuals(lbm_batch* b, double* max_dT, int32_t* status);
 lbm_status lbm_batch_set_active(lbm_batch* b, const int32_t* active);
 
 /* Run every active member to steady state with the rule of
- * lbm_run_to_steady (tolerance, plateau, step limit), checking all members
- * every check_every steps (even) and retiring each as it stops.  Outputs
- * (host arrays of n, may be NULL): steps each member took to its stopping
- * criterion (-1 if it hit max_steps or became unstable), how it ended
+ * lbm_run_to_steady (tolerance, plateau, stall, step limit), checking all
+ * members every check_every steps (even) and retiring each as it stops.
+ * Outputs (host arrays of n, may be NULL): steps each member took to its
+ * stopping criterion (-1 unless it ended with TOL or PLATEAU), how it ended
  * (lbm_steady), last residual.  Synchronises. */
 lbm_status lbm_batch_run_to_steady(lbm_batch* b, double tol, int64_t check_every,
                                    int64_t max_steps, int32_t plateau_checks,
-                                   double plateau_floor, int64_t* steps, int32_t* how,
-                                   double* last_residual);
+                                   double plateau_floor, int32_t stall_checks, int64_t* steps,
+                                   int32_t* how, double* last_residual);
 
 /* Launch shape: threads per block (a multiple of 64, >= the largest nx, at
  * most 1024), blocks per compute unit (1..32: a persistent grid whose blocks

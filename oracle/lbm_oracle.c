@@ -406,7 +406,8 @@ typedef struct {
     int32_t nx, ny, nz;
     int32_t qt;            /* thermal lattice: 7 or 15 */
     int32_t periodic;      /* bit 0/1/2: periodic in x/y/z instead of walls */
-    int32_t pad_;
+    int32_t specular;      /* scalar on the adiabatic faces: 0 bounce-back,
+                              1 specular reflection */
     double omega_nu;       /* shear rates omega_4..omega_8 */
     double omega_bulk;     /* trace (bulk) rate omega_9; <= 0 means omega_nu */
     double omega_hi;       /* higher-order flow rates (omega_10..omega_14) */
@@ -442,7 +443,14 @@ static int nbr_index(int dx, int dy, int dz) { return (dz + 1) * 9 + (dy + 1) * 
  *   thermal across an x wall: anti-bounce-back
  *             gbar_a(x) = -G_opp(a)(x) + 2 w_a T_wall (Dirichlet);
  *   thermal across only a y or z wall: bounce-back gbar_a(x) = G_opp(a)(x)
- *             (reading: zero normal flux per link for the adiabatic faces).
+ *             (reading: zero normal flux per link for the adiabatic faces);
+ *             or, with p->specular, specular reflection: the population
+ *             arrives from the mirror image of its source, i.e. it left the
+ *             cell (x - e_ax, y', z') with the velocity components normal to
+ *             the crossed faces reversed, where y' = y if the link crosses a
+ *             y face (else y - e_ay) and likewise z'.  Each link then keeps
+ *             its tangential flux and carries no normal flux, so the zero-
+ *             gradient (Neumann) condition holds link by link.
  *   A link that crosses an x wall and a y/z wall at once takes the Dirichlet
  *   rule (reading).
  * wT[a] is the rest equilibrium of the scalar per unit phi.
@@ -485,8 +493,22 @@ static void step_cell(const real* nb, int x, int y, int z, const oracle_params* 
         } else if (out_x) {
             real Tw = (pos[0] - LT->e[a][0] < 0) ? p->T_hot : p->T_cold;
             gbar[a] = -self[QF + ab] + 2 * wT[a] * Tw;
-        } else {
+        } else if (!p->specular) {
             gbar[a] = self[QF + ab];
+        } else {
+            /* mirror the components along the crossed faces */
+            int m[3] = {LT->e[a][0], LT->e[a][1], LT->e[a][2]}, d[3];
+            d[0] = -LT->e[a][0];
+            for (int k = 1; k < 3; ++k) {
+                int s = pos[k] - LT->e[a][k];
+                int out = (s < 0 || s >= n[k]) && !((p->periodic >> k) & 1);
+                if (out) m[k] = -m[k];
+                d[k] = out ? 0 : -LT->e[a][k];
+            }
+            int b = -1;
+            for (int c = 0; c < qt; ++c)
+                if (LT->e[c][0] == m[0] && LT->e[c][1] == m[1] && LT->e[c][2] == m[2]) b = c;
+            gbar[a] = nb[nbr_index(d[0], d[1], d[2]) * stride + QF + b];
         }
     }
 

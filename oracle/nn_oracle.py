@@ -86,6 +86,33 @@ def conv3d(x, w, b):
     return out + b
 
 
+def conv3d_at(x, w, b, pos):
+    """conv3d at listed output voxels only: out[i, o] = b[o] + sum over taps
+    and c of x[n, z+kz-p, y+ky-p, x+kx-p, c] w[o,kz,ky,kx,c] for pos[i] =
+    (n, z, y, x), x = 0 outside the grid; also the sum of the absolute
+    values of the terms (for rounding bounds).  Direct summation per voxel,
+    for grids too large to convolve whole."""
+    pos = np.asarray(pos)
+    n, d, h, wd, _ = x.shape
+    k = w.shape[1]
+    p = k // 2
+    out = np.tile(np.asarray(b, dtype=np.float64), (len(pos), 1))
+    mag = np.tile(np.abs(np.asarray(b, dtype=np.float64)), (len(pos), 1))
+    for kz in range(k):
+        for ky in range(k):
+            for kx in range(k):
+                zz = pos[:, 1] + kz - p
+                yy = pos[:, 2] + ky - p
+                xx = pos[:, 3] + kx - p
+                ok = (zz >= 0) & (zz < d) & (yy >= 0) & (yy < h) & (xx >= 0) & (xx < wd)
+                v = np.zeros((len(pos), x.shape[-1]))
+                v[ok] = x[pos[ok, 0], zz[ok], yy[ok], xx[ok], :]
+                wt = w[:, kz, ky, kx, :]
+                out += v @ wt.T
+                mag += np.abs(v) @ np.abs(wt).T
+    return out, mag
+
+
 def conv3d_backward(x, w, dout):
     """Gradients of sum(dout * conv3d(x, w, b)) with respect to x, w, b."""
     n, d, h, wd, _ = x.shape
@@ -190,20 +217,25 @@ def mse(out, target):
     return float(np.mean((out - target) ** 2))
 
 
-def backward(theta, a, dout):
+def backward(theta, a, dout, keep=None):
     """Gradient of sum(dout * forward(theta, x)) with respect to theta (flat,
-    same layout), by the chain rule through every layer."""
+    same layout), by the chain rule through every layer.  keep (a dict), when
+    given, receives each layer's (input, gradient of its pre-activation)."""
     P = unflatten(theta)
     grads = {}
 
     def conv_back(name, inp, out_act, dy):
         w, _ = P[name]
         dpre = dy * (out_act > 0)  # relu
+        if keep is not None:
+            keep[name] = (inp, dpre)
         dx, dw, db = conv3d_backward(inp, w, dpre)
         grads[name] = (dw, db)
         return dx
 
     w, _ = P["head"]
+    if keep is not None:
+        keep["head"] = (a["dec1b"], dout)
     dx, dw, db = conv3d_backward(a["dec1b"], w, dout)
     grads["head"] = (dw, db)
     d = conv_back("dec1b", a["dec1a"], a["dec1b"], dx)

@@ -21,7 +21,7 @@ _LIBS = {}
 class _Params(ctypes.Structure):
     _fields_ = [
         ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
-        ("qt", ctypes.c_int32), ("periodic", ctypes.c_int32), ("pad_", ctypes.c_int32),
+        ("qt", ctypes.c_int32), ("periodic", ctypes.c_int32), ("specular", ctypes.c_int32),
         ("omega_nu", ctypes.c_double), ("omega_bulk", ctypes.c_double),
         ("omega_hi", ctypes.c_double),
         ("omega_T", ctypes.c_double), ("omega_hiT", ctypes.c_double),
@@ -52,6 +52,7 @@ class Params:
     periodic: int = 0  # bit 0/1/2: periodic in x/y/z instead of walls
     fourth_maxwell: int = 0  # 4th-order flow equilibrium: 0 kxx~kyy~/rho, 1 rho/9
     R: float = 0.0  # uniform scalar source per cell and step
+    specular: int = 0  # scalar on the adiabatic faces: 0 bounce-back, 1 specular reflection
     alpha: float = float("nan")  # thermal diffusivity, for the Nusselt number
     nu: float = float("nan")
 
@@ -60,7 +61,7 @@ class Params:
         return self.nx * self.ny * self.nz
 
     def c_struct(self) -> _Params:
-        return _Params(self.nx, self.ny, self.nz, self.qt, self.periodic, 0,
+        return _Params(self.nx, self.ny, self.nz, self.qt, self.periodic, self.specular,
                        self.omega_nu, self.omega_bulk, self.omega_hi, self.omega_T,
                        self.omega_hiT, self.cs2T, self.gbeta, self.T_hot, self.T_cold,
                        self.T_ref, self.fourth_maxwell, 0, self.R)
@@ -68,7 +69,7 @@ class Params:
 
 def cavity_params(n, Ra, Pr=0.71, u0=0.05, qt=7, cs2T=1.0 / 3.0, ny=None, nz=None,
                   T_hot=0.5, T_cold=-0.5, omega_hi=1.0, omega_hiT=1.0, omega_bulk=0.0,
-                  fourth_maxwell=0, R=0.0) -> Params:
+                  fourth_maxwell=0, R=0.0, specular=0) -> Params:
     """Map (Ra, Pr, u0, L = n) to lattice parameters.
 
     Reading (the paper gives Ra = g beta dT L^3 / (alpha nu) and Pr = nu/alpha,
@@ -88,7 +89,7 @@ def cavity_params(n, Ra, Pr=0.71, u0=0.05, qt=7, cs2T=1.0 / 3.0, ny=None, nz=Non
                   fourth_maxwell=fourth_maxwell,
                   omega_T=1.0 / (alpha / cs2T + 0.5), omega_hiT=omega_hiT,
                   cs2T=cs2T, gbeta=gbeta, T_hot=T_hot, T_cold=T_cold,
-                  T_ref=0.5 * (T_hot + T_cold), R=R, alpha=alpha, nu=nu)
+                  T_ref=0.5 * (T_hot + T_cold), R=R, alpha=alpha, nu=nu, specular=specular)
 
 
 def _lib(long_double=False):

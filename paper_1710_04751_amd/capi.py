@@ -24,6 +24,7 @@ class lbm_params(ctypes.Structure):
         ("omega_hi_T", ctypes.c_double), ("R", ctypes.c_double),
         ("lattice_units", ctypes.c_int32), ("block_x", ctypes.c_int32),
         ("block_y", ctypes.c_int32), ("round_stochastic", ctypes.c_int32),
+        ("scalar_specular", ctypes.c_int32),
         ("nu", ctypes.c_double), ("alpha", ctypes.c_double), ("gbeta", ctypes.c_double),
     ]
 
@@ -44,6 +45,7 @@ class lbm_peaks(ctypes.Structure):
 
 
 LBM_STEADY_TOL, LBM_STEADY_PLATEAU, LBM_STEADY_MAX_STEPS, LBM_STEADY_UNSTABLE = 0, 1, 2, 3
+LBM_STEADY_STALLED = 4
 
 
 class lbm_nn_config(ctypes.Structure):
@@ -83,7 +85,7 @@ _SIGS = {
     "lbm_centerlines": (ctypes.c_int, [H, vp, vp, ctypes.POINTER(lbm_peaks)]),
     "lbm_symmetrize": (ctypes.c_int, [H, vp, vp, vp, vp]),
     "lbm_run_to_steady": (ctypes.c_int, [H, ctypes.c_double, ctypes.c_int64, ctypes.c_int64,
-                                         ctypes.c_int32, ctypes.c_double,
+                                         ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
                                          ctypes.POINTER(ctypes.c_int64),
                                          ctypes.POINTER(ctypes.c_int32),
                                          ctypes.POINTER(ctypes.c_double)]),
@@ -109,7 +111,7 @@ _SIGS = {
     "lbm_batch_set_active": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_int32)]),
     "lbm_batch_run_to_steady": (ctypes.c_int, [vp, ctypes.c_double, ctypes.c_int64,
                                                ctypes.c_int64, ctypes.c_int32, ctypes.c_double,
-                                               ctypes.POINTER(ctypes.c_int64),
+                                               ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
                                                ctypes.POINTER(ctypes.c_int32),
                                                ctypes.POINTER(ctypes.c_double)]),
     "lbm_batch_set_launch": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
@@ -261,12 +263,14 @@ def lbm_symmetrize(h, ux=None, uy=None, uz=None, T=None):
     return check(lib().lbm_symmetrize(h, ux, uy, uz, T))
 
 
-def lbm_run_to_steady(h, tol, check_every, max_steps, plateau_checks=0, plateau_floor=0.0):
+def lbm_run_to_steady(h, tol, check_every, max_steps, plateau_checks=0, plateau_floor=0.0,
+                      stall_checks=0):
     """Returns (steps, how, last residual); how is an LBM_STEADY_* value.  An
     unstable run raises LbmError(LBM_ERR_UNSTABLE)."""
     steps, how, res = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_double()
     check(lib().lbm_run_to_steady(h, float(tol), int(check_every), int(max_steps),
-                                  int(plateau_checks), float(plateau_floor), ctypes.byref(steps),
+                                  int(plateau_checks), float(plateau_floor), int(stall_checks),
+                                  ctypes.byref(steps),
                                   ctypes.byref(how),
                                   ctypes.byref(res)))
     return steps.value, how.value, res.value
@@ -358,13 +362,14 @@ def lbm_batch_set_active(b, active):
 
 
 def lbm_batch_run_to_steady(b, n, tol, check_every, max_steps, plateau_checks=0,
-                            plateau_floor=0.0):
+                            plateau_floor=0.0, stall_checks=0):
     """Returns (steps, how, last residual) per member; how is an LBM_STEADY_* value."""
     steps = (ctypes.c_int64 * n)()
     st = (ctypes.c_int32 * n)()
     res = (ctypes.c_double * n)()
     check(lib().lbm_batch_run_to_steady(b, float(tol), int(check_every), int(max_steps),
-                                        int(plateau_checks), float(plateau_floor), steps, st,
+                                        int(plateau_checks), float(plateau_floor),
+                                        int(stall_checks), steps, st,
                                         res))
     return list(steps), list(st), list(res)
 

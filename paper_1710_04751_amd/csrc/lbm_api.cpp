@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "lbm_handle.hpp"
+#include "lbm_index.hpp"
 
 using namespace lbm;
 
@@ -94,6 +95,10 @@ bool validate(const lbm_params* p, lbm_lattice* L, std::string* why) {
         *why = "round_stochastic is 0, or 1 with FP16 storage";
         return false;
     }
+    if (p->scalar_specular != 0 && p->scalar_specular != 1) {
+        *why = "scalar_specular is 0 or 1";
+        return false;
+    }
     if (!std::isfinite(p->R)) {
         *why = "the scalar source R must be finite";
         return false;
@@ -136,11 +141,7 @@ bool validate(const lbm_params* p, lbm_lattice* L, std::string* why) {
 }
 
 int run_rows_log2(const lbm_params* p) {
-    const int64_t row_bytes = (int64_t)p->nx * value_bytes((Prec)p->precision);
-    const int64_t nrows = (int64_t)p->ny * p->nz;
-    int gs = 0;
-    while ((row_bytes << (gs + 1)) <= 32768 && ((int64_t)2 << gs) <= nrows) ++gs;
-    return gs;
+    return idx::rows_log2(p->nx, p->ny, p->nz, value_bytes((Prec)p->precision));
 }
 
 Layout layout_of(const lbm_params* p) {
@@ -225,6 +226,7 @@ lbm_status make_handle(const lbm_params* p, void* workspace, size_t bytes, void*
     h->c.fourth_maxwell = p->fourth_maxwell;
     h->c.sr = p->round_stochastic;
     h->c.seed = 0;
+    h->c.spec = p->scalar_specular;
     int bx = p->block_x, by = p->block_y;
     if (!bx || !by) default_block(p->nx, &bx, &by);
     set_geom(h, bx, by);
@@ -491,12 +493,13 @@ lbm_status lbm_symmetrize(lbm_handle* h, float* ux, float* uy, float* uz, float*
 }
 
 lbm_status lbm_run_to_steady(lbm_handle* h, double tol, int64_t check_every, int64_t max_steps,
-                             int32_t plateau_checks, double plateau_floor, int64_t* steps,
-                             int32_t* how, double* last_residual) {
+                             int32_t plateau_checks, double plateau_floor, int32_t stall_checks,
+                             int64_t* steps, int32_t* how, double* last_residual) {
     if (!h) return fail(LBM_ERR_ARG, "null handle");
     if (h->owner) return fail(LBM_ERR_STATE, "batch members are run by lbm_batch_run_to_steady");
-    if (check_every <= 0 || (check_every & 1) || max_steps < 0 || plateau_checks < 0)
-        return fail(LBM_ERR_ARG, "check_every must be positive and even");
+    if (check_every <= 0 || (check_every & 1) || max_steps < 0 || plateau_checks < 0 ||
+        stall_checks < 0)
+        return fail(LBM_ERR_ARG, "check_every must be positive and even, the check counts >= 0");
     double res = INFINITY;
     lbm_status s = lbm_residual(h, &res);  // snapshot
     SteadyTracker tr;
@@ -508,7 +511,7 @@ lbm_status lbm_run_to_steady(lbm_handle* h, double tol, int64_t check_every, int
         done += check_every;
         s = lbm_residual(h, &res);
         if (s != LBM_OK) break;
-        const int r = tr.update(res, h->steps, tol, plateau_checks, plateau_floor);
+        const int r = tr.update(res, h->steps, tol, plateau_checks, plateau_floor, stall_checks);
         if (r >= 0) {
             result = r;
             break;

@@ -53,10 +53,15 @@ __device__ __forceinline__ void decode_tile(uint32_t d, int& cav, int& z, int& y
     yt = (int)(d & 0x3FFFu);
 }
 
+// keys[c] + key_off: member c's step index, the key of its stochastic
+// rounding (FP16 storage), so a member draws the random bits a single run of
+// it draws.  key_off is the step's position within a captured graph (the
+// device keys advance once per replay, k_batch_advance).
 template <typename R, typename S, int QT, bool HG>
 __global__ void __launch_bounds__(1024)
 k_batch_step(const DevCav* __restrict__ cavs, const uint32_t* __restrict__ tiles,
-             const uint32_t* __restrict__ ntiles_p, int parity) {
+             const uint32_t* __restrict__ ntiles_p, int parity,
+             const uint32_t* __restrict__ keys, uint32_t key_off) {
     const uint32_t ntiles = *ntiles_p;
     for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         int c, z, yt;
@@ -66,9 +71,18 @@ k_batch_step(const DevCav* __restrict__ cavs, const uint32_t* __restrict__ tiles
         const int x = (int)threadIdx.x - r * C.nx;
         const int y = yt * C.rows + r;
         if (r >= C.rows || y >= C.ny) continue;
+        uint32_t seed = 0;
+        if constexpr (std::is_same<S, _Float16>::value) seed = keys[c] + key_off;
         update_cell<R, S, QT, HG>((const S*)C.F[parity], (S*)C.F[1 - parity], x, y, z,
-                                  yt * C.rows, C.nx, C.ny, C.nz, C.pl.gs, coef_of<R>(C));
+                                  yt * C.rows, C.nx, C.ny, C.nz, C.pl.gs, coef_of<R>(C), seed);
     }
+}
+
+// Advance the step keys of the active members by k (one thread per member).
+__global__ void k_batch_advance(uint32_t* __restrict__ keys, const int32_t* __restrict__ active,
+                                int n, uint32_t k) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && active[i]) keys[i] += k;
 }
 
 // Residual of every active member: max |T - T_snapshot| (T = sum of the
@@ -157,7 +171,7 @@ constexpr size_t kAlignB = 256;
 size_t alignb(size_t v) { return (v + kAlignB - 1) / kAlignB * kAlignB; }
 
 struct BatchLayout {
-    size_t off_table, off_tiles, off_ntiles, off_flags, off_res, off_members, total;
+    size_t off_table, off_tiles, off_ntiles, off_flags, off_res, off_keys, off_members, total;
     std::vector<size_t> member_off, member_bytes;
     size_t max_tiles;
 };
@@ -182,8 +196,8 @@ bool batch_layout(const lbm_params* p, int n, BatchLayout* L, std::string* why) 
                    "(higher-order rates other than 1 or a scalar source)";
             return false;
         }
-        if (p[i].round_stochastic) {
-            *why = "stochastic rounding is not available in batches";
+        if (p[i].round_stochastic != p[0].round_stochastic) {
+            *why = "batch members must share the storage rounding mode";
             return false;
         }
         if (p[i].nx > 1024 || p[i].nz > 1023 || p[i].ny > 16383) {
@@ -198,7 +212,8 @@ bool batch_layout(const lbm_params* p, int n, BatchLayout* L, std::string* why) 
     L->off_ntiles = L->off_tiles + alignb(max_tiles * sizeof(uint32_t));
     L->off_flags = L->off_ntiles + kAlignB;                    // active[n], compare[n]
     L->off_res = L->off_flags + alignb(2 * n * sizeof(int32_t));  // max bits[n], bad[n]
-    L->off_members = L->off_res + alignb(2 * n * sizeof(unsigned long long));
+    L->off_keys = L->off_res + alignb(2 * n * sizeof(unsigned long long));  // step keys[n]
+    L->off_members = L->off_keys + alignb(n * sizeof(uint32_t));
     size_t off = L->off_members;
     for (int i = 0; i < n; ++i) {
         L->member_off[i] = off;
@@ -229,6 +244,9 @@ struct lbm_batch {
     hipGraphExec_t graph;
     bool graph_ok;
     std::vector<DevCav> table;
+    bool sr;                          // stochastic rounding: step keys live on the device
+    std::vector<uint32_t> keys_host;  // what d_keys() holds (valid once keys_ok)
+    bool keys_ok;
 
     DevCav* d_table() const { return (DevCav*)(ws + lay.off_table); }
     uint32_t* d_tiles() const { return (uint32_t*)(ws + lay.off_tiles); }
@@ -237,6 +255,7 @@ struct lbm_batch {
     int32_t* d_compare() const { return d_active() + n; }
     unsigned long long* d_maxbits() const { return (unsigned long long*)(ws + lay.off_res); }
     unsigned int* d_bad() const { return (unsigned int*)(d_maxbits() + n); }
+    uint32_t* d_keys() const { return (uint32_t*)(ws + lay.off_keys); }
 };
 
 namespace lbm {
@@ -257,8 +276,9 @@ void fill_kcoef(const lbm_handle* h, KCoef<R>* k) {
     k->t.omega_hiT = (R)h->c.omega_hiT;
     k->t.cs2 = (R)h->c.cs2;
     k->t.src = (R)h->c.src;
-    k->sr = 0;  // batches refuse stochastic rounding
-    k->seed = 0;
+    k->sr = h->c.sr;
+    k->seed = 0;  // the step keys are device data (k_batch_step)
+    k->spec = h->c.spec;
     k->T_hot = (R)h->c.T_hot;
     k->T_cold = (R)h->c.T_cold;
     const double cs2 = h->c.cs2;
@@ -339,13 +359,36 @@ unsigned batch_grid(const lbm_batch* b) {
     return (unsigned)(b->bpc > 0 ? (int64_t)b->cu_count * b->bpc : std::max<int64_t>(1, b->tiles_all));
 }
 
-hipError_t launch_one_step(lbm_batch* b, int parity) {
+hipError_t launch_one_step(lbm_batch* b, int parity, uint32_t key_off) {
     const dim3 grid(batch_grid(b)), block((unsigned)b->threads);
     LBM_BATCH_DISPATCH(b->prec, b->qt, b->general, {
         hipLaunchKernelGGL((k_batch_step<R, S, Q, G>), grid, block, 0, b->stream, b->d_table(),
-                           b->d_tiles(), b->d_ntiles(), parity);
+                           b->d_tiles(), b->d_ntiles(), parity, (const uint32_t*)b->d_keys(),
+                           key_off);
     });
     return hipGetLastError();
+}
+
+hipError_t launch_advance(lbm_batch* b, uint32_t k) {
+    hipLaunchKernelGGL(k_batch_advance, dim3((b->n + 255) / 256), dim3(256), 0, b->stream,
+                       b->d_keys(), (const int32_t*)b->d_active(), b->n, k);
+    return hipGetLastError();
+}
+
+// With stochastic rounding, make the device step keys equal the members'
+// step counts (members re-initialised since the last upload restart at 0).
+lbm_status sync_keys(lbm_batch* b) {
+    if (!b->sr) return LBM_OK;
+    bool same = b->keys_ok;
+    for (int i = 0; i < b->n && same; ++i) same = b->keys_host[i] == (uint32_t)b->mem[i]->steps;
+    if (same) return LBM_OK;
+    for (int i = 0; i < b->n; ++i) b->keys_host[i] = (uint32_t)b->mem[i]->steps;
+    hipError_t e = hipMemcpyAsync(b->d_keys(), b->keys_host.data(), sizeof(uint32_t) * b->n,
+                                  hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);  // pageable source
+    if (e != hipSuccess) return hip_fail(e, "batch step keys");
+    b->keys_ok = true;
+    return LBM_OK;
 }
 
 void drop_graph(lbm_batch* b) {
@@ -362,9 +405,10 @@ lbm_status capture_graph(lbm_batch* b) {
     hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(e, "graph capture begin");
     for (int i = 0; i < b->graph_steps; ++i) {
-        e = launch_one_step(b, i & 1);
+        e = launch_one_step(b, i & 1, (uint32_t)i);
         if (e != hipSuccess) break;
     }
+    if (e == hipSuccess && b->sr) e = launch_advance(b, (uint32_t)b->graph_steps);
     hipError_t e2 = hipStreamEndCapture(b->stream, &g);
     if (e != hipSuccess) return hip_fail(e, "graph capture launch");
     if (e2 != hipSuccess) return hip_fail(e2, "graph capture end");
@@ -381,6 +425,7 @@ void after_steps(lbm_batch* b, int64_t k) {
         if (b->active[i]) {
             b->mem[i]->steps += k;
             b->mem[i]->cur = (int)(b->gsteps & 1);
+            if (b->sr) b->keys_host[i] += (uint32_t)k;  // as k_batch_advance did on the device
         }
 }
 
@@ -439,6 +484,9 @@ lbm_status lbm_batch_create(const lbm_params* p, int32_t n, void* workspace, siz
     b->graph_steps = stream ? 100 : 0;  // the legacy default stream cannot be captured
     b->cu_count = cus;
     b->graph_ok = false;
+    b->sr = p[0].round_stochastic != 0;
+    b->keys_host.assign(n, 0);
+    b->keys_ok = false;
     b->active.assign(n, 1);
     b->last_res.assign(n, INFINITY);
     b->last_status.assign(n, LBM_OK);
@@ -484,6 +532,8 @@ lbm_status lbm_batch_step(lbm_batch* b, int64_t nsteps) {
         if (b->active[i] && b->mem[i]->cur != (int)(b->gsteps & 1))
             return fail(LBM_ERR_STATE, "member " + std::to_string(i) +
                                            " was re-initialised out of step with its batch");
+    lbm_status ks = sync_keys(b);
+    if (ks != LBM_OK) return ks;
     while (nsteps > 0) {
         if (b->graph_ok && (b->gsteps & 1) == 0 && nsteps >= b->graph_steps) {
             hipError_t e = hipGraphLaunch(b->graph, b->stream);
@@ -491,7 +541,8 @@ lbm_status lbm_batch_step(lbm_batch* b, int64_t nsteps) {
             after_steps(b, b->graph_steps);
             nsteps -= b->graph_steps;
         } else {
-            hipError_t e = launch_one_step(b, (int)(b->gsteps & 1));
+            hipError_t e = launch_one_step(b, (int)(b->gsteps & 1), 0u);
+            if (e == hipSuccess && b->sr) e = launch_advance(b, 1u);
             if (e != hipSuccess) return hip_fail(e, "batch step");
             after_steps(b, 1);
             nsteps -= 1;
@@ -581,10 +632,11 @@ lbm_status lbm_batch_set_active(lbm_batch* b, const int32_t* active) {
 
 lbm_status lbm_batch_run_to_steady(lbm_batch* b, double tol, int64_t check_every,
                                    int64_t max_steps, int32_t plateau_checks,
-                                   double plateau_floor, int64_t* steps, int32_t* how,
-                                   double* last_residual) {
-    if (!b || check_every <= 0 || (check_every & 1) || max_steps < 0 || plateau_checks < 0)
-        return fail(LBM_ERR_ARG, "check_every must be positive and even");
+                                   double plateau_floor, int32_t stall_checks, int64_t* steps,
+                                   int32_t* how, double* last_residual) {
+    if (!b || check_every <= 0 || (check_every & 1) || max_steps < 0 || plateau_checks < 0 ||
+        stall_checks < 0)
+        return fail(LBM_ERR_ARG, "check_every must be positive and even, the check counts >= 0");
     std::vector<SteadyTracker> tr(b->n);
     std::vector<int32_t> end(b->n, LBM_STEADY_MAX_STEPS);
     std::vector<double> res(b->n);
@@ -609,7 +661,7 @@ lbm_status lbm_batch_run_to_steady(lbm_batch* b, double tol, int64_t check_every
             const int r = rs[i] != LBM_OK
                               ? (int)LBM_STEADY_UNSTABLE
                               : tr[i].update(res[i], b->mem[i]->steps, tol, plateau_checks,
-                                             plateau_floor);
+                                             plateau_floor, stall_checks);
             if (r >= 0) {
                 end[i] = r;
                 act[i] = 0;

@@ -76,7 +76,8 @@ struct SteadyTracker {
     int64_t best_step = -1;
     int32_t since = 0;  // checks since the last new minimum
     // Returns an lbm_steady value once the run should stop, else -1.
-    int update(double res, int64_t step, double tol, int32_t plateau_checks, double floor) {
+    int update(double res, int64_t step, double tol, int32_t plateau_checks, double floor,
+               int32_t stall_checks) {
         if (!std::isfinite(res)) return res != res ? LBM_STEADY_UNSTABLE : -1;
         if (res < tol) {
             best_step = step;
@@ -86,9 +87,13 @@ struct SteadyTracker {
             best = res;
             best_step = step;
             since = 0;
-        } else if (plateau_checks > 0 && ++since >= plateau_checks && best < floor) {
-            return LBM_STEADY_PLATEAU;
+            return -1;
         }
+        ++since;
+        if (plateau_checks > 0 && since >= plateau_checks && best < floor)
+            return LBM_STEADY_PLATEAU;
+        if (stall_checks > 0 && since >= stall_checks && !(best < floor))
+            return LBM_STEADY_STALLED;
         return -1;
     }
 };

@@ -26,6 +26,7 @@ struct Coefs {
     int32_t fourth_maxwell;
     int32_t sr;                          // FP16 storage: stochastic rounding
     uint32_t seed;                       // step index, the random stream's key
+    int32_t spec;                        // scalar adiabatic faces: specular reflection
 };
 
 // Layout of one stored state (A or B), row groups interleaved.  The x-rows

@@ -68,7 +68,7 @@ __global__ void __launch_bounds__(1024)
 k_step(const S* __restrict__ in, S* __restrict__ out, Geom g, KCoef<R> k) {
     const CellPos p = tile_cell(g);
     if (!p.ok) return;
-    update_cell<R, S, QT, HG>(in, out, p.x, p.y, p.z, p.y0, g.nx, g.ny, g.nz, g.gs, k);
+    update_cell<R, S, QT, HG>(in, out, p.x, p.y, p.z, p.y0, g.nx, g.ny, g.nz, g.gs, k, k.seed);
 }
 
 template <typename R, typename S, int QT, bool HG>

@@ -10,20 +10,21 @@
 #include <type_traits>
 
 #include "lbm_device.hpp"
+#include "lbm_index.hpp"
 #include "lbm_internal.hpp"
 
 namespace lbm {
 namespace kern {
 
 
-constexpr int EX15[15] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1};
-constexpr int EY15[15] = {0, 0, 0, 1, -1, 0, 0, 1, 1, -1, -1, 1, 1, -1, -1};
-constexpr int EZ15[15] = {0, 0, 0, 0, 0, 1, -1, 1, 1, 1, 1, -1, -1, -1, -1};
-constexpr int OPP15[15] = {0, 2, 1, 4, 3, 6, 5, 14, 13, 12, 11, 10, 9, 8, 7};
-constexpr int EX7[7] = {0, 1, -1, 0, 0, 0, 0};
-constexpr int EY7[7] = {0, 0, 0, 1, -1, 0, 0};
-constexpr int EZ7[7] = {0, 0, 0, 0, 0, 1, -1};
-constexpr int OPP7[7] = {0, 2, 1, 4, 3, 6, 5};
+using idx::EX15;
+using idx::EY15;
+using idx::EZ15;
+using idx::OPP15;
+using idx::EX7;
+using idx::EY7;
+using idx::EZ7;
+using idx::OPP7;
 
 // Rest-state flow weights (D3Q15, c_s^2 = 1/3).
 __device__ __forceinline__ double flow_weight(int a) {
@@ -82,7 +83,7 @@ __device__ __forceinline__ uint32_t mix32(uint32_t x) {
 
 // Position of population a of cell c = (z*ny + y)*nx + x in a state
 // (c < 2^31; the flow base for a < 15, the scalar base for scalar a).
-__device__ __forceinline__ int64_t pop_at(PopLay L, int a, int64_t c) {
+__host__ __device__ __forceinline__ int64_t pop_at(PopLay L, int a, int64_t c) {
     const uint32_t row = (uint32_t)c / (uint32_t)L.nx;
     const uint32_t x = (uint32_t)c - row * (uint32_t)L.nx;
     const uint32_t grp = row >> L.gs, sub = row & ((1u << L.gs) - 1u);
@@ -146,6 +147,7 @@ struct KCoef {
     R w_face, w_corner;  // rest weights of the scalar (anti-bounce-back)
     int32_t sr;          // FP16 storage: stochastic rounding
     uint32_t seed;       // step index
+    int32_t spec;        // scalar on the adiabatic faces: specular reflection
 };
 
 template <typename R>
@@ -163,6 +165,7 @@ KCoef<R> make_kcoef(const Coefs& c, int qt) {
     k.t.src = (R)c.src;
     k.sr = c.sr;
     k.seed = c.seed;
+    k.spec = c.spec;
     k.T_hot = (R)c.T_hot;
     k.T_cold = (R)c.T_cold;
     if (qt == 7) {
@@ -179,64 +182,48 @@ KCoef<R> make_kcoef(const Coefs& c, int qt) {
 // Fused stream-collide update of one cell (shared by the single-cavity and
 // the batched kernels, so both compute bit-identical results)
 // ---------------------------------------------------------------------------
+// seed: the step index keying stochastic rounding (FP16 storage with k.sr).
 template <typename R, typename S, int QT, bool HG>
 __device__ __forceinline__ void update_cell(const S* __restrict__ in, S* __restrict__ out, int x,
                                             int y, int z, int y0, int nxi, int nyi, int nzi,
-                                            int gs, const KCoef<R>& k) {
-    constexpr uint32_t RQ = 15 + QT;
-    const uint32_t nx = (uint32_t)nxi, ny = (uint32_t)nyi;
-    const uint32_t gmask = (1u << gs) - 1u;
-    const uint32_t run = nx << gs;    // values per population run (one group of rows)
-    const uint32_t glen = RQ * run;   // values per group
-    const bool xlo = x == 0, xhi = x == nxi - 1;
-    const bool ylo = y == 0, yhi = y == nyi - 1;
-    const bool zlo = z == 0, zhi = z == nzi - 1;
-    // Window: from the group of row (z-1, y0-1), the first row a cell of a
-    // tile starting at row (z, y0) can pull from (clamped at 0), to the end
-    // of the state.  y0 and z are uniform over the block, so the base is a
-    // scalar.
-    const uint32_t r0 = (uint32_t)z * ny + (uint32_t)y0;
-    const uint32_t g0 = (r0 > ny ? r0 - ny - 1 : 0u) >> gs;
-    const uint32_t ngroups = (ny * (uint32_t)nzi + gmask) >> gs;
-    const uint64_t wbytes = (uint64_t)(ngroups - g0) * glen * sizeof(S);
-    const uint32_t wb = wbytes > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)wbytes;
-    const __amdgpu_buffer_rsrc_t ri = pop_rsrc(in + (size_t)g0 * glen, wb);
-    const __amdgpu_buffer_rsrc_t ro = pop_rsrc(out + (size_t)g0 * glen, wb);
-    // offset of row r's first value in population run 0, from the window base
-    auto row_at = [&](uint32_t r) { return ((r >> gs) - g0) * glen + (r & gmask) * nx; };
-    const uint32_t r = (uint32_t)z * ny + (uint32_t)y;
-    const uint32_t own = row_at(r) + (uint32_t)x;
+                                            int gs, const KCoef<R>& k, uint32_t seed) {
+    constexpr int RQ = 15 + QT;
+    // The block's window starts at the group of row (z-1, y0-1) and runs to
+    // the end of the state; y0 and z are uniform over the block, so the base
+    // is a scalar.  Every offset below is relative to it (lbm_index.hpp).
+    const idx::Window w = idx::window_of(z, y0, nxi, nyi, nzi, gs, RQ, (int)sizeof(S));
+    const __amdgpu_buffer_rsrc_t ri = pop_rsrc(in + (size_t)w.g0 * w.glen, w.bytes);
+    const __amdgpu_buffer_rsrc_t ro = pop_rsrc(out + (size_t)w.g0 * w.glen, w.bytes);
+    const idx::CellAt c = idx::cell_at(w, x, y, z, nxi, nyi, nzi);
     R d[15];
 #pragma unroll
-    for (int a = 0; a < 15; ++a) {
-        const int ex = EX15[a], ey = EY15[a], ez = EZ15[a];
-        const bool o = (ex > 0 && xlo) || (ex < 0 && xhi) || (ey > 0 && ylo) || (ey < 0 && yhi) ||
-                       (ez > 0 && zlo) || (ez < 0 && zhi);
-        const uint32_t src = row_at(r - (uint32_t)(ey + ez * (int32_t)ny)) + (uint32_t)(x - ex);
-        // wall links take the opposite population of their own cell
-        d[a] = Buf<S>::template ld<R>(ri, o ? own + (uint32_t)OPP15[a] * run
-                                            : src + (uint32_t)a * run);
-    }
+    for (int a = 0; a < 15; ++a) d[a] = Buf<S>::template ld<R>(ri, idx::flow_load(w, c, a));
     R gq[QT];
+    // Scalar gather: anti-bounce-back across the Dirichlet walls (this rule
+    // wins on edges), bounce-back or -- with specular reflection, D3Q15
+    // only (on D3Q7 the two coincide) -- the mirrored population across the
+    // adiabatic faces.  The choice is uniform over the launch.
+    auto gather_scalar = [&](auto spec_tag) {
+        constexpr bool SPEC = decltype(spec_tag)::value;
 #pragma unroll
-    for (int a = 0; a < QT; ++a) {
-        const int ex = QT == 7 ? EX7[a] : EX15[a];
-        const int ey = QT == 7 ? EY7[a] : EY15[a];
-        const int ez = QT == 7 ? EZ7[a] : EZ15[a];
-        const int ob = QT == 7 ? OPP7[a] : OPP15[a];
-        const bool outx = (ex > 0 && xlo) || (ex < 0 && xhi);
-        const bool outyz = (ey > 0 && ylo) || (ey < 0 && yhi) || (ez > 0 && zlo) || (ez < 0 && zhi);
-        const uint32_t src = row_at(r - (uint32_t)(ey + ez * (int32_t)ny)) + (uint32_t)(x - ex);
-        const bool o = outx || outyz;
-        R v = Buf<S>::template ld<R>(ri, o ? own + (uint32_t)(15 + ob) * run
-                                           : src + (uint32_t)(15 + a) * run);
-        if (o && ex != 0 && outx) {
-            const R w = (ey == 0 && ez == 0) ? k.w_face : k.w_corner;
-            const R tw = ex > 0 ? k.T_hot : k.T_cold;  // source beyond x = -1/2 or nx - 1/2
-            v = R(2) * w * tw - v;
+        for (int a = 0; a < QT; ++a) {
+            const idx::ScalarLoad l = idx::scalar_load<QT, SPEC>(w, c, a);
+            R v = Buf<S>::template ld<R>(ri, l.off);
+            if (l.dirichlet) {
+                const int ex = QT == 7 ? EX7[a] : EX15[a];
+                const int ey = QT == 7 ? EY7[a] : EY15[a];
+                const int ez = QT == 7 ? EZ7[a] : EZ15[a];
+                const R wa = (ey == 0 && ez == 0) ? k.w_face : k.w_corner;
+                const R tw = ex > 0 ? k.T_hot : k.T_cold;  // source beyond x = -1/2 or nx - 1/2
+                v = R(2) * wa * tw - v;
+            }
+            gq[a] = v;
         }
-        gq[a] = v;
-    }
+    };
+    if (QT == 15 && k.spec)
+        gather_scalar(std::true_type{});
+    else
+        gather_scalar(std::false_type{});
 
     R T = 0;
 #pragma unroll
@@ -255,8 +242,8 @@ __device__ __forceinline__ void update_cell(const S* __restrict__ in, S* __restr
             // The cell's random stream: a hash of (step, cell) seeds a
             // xorshift32 generator (shifts 13, 17, 5; state never 0); each
             // 32-bit word gives the 16 random bits of two stores.
-            const uint32_t cell = ((uint32_t)z * ny + (uint32_t)y) * nx + (uint32_t)x;
-            uint32_t xs = mix32(k.seed * 0x9e3779b9u ^ cell);
+            const uint32_t cell = ((uint32_t)z * w.ny + (uint32_t)y) * w.nx + (uint32_t)x;
+            uint32_t xs = mix32(seed * 0x9e3779b9u ^ cell);
             xs = xs ? xs : 0x9e3779b9u;
             uint32_t rnd[(15 + QT + 1) / 2];
 #pragma unroll
@@ -269,19 +256,19 @@ __device__ __forceinline__ void update_cell(const S* __restrict__ in, S* __restr
             // value 2j takes the high half of word j, value 2j + 1 the low half
 #pragma unroll
             for (int a = 0; a < 15; ++a)
-                Buf<S>::st(ro, own + (uint32_t)a * run,
+                Buf<S>::st(ro, idx::store_at(w, c, a),
                            (float)half_stochastic(d[a], rnd[a >> 1] << (16 * (a & 1))));
 #pragma unroll
             for (int a = 0; a < QT; ++a)
-                Buf<S>::st(ro, own + (uint32_t)(15 + a) * run,
+                Buf<S>::st(ro, idx::store_at(w, c, 15 + a),
                            (float)half_stochastic(gq[a], rnd[(a + 15) >> 1] << (16 * ((a + 15) & 1))));
             return;
         }
     }
 #pragma unroll
-    for (int a = 0; a < 15; ++a) Buf<S>::st(ro, own + (uint32_t)a * run, d[a]);
+    for (int a = 0; a < 15; ++a) Buf<S>::st(ro, idx::store_at(w, c, a), d[a]);
 #pragma unroll
-    for (int a = 0; a < QT; ++a) Buf<S>::st(ro, own + (uint32_t)(15 + a) * run, gq[a]);
+    for (int a = 0; a < QT; ++a) Buf<S>::st(ro, idx::store_at(w, c, 15 + a), gq[a]);
 }
 
 }  // namespace kern

@@ -90,8 +90,10 @@ class WarmStartNet:
 
     def _targets(self, targets):
         g = self.grid
+        on_device = targets.is_cuda and (self.device.index is None or
+                                         targets.device.index == self.device.index)
         if (targets.dtype != torch.float32 or not targets.is_contiguous() or targets.dim() != 5
-                or tuple(targets.shape[1:]) != (4, g, g, g) or targets.device != self.device):
+                or tuple(targets.shape[1:]) != (4, g, g, g) or not on_device):
             raise ValueError(f"targets must be a contiguous float32 device tensor [N][4][{g}]"
                              f"[{g}][{g}]")
         return targets.data_ptr(), targets.shape[0], 4 * g ** 3

@@ -115,10 +115,10 @@ class Cavity:
         return pk, ul, wl
 
     def run_to_steady(self, tol=1e-8, check_every=1000, max_steps=10 ** 7, plateau_checks=0,
-                      plateau_floor=0.0):
+                      plateau_floor=0.0, stall_checks=0):
         """(steps, how, last residual) of lbm_run_to_steady."""
         return capi.lbm_run_to_steady(self.h, tol, check_every, max_steps, plateau_checks,
-                                      plateau_floor)
+                                      plateau_floor, stall_checks)
 
     def populations(self):
         F = self._empty(15)
@@ -233,9 +233,9 @@ class Batch:
         capi.lbm_batch_set_active(self.b, active)
 
     def run_to_steady(self, tol, check_every=1000, max_steps=10 ** 6, plateau_checks=0,
-                      plateau_floor=0.0):
+                      plateau_floor=0.0, stall_checks=0):
         return capi.lbm_batch_run_to_steady(self.b, self.n, tol, check_every, max_steps,
-                                            plateau_checks, plateau_floor)
+                                            plateau_checks, plateau_floor, stall_checks)
 
     def set_launch(self, threads, blocks_per_cu, graph_steps):
         capi.lbm_batch_set_launch(self.b, threads, blocks_per_cu, graph_steps)

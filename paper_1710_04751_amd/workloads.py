@@ -80,8 +80,13 @@ STABLE_RATES = {"omega_bulk": 1.0, "fourth_maxwell": 1, "cs2_T": 0.25}
 
 # Steady-state rule: max |T_n - T_(n-1000)| < 1e-8, or, when the residual
 # has stalled for 10 checks below 1e-6 (16 units in the last place of
-# T = 0.5 in FP32), the precision's floor.
-STEADY_RULE = {"tol": 1e-8, "check_every": 1000, "plateau_checks": 10, "plateau_floor": 1e-6}
+# T = 0.5 in FP32), the precision's floor.  A residual that has reached no
+# new minimum for 30 checks while staying above 1e-6 ends the run as
+# "stalled": the state came near a steady state and left it (measured on
+# 64^3 and 128^3 cavities: runs that converge reach a new minimum at least
+# every 15 checks).
+STEADY_RULE = {"tol": 1e-8, "check_every": 1000, "plateau_checks": 10, "plateau_floor": 1e-6,
+               "stall_checks": 30}
 
 
 def batched_cavities(count=64, seed=1710, sizes=(32, 48, 64, 80, 96), log_ra=(3.0, 6.0)):

@@ -55,7 +55,7 @@ def test_params_defaults_and_lattice_mapping(capi):
     ("nx", 3, ">= 4"), ("thermal_q", 9, "7 or 15"), ("R", float("inf"), "source"),
     ("u0", 0.2, "0.3"), ("omega_hi", 2.0, "(0, 2)"), ("precision", 7, "precision"),
     ("block_x", 48, "multiple of 64"), ("Pr", -1.0, "positive"),
-    ("round_stochastic", 1, "round_stochastic"),
+    ("round_stochastic", 1, "round_stochastic"), ("scalar_specular", 2, "scalar_specular"),
 ])
 def test_invalid_parameters_are_rejected(capi, field, value, msg):
     p = capi.lbm_params_init(16, 1e3)
@@ -129,3 +129,21 @@ def test_network_parameter_count_and_config_checks(capi):
             capi.lbm_nn_workspace_bytes(bad)
     with pytest.raises(capi.LbmError):
         capi.lbm_nn_create(c, 0x1000, 16)
+
+
+def test_batch_members_must_share_the_kernel_variant(capi):
+    """A batch is one kernel: members differing in precision, scalar lattice,
+    rounding mode or collision path are refused on the host."""
+    def member(**kw):
+        p = capi.lbm_params_init(16, 1e3)
+        for k, v in kw.items():
+            setattr(p, k, v)
+        return p
+    base = dict(precision=capi.LBM_FP32_S16, round_stochastic=1)
+    assert capi.lbm_batch_workspace_bytes([member(**base), member(**base)]) > 0
+    for other, msg in ((dict(precision=capi.LBM_FP32_S16), "rounding"),
+                       (dict(base, thermal_q=15), "thermal_q"),
+                       (dict(base, omega_hi=1.2), "collision path")):
+        arr = (capi.lbm_params * 2)(member(**base), member(**other))
+        assert capi.lib().lbm_batch_workspace_bytes(arr, 2) == 0
+        assert msg in capi.lbm_last_error()

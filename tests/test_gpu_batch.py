@@ -35,10 +35,15 @@ SIZES = [(32, 32, 32), (48, 40, 36), (20, 28, 16), (64, 16, 24), (96, 12, 10)]
 RAS = [1e4, 3e4, 2e3, 5e4, 1e5]
 
 
-@pytest.mark.parametrize("prec,qt", [("fp32", 7), ("fp64", 15), ("fp16", 7)])
-def test_batch_equals_single_runs(solver, prec, qt):
-    log(f"case: batch vs single {prec} q{qt}")
-    params = _members(solver, prec, qt, SIZES, RAS)
+@pytest.mark.parametrize("prec,qt,spec,sr", [("fp32", 7, 0, 0), ("fp64", 15, 0, 0),
+                                              ("fp16", 7, 0, 0), ("fp32", 15, 1, 0),
+                                              ("fp16", 7, 0, 1), ("fp16", 15, 1, 1)])
+def test_batch_equals_single_runs(solver, prec, qt, spec, sr):
+    """130 steps: one graph replay of 100 steps and 30 single launches; with
+    stochastic rounding each member draws the random bits of its own single
+    run (the step keys advance on the device across replays)."""
+    log(f"case: batch vs single {prec} q{qt} specular {spec} stochastic rounding {sr}")
+    params = _members(solver, prec, qt, SIZES, RAS, scalar_specular=spec, round_stochastic=sr)
     batch = solver.Batch(params)
     batch.step(130)  # graph replay (100) + single launches
     info = batch.launch_info()
@@ -68,6 +73,31 @@ def test_retired_member_freezes_and_rejoins(solver):
         cav = solver.Cavity(p)
         cav.step(expect[i])
         assert torch.equal(cav.populations()[0], batch.members[i].populations()[0]), i
+        cav.close()
+    batch.close()
+
+
+def test_stochastic_rounding_keys_follow_each_member(solver):
+    """FP16 storage with stochastic rounding: a member that sat out steps and
+    one re-initialised mid-run keep drawing the random bits of their own
+    single runs (keys = each member's step count), through graph replays."""
+    log("case: batch stochastic rounding with retirement and restart")
+    params = _members(solver, "fp16", 7, SIZES[:3], RAS[:3], round_stochastic=1)
+    batch = solver.Batch(params)
+    batch.step(40)
+    batch.set_active([1, 0, 1])
+    batch.step(60)
+    batch.members[2].init_rest()  # batch step 100 (even): restarts at step 0
+    batch.set_active([1, 1, 1])
+    batch.step(120)  # one graph replay and 20 single launches
+    expect = [220, 160, 120]
+    for i, p in enumerate(params):
+        assert batch.members[i].steps_done() == expect[i]
+        cav = solver.Cavity(p)
+        cav.step(expect[i])
+        Fs, Gs = cav.populations()
+        Fb, Gb = batch.members[i].populations()
+        assert torch.equal(Fs, Fb) and torch.equal(Gs, Gb), i
         cav.close()
     batch.close()
 

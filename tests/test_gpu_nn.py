@@ -100,6 +100,60 @@ def test_each_layer_matches_oracle_on_gpu_inputs(net_mod, N, grid):
     net.close()
 
 
+def _sample_voxels(n, g, seed, extra=200):
+    """Voxels (sample, z, y, x) of an n x g^3 grid: for every sample the 27
+    points of {0, g/2, g-1}^3 (corners, edge and face centres, centre) and
+    `extra` seeded random ones."""
+    rng = np.random.default_rng(seed)
+    pts = []
+    for s in range(n):
+        for z in (0, g // 2, g - 1):
+            for y in (0, g // 2, g - 1):
+                for x in (0, g // 2, g - 1):
+                    pts.append((s, z, y, x))
+        pts += [(s, *rng.integers(0, g, 3)) for _ in range(extra)]
+    return np.array(pts, dtype=np.int64)
+
+
+def test_each_layer_at_the_production_shape(net_mod, N):
+    """Grid 64, batch 8 (the warm start's training shape): every launch
+    variant of the forward pass at its production size -- the brick kernel
+    with one output group on 64^3 (16 and 48 input channels), two groups on
+    32^3, the 16^3 brick grid, the four-tile kernel of the 4-channel input
+    layer and of the head, the split-k kernel on 8^3 -- checked per layer on
+    the GPU's own inputs at sampled voxels (every sample's corners, edge and
+    face centres and 200 random voxels), which the oracle sums directly.
+    Same per-element bar as the small grids: 2^-8 |ref| + 1e-4 sum|terms|."""
+    grid, n = 64, 8
+    log(f"case: nn per-layer forward, grid {grid}, batch {n}, sampled voxels")
+    theta = params(N, 19)
+    lra = list(np.linspace(3.1, 5.9, n))
+    net = net_mod.WarmStartNet(grid, n)
+    net.set_params(torch.from_numpy(theta.astype(np.float32)))
+    net.forward(lra)
+    acts = {}
+    for i, name in enumerate(net_mod.LAYER_NAMES):
+        acts[name] = to_np(net.activation(i, n)).astype(np.float64)
+    net.close()
+    x0 = to_bf16(N.inputs(lra, grid))
+    P = N.unflatten(theta)
+    for li, (name, ci, co, k, relu) in enumerate(N.LAYERS):
+        x = layer_input(N, name, acts, x0)
+        g = x.shape[1]
+        pos = _sample_voxels(n, g, 100 + li)
+        w, b = P[name]
+        ref, mag = N.conv3d_at(x, w, b, pos)
+        if relu:
+            ref = N.relu(ref)
+        got = acts[name][pos[:, 0], pos[:, 1], pos[:, 2], pos[:, 3], :]
+        err = np.abs(got - ref)
+        lim = 2.0 ** -8 * np.abs(ref) + 1e-4 * mag
+        worst = float(np.max(err - lim))
+        log(f"{name} ({g}^3, {len(pos)} voxels): max err {np.max(err):.2e} "
+            f"(max |ref| {np.max(np.abs(ref)):.2e})")
+        assert worst <= 0, (name, worst)
+
+
 def test_network_output_matches_oracle(net_mod, N):
     log("case: nn full forward, grid 16 and 8")
     theta = params(N, 12)
@@ -130,6 +184,30 @@ def gpu_cache(N, net_mod, net, n, x0):
     a["cat2"] = np.concatenate([acts["enc2b"], N.upsample2(acts["dec3b"])], axis=-1)
     a["cat1"] = np.concatenate([acts["enc1b"], N.upsample2(acts["dec2b"])], axis=-1)
     return a, acts["head"]
+
+
+def elementwise_excess(N, theta, a, dout, g, ref_g):
+    """Element-by-element check of a gradient computed on the GPU's own
+    activations.  The GPU stores every gradient tensor of the chain in BF16:
+    each of the at most 20 roundings on the way from the loss to a parameter
+    (16 layers, three pooling and three upsampling adjoints) changes a value
+    by at most 2^-9 of itself, and the linear backward maps carry that change
+    on by at most the absolute chain: the same backward pass run on |theta|,
+    |activations| and |dout| (same ReLU masks).  Per element, |g - ref| must
+    stay below 20 * 2^-9 of that absolute gradient (plus FP32 summation,
+    1e-4 of it).  Returns the largest (|g - ref| - bound) / bound per layer
+    (<= 0 passes) and the largest ratio |g - ref| / absolute gradient."""
+    a_abs = {k: np.abs(v) for k, v in a.items()}
+    A = N.backward(np.abs(theta), a_abs, np.abs(dout))
+    bound = (20 * 2.0 ** -9 + 1e-4) * A + 1e-30
+    out, o = {}, 0
+    for name, ci, co, k, _ in N.LAYERS:
+        m = co * k ** 3 * ci + co
+        d = np.abs(g[o:o + m] - ref_g[o:o + m])
+        out[name] = (float(np.max((d - bound[o:o + m]) / bound[o:o + m])),
+                     float(np.max(d / (A[o:o + m] + 1e-30))))
+        o += m
+    return out
 
 
 def per_layer_rel(N, g, ref_g):
@@ -166,15 +244,21 @@ def test_gradient_matches_oracle(net_mod, N):
     x0 = to_bf16(N.inputs(LRA, GRID))
     a, out = gpu_cache(N, net_mod, net, 2, x0)
     net.close()
-    same = per_layer_rel(N, g, N.backward(theta, a, 2.0 * (out - tg) / out.size))
+    dout = 2.0 * (out - tg) / out.size
+    ref_same = N.backward(theta, a, dout)
+    same = per_layer_rel(N, g, ref_same)
+    elem = elementwise_excess(N, theta, a, dout, g, ref_same)
     ref_loss, ref_g = N.loss_and_gradient(theta, x0, tg)
     pure = per_layer_rel(N, g, ref_g)
     log(f"loss {loss:.6e} ref {ref_loss:.6e}")
     for name in same:
-        log(f"{name}: same activations rel {same[name][0]:.2e}; pure oracle rel "
-            f"{pure[name][0]:.2e} cosine {pure[name][1]:.5f}")
+        log(f"{name}: same activations rel {same[name][0]:.2e}, element/abs-chain "
+            f"{elem[name][1]:.2e}; pure oracle rel {pure[name][0]:.2e} cosine "
+            f"{pure[name][1]:.5f}")
     assert abs(loss - ref_loss) < 2e-2 * ref_loss
     bad = {k: v[0] for k, v in same.items() if not v[0] < 2e-2}
+    assert not bad, bad
+    bad = {k: v[0] for k, v in elem.items() if not v[0] <= 0}
     assert not bad, bad
     bad = {k: v[1] for k, v in pure.items() if not v[1] > 0.99}
     assert not bad, bad
@@ -227,7 +311,10 @@ def test_gradient_on_the_full_grid(net_mod, N):
     channels), the coarse convolutions from the split-k kernel.  The oracle's
     backward pass runs on the GPU's own activations, so the remaining
     difference is the BF16 rounding of the gradient tensors: relative L2
-    error of each layer's gradient below 2e-2 (as on the 16^3 grid)."""
+    error of each layer's gradient below 2e-2 (as on the 16^3 grid), and
+    every element within its rounding bound (elementwise_excess).  The
+    forward pass at this shape is checked layer by layer in
+    test_each_layer_at_the_production_shape."""
     log("case: nn gradient, grid 64, batch 1")
     g = 64
     theta = params(N, 17)
@@ -243,8 +330,14 @@ def test_gradient_on_the_full_grid(net_mod, N):
     x0 = to_bf16(N.inputs(lra, g))
     a, out = gpu_cache(N, net_mod, net, 1, x0)
     net.close()
-    same = per_layer_rel(N, grad, N.backward(theta, a, 2.0 * (out - tg) / out.size))
+    dout = 2.0 * (out - tg) / out.size
+    ref_same = N.backward(theta, a, dout)
+    same = per_layer_rel(N, grad, ref_same)
+    elem = elementwise_excess(N, theta, a, dout, grad, ref_same)
     for name in same:
-        log(f"{name}: same activations rel {same[name][0]:.2e}")
+        log(f"{name}: same activations rel {same[name][0]:.2e}, element/abs-chain "
+            f"{elem[name][1]:.2e}")
     bad = {k: v[0] for k, v in same.items() if not v[0] < 2e-2}
+    assert not bad, bad
+    bad = {k: v[0] for k, v in elem.items() if not v[0] <= 0}
     assert not bad, bad

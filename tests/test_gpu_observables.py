@@ -131,7 +131,7 @@ def test_centerlines_match_oracle(solver, oracle, shape):
 
 
 def test_run_to_steady_rules(solver):
-    """Tolerance, plateau and step-limit endings of lbm_run_to_steady."""
+    """Tolerance, plateau, stall and step-limit endings of lbm_run_to_steady."""
     from paper_1710_04751_amd import capi
     log("case: run_to_steady single cavity")
     mk = lambda prec: solver.Cavity(solver.make_params(12, 1e3, u0=0.1, precision=prec))
@@ -158,6 +158,18 @@ def test_run_to_steady_rules(solver):
     if how == capi.LBM_STEADY_MAX_STEPS:
         assert steps == -1 and c4.steps_done() == 30000
     c4.close()
+    # the same floor with the stall rule: a residual that reaches no new
+    # minimum for 8 checks above the floor ends the run as stalled (and only
+    # once it wanders: the run first goes past the steps the FP32 plateau
+    # needed above)
+    c5 = mk("fp32")
+    steps, how, res = c5.run_to_steady(tol=1e-15, check_every=500, max_steps=400000,
+                                       plateau_checks=8, plateau_floor=1e-12, stall_checks=8)
+    log("fp32 stall:", steps, how, res, c5.steps_done())
+    assert how in (capi.LBM_STEADY_STALLED, capi.LBM_STEADY_TOL)
+    if how == capi.LBM_STEADY_STALLED:
+        assert steps == -1 and c5.steps_done() < 400000 and res > 1e-15
+    c5.close()
     # a step limit below the convergence time
     c3 = mk("fp64")
     steps, how, res = c3.run_to_steady(tol=1e-12, check_every=100, max_steps=1000)

@@ -97,7 +97,8 @@ def _lattice_params(solver, oracle_p, prec, qt, **extra):
                               cs2_T=oracle_p.cs2T,
                               omega_bulk=oracle_p.omega_bulk, omega_hi=oracle_p.omega_hi,
                               omega_hi_T=oracle_p.omega_hiT,
-                              fourth_maxwell=oracle_p.fourth_maxwell, **extra)
+                              fourth_maxwell=oracle_p.fourth_maxwell,
+                              scalar_specular=oracle_p.specular, **extra)
 
 
 VARIANTS = [
@@ -108,6 +109,9 @@ VARIANTS = [
     ("q7_general_rates", 7, {"omega_hi": 1.2, "omega_hiT": 0.7}),
     ("q15_bulk1_maxwell", 15, {"omega_bulk": 1.0, "fourth_maxwell": 1}),
     ("q7_cs2_quarter", 7, {"cs2T": 0.25}),
+    ("q15_specular", 15, {"specular": 1}),
+    ("q15_specular_general_rates", 15, {"specular": 1, "omega_hi": 0.9, "omega_hiT": 1.2}),
+    ("q7_specular", 7, {"specular": 1}),
 ]
 
 
@@ -215,20 +219,22 @@ def test_full_size_sampled_one_step(solver, oracle, n, prec):
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("shape,qt", [((4, 4, 4), 7), ((4, 5, 6), 15), ((5, 4, 4), 7),
-                                      ((6, 4, 5), 15)])
-def test_minimal_grids(solver, oracle, shape, qt):
+@pytest.mark.parametrize("shape,qt,spec", [((4, 4, 4), 7, 0), ((4, 5, 6), 15, 0),
+                                           ((5, 4, 4), 7, 0), ((6, 4, 5), 15, 0),
+                                           ((4, 6, 5), 15, 1), ((5, 4, 4), 15, 1)])
+def test_minimal_grids(solver, oracle, shape, qt, spec):
     """The smallest boxes the library accepts (4 cells on an axis): every
     cell is a wall cell on some axis; FP64 against the oracle over 300
-    steps."""
+    steps (bounce-back and specular adiabatic faces)."""
     nx, ny, nz = shape
-    log(f"case: minimal grid {shape} q{qt} fp64")
+    log(f"case: minimal grid {shape} q{qt} specular {spec} fp64")
     p = oracle.cavity_params(nx, 2e3, u0=0.1, qt=qt, ny=ny, nz=nz, omega_bulk=1.0,
-                             fourth_maxwell=1)
+                             fourth_maxwell=1, specular=spec)
     F, G = oracle.rest_state(p)
     F, G, mac = oracle.run(p, 300, F, G)
     cav = solver.Cavity(solver.make_params(nx=nx, ny=ny, nz=nz, Ra=2e3, u0=0.1, precision="fp64",
-                                           thermal_q=qt, omega_bulk=1.0, fourth_maxwell=1))
+                                           thermal_q=qt, omega_bulk=1.0, fourth_maxwell=1,
+                                           scalar_specular=spec))
     cav.step(300)
     Fg, Gg = (to_np(t) for t in cav.populations())
     assert np.max(np.abs(Fg - F)) < 1e-13 and np.max(np.abs(Gg - G)) < 1e-13

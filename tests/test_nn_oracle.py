@@ -49,6 +49,36 @@ def test_conv3d_equals_library_correlation():
     assert np.allclose(N.conv3d(x, w1, np.zeros(2)), x @ w1[:, 0, 0, 0, :].T, atol=1e-14)
 
 
+def test_conv3d_at_equals_brute_force_loops():
+    """The per-voxel form (for grids too large to convolve whole) against
+    the loops written out, at every voxel of a ragged grid, with its sum of
+    absolute terms; and the 1x1x1 case."""
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal((2, 3, 4, 5, 2))
+    w = rng.standard_normal((3, 3, 3, 3, 2))
+    b = rng.standard_normal(3)
+    pos = np.array([(n, z, y, xx) for n in range(2) for z in range(3) for y in range(4)
+                    for xx in range(5)])
+    out, mag = N.conv3d_at(x, w, b, pos)
+    for i, (n, z, y, xx) in enumerate(pos):
+        for o in range(3):
+            s, m = b[o], abs(b[o])
+            for kz in range(3):
+                for ky in range(3):
+                    for kx in range(3):
+                        zz, yy, x2 = z + kz - 1, y + ky - 1, xx + kx - 1
+                        if 0 <= zz < 3 and 0 <= yy < 4 and 0 <= x2 < 5:
+                            for c in range(2):
+                                t = x[n, zz, yy, x2, c] * w[o, kz, ky, kx, c]
+                                s += t
+                                m += abs(t)
+            assert abs(out[i, o] - s) < 1e-12 and abs(mag[i, o] - m) < 1e-12
+    w1 = rng.standard_normal((4, 1, 1, 1, 2))
+    out1, _ = N.conv3d_at(x, w1, np.zeros(4), pos)
+    assert np.allclose(out1, x[pos[:, 0], pos[:, 1], pos[:, 2], pos[:, 3]] @ w1[:, 0, 0, 0, :].T,
+                       atol=1e-14)
+
+
 def test_conv3d_backward_matches_finite_differences():
     rng = np.random.default_rng(3)
     x = rng.standard_normal((1, 4, 3, 5, 2))

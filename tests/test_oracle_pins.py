@@ -617,3 +617,89 @@ def test_step_cells_equals_one_step_of_run(oracle, qt, shape, rates):
     assert np.array_equal(fo, F1[:, zs, ys, xs].T)
     assert np.array_equal(go, G1[:, zs, ys, xs].T)
     assert np.array_equal(mac, mac1[:, zs, ys, xs].T)
+
+
+# --------------------------------------------------------------------------
+# Specular reflection of the scalar on the adiabatic faces (an option next
+# to the bounce-back reading of the zero-gradient condition of Sec. 3)
+# --------------------------------------------------------------------------
+
+def test_pure_conduction_is_exact_on_d3q15_with_specular_faces(oracle):
+    """With the adiabatic faces reflecting the scalar specularly, every link
+    keeps its flux along the heated axis, so the linear conduction profile
+    between the Dirichlet walls is the exact steady state on D3Q15 as well
+    (bounce-back reverses the diagonal links' flux there and only reaches it
+    as the grid is refined): T linear to round-off, Nu = 1 on every cell of
+    both walls."""
+    p = oracle.cavity_params(8, 1e3, qt=15, ny=7, nz=6, specular=1)
+    p.gbeta = 0.0
+    p.omega_nu = 1.5
+    p.omega_T = 1.0
+    p.alpha = (1 / 3) * (1 / p.omega_T - 0.5)
+    F, G = oracle.rest_state(p)
+    F, G, mac = oracle.run(p, 1500, F, G)
+    assert np.max(np.abs(mac[4] - _linear_T(p))) < 1e-12
+    assert np.max(np.abs(mac[1:4])) < 1e-15
+    nh, nc = oracle.nusselt(p, G)
+    assert np.max(np.abs(nh - 1)) < 1e-10 and np.max(np.abs(nc - 1)) < 1e-10
+    # the same run with bounce-back faces misses it (the reading it replaces)
+    p.specular = 0
+    F, G = oracle.rest_state(p)
+    F, G, _ = oracle.run(p, 1500, F, G)
+    nh, _ = oracle.nusselt(p, G)
+    assert np.max(np.abs(nh - 1)) > 1e-2
+
+
+def test_specular_faces_equal_a_mirrored_periodic_box(oracle):
+    """With the fluid at rest (no buoyancy), a box whose y and z faces reflect
+    the scalar specularly evolves exactly like the lower half of a periodic
+    box of twice the size along y and z filled with the mirrored state (the
+    image cell of y is 2 ny - 1 - y, its populations have e_y reversed;
+    likewise along z): the periodic box carries no reflection code, so this
+    checks the reflection rule on every face, edge and corner link.  On
+    D3Q7 specular reflection and bounce-back coincide."""
+    from paper_1710_04751_amd import workloads as W
+    E = {15: E15, 7: np.array([[0, 0, 0], [1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0],
+                               [0, 0, 1], [0, 0, -1]])}
+    for qt in (15, 7):
+        e = E[qt]
+        flip = lambda k: np.array([int(np.flatnonzero((e == e[a] * np.where(np.arange(3) == k, -1, 1))
+                                                      .all(axis=1))[0]) for a in range(qt)])
+        my, mz = flip(1), flip(2)
+        nx, ny, nz = 6, 5, 4
+        p = oracle.cavity_params(nx, 1e3, qt=qt, ny=ny, nz=nz, specular=1)
+        p.gbeta = 0.0
+        p.omega_T = 1.3
+        F, G = oracle.rest_state(p)
+        G = G + W.perturbation((nz, ny, nx), qt, 31 + qt, 5e-2)
+        big = oracle.cavity_params(nx, 1e3, qt=qt, ny=2 * ny, nz=2 * nz)
+        big.gbeta, big.omega_T, big.periodic = 0.0, 1.3, 6
+        Fb, Gb = oracle.rest_state(big)
+        Gb[:, :nz, :ny] = G
+        Gb[:, :nz, ny:] = G[my][:, :, ::-1]
+        Gb[:, nz:, :ny] = G[mz][:, ::-1, :]
+        Gb[:, nz:, ny:] = G[my][mz][:, ::-1, ::-1]
+        _, G1, _ = oracle.run(p, 25, F, G)
+        _, Gb1, _ = oracle.run(big, 25, Fb, Gb)
+        assert np.max(np.abs(G1 - Gb1[:, :nz, :ny])) < 1e-15
+        if qt == 7:
+            p.specular = 0
+            _, G2, _ = oracle.run(p, 25, F, G)
+            assert np.array_equal(G1, G2)
+
+
+def test_specular_faces_conserve_the_scalar(oracle):
+    """Periodic along the heated axis (no Dirichlet walls) and specular on
+    the four other faces, with buoyant flow: the scalar total is unchanged
+    by every step (streaming is a permutation of the populations)."""
+    from paper_1710_04751_amd import workloads as W
+    p = oracle.cavity_params(6, 5e3, u0=0.1, qt=15, ny=7, nz=5, specular=1)
+    p.periodic = 1
+    F, G = oracle.rest_state(p)
+    F = F + W.perturbation(F.shape[1:], 15, 41, 1e-3)
+    G = G + W.perturbation(G.shape[1:], 15, 42, 5e-2)
+    tot = [G.sum()]
+    for _ in range(5):
+        F, G, _ = oracle.run(p, 3, F, G)
+        tot.append(G.sum())
+    assert max(abs(t - tot[0]) for t in tot) < 1e-13
