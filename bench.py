@@ -41,7 +41,7 @@ def recorded_traffic(n, precision):
         return None
     rec = json.load(open(path))
     src = b"".join(open(os.path.join(ROOT, "paper_1710_04751_amd", "csrc", f), "rb").read()
-                   for f in ("lbm_device.hpp", "lbm_step.hpp", "lbm_step.hip"))
+                   for f in ("lbm_device.hpp", "lbm_index.hpp", "lbm_step.hpp", "lbm_step.hip"))
     if hashlib.sha256(src).hexdigest() != rec.get("source_sha256"):
         return None
     entry = rec.get(precision)

@@ -51,12 +51,15 @@ hipError_t conv_forward(const ConvGeom& g, const __bf16* x1, const __bf16* x2,
 hipError_t conv_backward_data(const ConvGeom& g, const __bf16* dy, const __bf16* wt,
                               const __bf16* dxmask, __bf16* dx, hipStream_t s);
 
-// Weight and bias gradients, accumulated (atomic adds) into the master
-// layout: dw[co][tap][ci] += sum_v dpre[v][co] x(v + tap)[ci], db[co] +=
-// sum_v dpre[v][co].
+// Weight and bias gradients, written into the master layout:
+// dw[co][tap][ci] = sum_v dpre[v][co] x(v + tap)[ci], db[co] = sum_v
+// dpre[v][co] (dpre = dy, masked by y > 0 when relu).  Blocks sum ranges of
+// voxels into scratch (wgrad_scratch_floats(g) floats, device), a second
+// kernel adds the ranges in a fixed order.
+int64_t wgrad_scratch_floats(const ConvGeom& g);
 hipError_t conv_backward_weight(const ConvGeom& g, const __bf16* x1, const __bf16* x2,
                                 const __bf16* dy, const __bf16* y, int relu, float* dw,
-                                float* db, hipStream_t s);
+                                float* db, float* scratch, hipStream_t s);
 
 // Average pooling of 2x2x2 blocks: x on grid 2^lg, y on 2^(lg-1), c channels.
 hipError_t pool_forward(int n, int lg, int c, const __bf16* x, __bf16* y, hipStream_t s);

@@ -11,8 +11,10 @@
 // 8 k values are one 16-byte load of a channels-last voxel.  The input
 // gradient is the same kernel run on the output gradient with the
 // transposed, tap-flipped weight.  The weight gradient takes rows = output
-// channels, columns = (tap, input channel) and k = voxels, summed over
-// chunks of voxels with FP32 atomic adds.
+// channels, columns = (tap, input channel) and k = voxels; each block sums
+// a range of voxels and writes its partial sums, and a second kernel adds
+// the partials of all ranges in a fixed order (no atomics, so gradients are
+// bit-reproducible).
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -179,11 +181,20 @@ struct WgradArgs {
     const __bf16* x2;
     const __bf16* dy;
     const __bf16* y;
-    float* dw;
-    float* db;
+    float* part;    // partial sums: weights of every block, then the bias partials
+    int64_t bias_off;  // floats from part to the bias partials
     int32_t n, lg, taps, c1, c1s, c2, cin, K, cout, coutp, ys, relu, cin_real;
     int64_t vchunk;
 };
+
+// B fragment of ones: an A fragment times it gives its row sums in every
+// column (the bias gradient's sum over voxels, on the matrix cores).
+__device__ __forceinline__ bf16x8 ones_frag() {
+    bf16x8 o;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) o[i] = (__bf16)1.f;
+    return o;
+}
 
 // Weight gradient, one block of 4 waves per (row tile, column tile, voxel
 // chunk): rows are RS * 16 output channels, columns CS * 16 (tap, channel)
@@ -192,7 +203,10 @@ struct WgradArgs {
 // with 16-byte loads (8 channels of one voxel) and writes them transposed
 // into LDS ([channel][voxel]), where each fragment (8 consecutive voxels) is
 // one 16-byte read.  Blocks of the first column tile also sum the output
-// gradient into the bias gradient.
+// gradient into the bias gradient (one more matrix-core product, against
+// ones).  Every block writes its partial sums to part (block b = (z * ct +
+// y) * kt + x: RS * 16 rows x CS * 16 columns; bias partials [z * ct + y][RS
+// * 16] at bias_off); k_wgrad_reduce adds them up.
 template <int RS>
 __global__ void __launch_bounds__(256) k_wgrad(WgradArgs a) {
     constexpr int CS = 8 / RS;
@@ -206,7 +220,8 @@ __global__ void __launch_bounds__(256) k_wgrad(WgradArgs a) {
     const int row0 = blockIdx.y * RS * 16, col0 = blockIdx.x * CS * 16;
     const int wr = wave % RS, wc = 2 * (wave / RS);
     floatx4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
-    float bsum = 0.f;
+    floatx4 accb = {0.f, 0.f, 0.f, 0.f};
+    const bool bias_wave = blockIdx.x == 0 && wave < RS;  // wc == 0
     const int64_t v0 = (int64_t)blockIdx.z * a.vchunk;
     const int64_t v1 = std::min(M, v0 + a.vchunk);
     for (int64_t vb = v0; vb < v1; vb += 32) {
@@ -267,33 +282,80 @@ __global__ void __launch_bounds__(256) k_wgrad(WgradArgs a) {
             for (int i = 0; i < 8; ++i) xT[g8 * 8 + i][vi] = xv[i];
         }
         __syncthreads();
-        if (blockIdx.x == 0 && tid < RS * 16) {
-#pragma unroll 8
-            for (int i = 0; i < 32; ++i) bsum += (float)dT[tid][i];
-        }
         const bf16x8 av = *(const bf16x8*)&dT[wr * 16 + r][q * 8];
         const bf16x8 b0 = *(const bf16x8*)&xT[wc * 16 + r][q * 8];
         const bf16x8 b1 = *(const bf16x8*)&xT[(wc + 1) * 16 + r][q * 8];
         acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b0, acc0, 0, 0, 0);
         acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b1, acc1, 0, 0, 0);
+        if (bias_wave) accb = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, ones_frag(), accb, 0, 0, 0);
         __syncthreads();
     }
-    if (blockIdx.x == 0 && tid < RS * 16 && row0 + tid < a.cout) atomicAdd(&a.db[row0 + tid], bsum);
+    const int64_t blk = ((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    float* pb = a.part + blk * (RS * 16) * (CS * 16);
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-        const int kcol = col0 + (wc + j) * 16 + r;
-        if (kcol >= a.K) continue;
-        const int t = kcol / a.cin;
-        const int cc = kcol - t * a.cin;
-        if (cc < a.c1s && cc >= a.c1) continue;  // zero padding channels of x1
-        const int ci = cc < a.c1s ? cc : a.c1 + (cc - a.c1s);
         const floatx4 acc = j ? acc1 : acc0;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int coo = row0 + wr * 16 + q * 4 + i;
-            if (coo < a.cout)
-                atomicAdd(&a.dw[((int64_t)coo * a.taps + t) * a.cin_real + ci], acc[i]);
-        }
+        for (int i = 0; i < 4; ++i)
+            pb[(wr * 16 + q * 4 + i) * (CS * 16) + (wc + j) * 16 + r] = acc[i];
+    }
+    if (bias_wave && r == 0) {
+        float* bb = a.part + a.bias_off + ((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * (RS * 16);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) bb[wr * 16 + q * 4 + i] = accb[i];
+    }
+}
+
+// First pass of the partial-sum reduction: out[j][w] = sum of in[g][w] over
+// the rows g of slice j (kRowSlice consecutive rows, fewer in the last), in
+// order; one thread per (slice, column), so the loads of many rows are in
+// flight at once.
+constexpr int kRowSlice = 16;
+__global__ void k_sum_row_slices(const float* __restrict__ in, int64_t rows, int64_t width,
+                                 float* __restrict__ out) {
+    const int64_t slices = (rows + kRowSlice - 1) / kRowSlice;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= slices * width) return;
+    const int64_t j = i / width, w = i - j * width;
+    const int64_t g0 = j * kRowSlice;
+    const int n = (int)(rows - g0 < kRowSlice ? rows - g0 : kRowSlice);
+    float v[kRowSlice];
+#pragma unroll
+    for (int k = 0; k < kRowSlice; ++k) v[k] = k < n ? in[(g0 + k) * width + w] : 0.f;
+    float sum = 0.f;
+#pragma unroll
+    for (int k = 0; k < kRowSlice; ++k) sum += v[k];
+    out[i] = sum;
+}
+
+// Sum of the k_wgrad partials over the voxel chunks, into the master layout
+// dw[co][tap][ci] (zero padding channels dropped) and db.  One thread per
+// (row, column) of the gradient matrix or per bias entry.
+__global__ void k_wgrad_reduce(WgradArgs a, int kt, int ct, int nz, int rs, int cs, float* dw,
+                               float* db) {
+    const int64_t rows = (int64_t)ct * rs * 16, cols = (int64_t)kt * cs * 16;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < rows * cols) {
+        const int row = (int)(i / cols), col = (int)(i - (int64_t)row * cols);
+        const int cty = row / (rs * 16), rl = row - cty * rs * 16;
+        const int ktx = col / (cs * 16), cl = col - ktx * cs * 16;
+        if (row >= a.cout || col >= a.K) return;
+        const int t = col / a.cin, cc = col - t * a.cin;
+        if (cc < a.c1s && cc >= a.c1) return;  // zero padding channels of x1
+        const int ci = cc < a.c1s ? cc : a.c1 + (cc - a.c1s);
+        const int64_t per = (int64_t)rs * 16 * cs * 16;
+        float sum = 0.f;
+#pragma unroll 8
+        for (int z = 0; z < nz; ++z)
+            sum += a.part[(((int64_t)z * ct + cty) * kt + ktx) * per + rl * (cs * 16) + cl];
+        dw[((int64_t)row * a.taps + t) * a.cin_real + ci] = sum;
+    } else if (i < rows * cols + a.cout) {
+        const int co = (int)(i - rows * cols);
+        const int cty = co / (rs * 16), rl = co - cty * rs * 16;
+        float sum = 0.f;
+        for (int z = 0; z < nz; ++z)
+            sum += a.part[a.bias_off + ((int64_t)z * ct + cty) * (rs * 16) + rl];
+        db[co] = sum;
     }
 }
 
@@ -310,8 +372,11 @@ __global__ void __launch_bounds__(256) k_wgrad(WgradArgs a) {
 //     aligned 16-byte read;
 //   - the output gradient is transposed the same way (8 cells x 8 channels
 //     per thread), and its A fragments serve all taps.
-// Wave w accumulates taps w, w + 4, ...  Results go to FP32 with atomic
-// adds; blocks of the first channel group also sum the bias gradient.
+// Wave w accumulates taps w, w + 4, ...  Each block writes its partial sums
+// (block b = blockIdx.y * gridDim.x + blockIdx.x: [tap][co][16 channels]);
+// wave 0 of the first channel group also sums the output gradient for the
+// bias (a matrix-core product against ones; partials [blockIdx.y][coutp] at
+// bias_off).  k_wgrad_brick_reduce adds the partials up.
 constexpr int kBrickRow = 4 * 6 * 16 + 8;  // one channel's halo (hz, hy, x), padded
 
 template <int RS>
@@ -332,7 +397,10 @@ __global__ void __launch_bounds__(256) k_wgrad_brick(WgradArgs a, int64_t bricks
     for (int j = 0; j < NT; ++j)
 #pragma unroll
         for (int m = 0; m < RS; ++m) acc[j][m] = floatx4{0.f, 0.f, 0.f, 0.f};
-    float bsum = 0.f;
+    floatx4 accb[RS];
+#pragma unroll
+    for (int m = 0; m < RS; ++m) accb[m] = floatx4{0.f, 0.f, 0.f, 0.f};
+    const bool bias_wave = blockIdx.x == 0 && wave == 0;
     // Roles: threads 0-95 load input halo rows, the next 32 * RS the output
     // gradient.  The global loads of brick b + 1 are issued into registers
     // before the matrix-core phase of brick b, so their latency is hidden.
@@ -409,15 +477,17 @@ __global__ void __launch_bounds__(256) k_wgrad_brick(WgradArgs a, int64_t bricks
         }
         __syncthreads();
         if (b + 1 < b1) fetch(b + 1);
-        if (blockIdx.x == 0 && tid < RS * 16) {
-#pragma unroll 8
-            for (int i = 0; i < 128; ++i) bsum += (float)dT[tid][i];
-        }
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
             bf16x8 av[RS];
 #pragma unroll
             for (int m = 0; m < RS; ++m) av[m] = *(const bf16x8*)&dT[m * 16 + r][s * 32 + q * 8];
+            if (bias_wave) {
+#pragma unroll
+                for (int m = 0; m < RS; ++m)
+                    accb[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[m], ones_frag(), accb[m],
+                                                                      0, 0, 0);
+            }
 #pragma unroll
             for (int j = 0; j < NT; ++j) {
                 const int t = wave + 4 * j;
@@ -435,10 +505,8 @@ __global__ void __launch_bounds__(256) k_wgrad_brick(WgradArgs a, int64_t bricks
         }
         __syncthreads();
     }
-    if (blockIdx.x == 0 && tid < RS * 16 && tid < a.cout) atomicAdd(&a.db[tid], bsum);
-    const int cc = c0 + r;
-    if (cc >= a.cin || (cc < a.c1s && cc >= a.c1)) return;  // padding channels
-    const int ci = cc < a.c1s ? cc : a.c1 + (cc - a.c1s);
+    const int64_t blk = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+    float* pb = a.part + blk * (27 * RS * 16 * 16);
 #pragma unroll
     for (int j = 0; j < NT; ++j) {
         const int t = wave + 4 * j;
@@ -446,11 +514,42 @@ __global__ void __launch_bounds__(256) k_wgrad_brick(WgradArgs a, int64_t bricks
 #pragma unroll
         for (int m = 0; m < RS; ++m)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int co = m * 16 + q * 4 + i;
-                if (co < a.cout)
-                    atomicAdd(&a.dw[((int64_t)co * 27 + t) * a.cin_real + ci], acc[j][m][i]);
-            }
+            for (int i = 0; i < 4; ++i)
+                pb[((t * RS + m) * 16 + q * 4 + i) * 16 + r] = acc[j][m][i];
+    }
+    if (bias_wave && r == 0) {
+        float* bb = a.part + a.bias_off + (int64_t)blockIdx.y * (RS * 16);
+#pragma unroll
+        for (int m = 0; m < RS; ++m)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) bb[m * 16 + q * 4 + i] = accb[m][i];
+    }
+}
+
+// Sum of the k_wgrad_brick partials over the brick ranges, into dw[co][tap]
+// [ci] (zero padding channels dropped) and db.  One thread per gradient
+// entry of (channel group, tap, co, channel) or per bias entry.
+__global__ void k_wgrad_brick_reduce(WgradArgs a, int chunks, int groups, int rs, float* dw,
+                                     float* db) {
+    const int64_t per = (int64_t)27 * rs * 16 * 16;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < per * chunks) {
+        const int chunk = (int)(i / per);
+        const int e = (int)(i - (int64_t)chunk * per);
+        const int t = e / (rs * 256), rem = e - t * rs * 256;
+        const int co = rem >> 4, cl = rem & 15;
+        const int cc = chunk * 16 + cl;
+        if (co >= a.cout || cc >= a.cin || (cc < a.c1s && cc >= a.c1)) return;
+        const int ci = cc < a.c1s ? cc : a.c1 + (cc - a.c1s);
+        float sum = 0.f;
+#pragma unroll 8
+        for (int g = 0; g < groups; ++g) sum += a.part[((int64_t)g * chunks + chunk) * per + e];
+        dw[((int64_t)co * 27 + t) * a.cin_real + ci] = sum;
+    } else if (i < per * chunks + a.cout) {
+        const int co = (int)(i - per * chunks);
+        float sum = 0.f;
+        for (int g = 0; g < groups; ++g) sum += a.part[a.bias_off + (int64_t)g * rs * 16 + co];
+        db[co] = sum;
     }
 }
 
@@ -946,19 +1045,118 @@ hipError_t conv_backward_data(const ConvGeom& g, const __bf16* dy, const __bf16*
     return launch_conv<0>(a, g.cinp, s);
 }
 
+namespace {
+
+// Launch plan of the weight gradient: the brick kernel (grids of at least 16
+// cells, 27 taps, >= 16 input channels, 16/32/64 output channels) or the
+// tiled kernel, its grid, and the floats of partial sums it writes.
+struct WgradPlan {
+    bool brick;
+    int rs, cs;
+    int chunks, groups;  // brick: channel groups x brick ranges
+    int64_t per;         // brick: bricks per range
+    int kt, ct, nz;      // tiled: column tiles, row tiles, voxel chunks
+    int64_t vchunk;
+    int64_t part_floats, bias_off;  // partial sums of every block
+    int64_t rows, wwidth, bwidth;   // rows of partials, weight / bias floats per row
+    int64_t scratch_floats;         // partials + the first reduction pass
+};
+
+// Scratch of the first reduction pass, after the partials: the weight rows
+// and the bias rows summed over slices of kRowSlice rows.
+void finish_plan(WgradPlan* p) {
+    const int64_t sl = (p->rows + kRowSlice - 1) / kRowSlice;
+    p->scratch_floats = p->part_floats + sl * (p->wwidth + p->bwidth);
+}
+
+// Partial sums kept to about 32 MB and 1024 blocks: enough blocks to fill
+// the chip, and a second pass that reads far less than the layer's inputs.
+constexpr int64_t kPartFloats = 8 << 20;
+constexpr int64_t kPartBlocks = 1024;
+
+// (The brick kernel reads the output gradient unmasked: relu != 0 takes the
+// tiled kernel.)
+WgradPlan wgrad_plan(const ConvGeom& g, int relu) {
+    WgradPlan p = {};
+    const int64_t M = (int64_t)g.n << (3 * g.lg);
+    p.brick = !relu && g.lg >= 4 && g.taps == 27 && g.cin >= 16 &&
+              (g.coutp == 16 || g.coutp == 32 || g.coutp == 64);
+    if (p.brick) {
+        p.rs = g.coutp / 16;
+        p.chunks = ceil_div(g.cin, 16);
+        const int64_t nbricks = M / 128;
+        const int64_t blk_floats = (int64_t)27 * g.coutp * 16;
+        const int64_t cap = std::max<int64_t>(
+            1, std::min<int64_t>(kPartBlocks, kPartFloats / blk_floats) / p.chunks);
+        const int64_t groups = std::max<int64_t>(1, std::min<int64_t>(nbricks, cap));
+        p.per = (nbricks + groups - 1) / groups;
+        p.groups = ceil_div(nbricks, p.per);
+        p.bias_off = (int64_t)p.groups * p.chunks * blk_floats;
+        p.part_floats = p.bias_off + (int64_t)p.groups * g.coutp;
+        p.rows = p.groups;
+        p.wwidth = (int64_t)p.chunks * blk_floats;
+        p.bwidth = g.coutp;
+        finish_plan(&p);
+        return p;
+    }
+    p.rs = g.coutp >= 64 ? 4 : g.coutp >= 32 ? 2 : 1;
+    p.cs = 8 / p.rs;
+    p.ct = ceil_div(g.coutp, 16 * p.rs);
+    p.kt = ceil_div(g.K, 16 * p.cs);
+    const int64_t steps = (M + 31) / 32;
+    const int64_t blk_floats = (int64_t)p.rs * 16 * p.cs * 16;
+    const int64_t tiles = (int64_t)p.kt * p.ct;
+    const int64_t cap = std::max<int64_t>(
+        1, std::min<int64_t>(2 * kPartBlocks, kPartFloats / blk_floats) / tiles);
+    const int64_t chunks = std::max<int64_t>(1, std::min<int64_t>(steps, cap));
+    p.vchunk = (steps + chunks - 1) / chunks * 32;
+    p.nz = ceil_div(M, p.vchunk);
+    p.bias_off = (int64_t)p.nz * tiles * blk_floats;
+    p.part_floats = p.bias_off + (int64_t)p.nz * p.ct * p.rs * 16;
+    p.rows = p.nz;
+    p.wwidth = tiles * blk_floats;
+    p.bwidth = (int64_t)p.ct * p.rs * 16;
+    finish_plan(&p);
+    return p;
+}
+
+// First reduction pass over the partials of plan p; returns the arguments
+// of the second pass (partials replaced by the slice sums, rows by slices).
+hipError_t sum_slices(const WgradPlan& p, const WgradArgs& a, WgradArgs* b, int64_t* rows,
+                      hipStream_t s) {
+    const int64_t sl = (p.rows + kRowSlice - 1) / kRowSlice;
+    float* out = a.part + p.part_floats;
+    hipLaunchKernelGGL(k_sum_row_slices, dim3(ceil_div(sl * p.wwidth, 256)), dim3(256), 0, s,
+                       (const float*)a.part, p.rows, p.wwidth, out);
+    hipLaunchKernelGGL(k_sum_row_slices, dim3(ceil_div(sl * p.bwidth, 256)), dim3(256), 0, s,
+                       (const float*)(a.part + p.bias_off), p.rows, p.bwidth,
+                       out + sl * p.wwidth);
+    *b = a;
+    b->part = out;
+    b->bias_off = sl * p.wwidth;
+    *rows = sl;
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int64_t wgrad_scratch_floats(const ConvGeom& g) {
+    return std::max(wgrad_plan(g, 0).scratch_floats, wgrad_plan(g, 1).scratch_floats);
+}
+
 hipError_t conv_backward_weight(const ConvGeom& g, const __bf16* x1, const __bf16* x2,
                                 const __bf16* dy, const __bf16* y, int relu, float* dw,
-                                float* db, hipStream_t s) {
-    if (!x1 || !dy || !dw || !db || (relu && !y) || (g.c2 > 0 && (!x2 || g.lg < 1)))
+                                float* db, float* scratch, hipStream_t s) {
+    if (!x1 || !dy || !dw || !db || !scratch || (relu && !y) || (g.c2 > 0 && (!x2 || g.lg < 1)))
         return hipErrorInvalidValue;
-    const int64_t M = (int64_t)g.n << (3 * g.lg);
+    const WgradPlan p = wgrad_plan(g, relu);
     WgradArgs a;
     a.x1 = x1;
     a.x2 = x2;
     a.dy = dy;
     a.y = y;
-    a.dw = dw;
-    a.db = db;
+    a.part = scratch;
+    a.bias_off = p.bias_off;
     a.n = g.n;
     a.lg = g.lg;
     a.taps = g.taps;
@@ -972,36 +1170,40 @@ hipError_t conv_backward_weight(const ConvGeom& g, const __bf16* x1, const __bf1
     a.ys = g.ys;
     a.relu = relu;
     a.cin_real = g.c1 + g.c2;
-    if (!relu && g.lg >= 4 && g.taps == 27 && g.cin >= 16 &&
-        (g.coutp == 16 || g.coutp == 32 || g.coutp == 64)) {
-        // bricks: one block per 16 input channels and range of bricks; the
-        // number of blocks keeps the atomic adds of their partial sums (27 *
-        // 16 * coutp each) near 8e6
-        const int chunks = ceil_div(g.cin, 16);
-        const int64_t nbricks = M / 128;
-        const int64_t cap = std::max<int64_t>(1, 8000000 / (27 * 16 * (int64_t)g.coutp * chunks));
-        const int64_t groups = std::max<int64_t>(1, std::min<int64_t>(nbricks, cap));
-        const int64_t per = (nbricks + groups - 1) / groups;
-        const dim3 grid(chunks, (unsigned)ceil_div(nbricks, per));
-        switch (g.coutp) {
-            case 64: hipLaunchKernelGGL(k_wgrad_brick<4>, grid, dim3(256), 0, s, a, per); break;
-            case 32: hipLaunchKernelGGL(k_wgrad_brick<2>, grid, dim3(256), 0, s, a, per); break;
-            default: hipLaunchKernelGGL(k_wgrad_brick<1>, grid, dim3(256), 0, s, a, per); break;
+    a.vchunk = p.vchunk;
+    if (p.brick) {
+        const dim3 grid(p.chunks, p.groups);
+        switch (p.rs) {
+            case 4: hipLaunchKernelGGL(k_wgrad_brick<4>, grid, dim3(256), 0, s, a, p.per); break;
+            case 2: hipLaunchKernelGGL(k_wgrad_brick<2>, grid, dim3(256), 0, s, a, p.per); break;
+            default: hipLaunchKernelGGL(k_wgrad_brick<1>, grid, dim3(256), 0, s, a, p.per); break;
         }
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        WgradArgs b;
+        int64_t rows = 0;
+        e = sum_slices(p, a, &b, &rows, s);
+        if (e != hipSuccess) return e;
+        const int64_t nred = (int64_t)27 * g.coutp * 16 * p.chunks + g.cout;
+        hipLaunchKernelGGL(k_wgrad_brick_reduce, dim3(ceil_div(nred, 256)), dim3(256), 0, s, b,
+                           p.chunks, (int)rows, p.rs, dw, db);
         return hipGetLastError();
     }
-    const int rs = g.coutp >= 64 ? 4 : g.coutp >= 32 ? 2 : 1;
-    const int cs = 8 / rs;
-    const int ct = ceil_div(g.coutp, 16 * rs), kt = ceil_div(g.K, 16 * cs);
-    const int64_t steps = (M + 31) / 32;
-    const int64_t chunks = std::max<int64_t>(1, std::min<int64_t>(steps, 4096 / (kt * ct)));
-    a.vchunk = (steps + chunks - 1) / chunks * 32;
-    const dim3 grid(kt, ct, ceil_div(M, a.vchunk));
-    switch (rs) {
+    const dim3 grid(p.kt, p.ct, p.nz);
+    switch (p.rs) {
         case 4: hipLaunchKernelGGL(k_wgrad<4>, grid, dim3(256), 0, s, a); break;
         case 2: hipLaunchKernelGGL(k_wgrad<2>, grid, dim3(256), 0, s, a); break;
         default: hipLaunchKernelGGL(k_wgrad<1>, grid, dim3(256), 0, s, a); break;
     }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    WgradArgs b;
+    int64_t rows = 0;
+    e = sum_slices(p, a, &b, &rows, s);
+    if (e != hipSuccess) return e;
+    const int64_t nred = (int64_t)p.ct * p.rs * 16 * p.kt * p.cs * 16 + g.cout;
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3(ceil_div(nred, 256)), dim3(256), 0, s, b, p.kt, p.ct,
+                       (int)rows, p.rs, p.cs, dw, db);
     return hipGetLastError();
 }
 

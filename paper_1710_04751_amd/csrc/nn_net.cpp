@@ -62,6 +62,7 @@ struct Layout {
     size_t dact[kLayers];  // gradients of the outputs (head: dy with 8 channels)
     size_t in, pool[3], dpool[3], dcat[3];
     size_t partial, loss;
+    size_t wpart;  // weight-gradient partial sums (the largest layer's)
     size_t total;
 };
 
@@ -136,6 +137,13 @@ Layout make_layout(const lbm_nn_config& c) {
     }
     L.partial = take(((c0 + 255) / 256) * 8);
     L.loss = take(64);
+    int64_t wpart = 0;
+    for (int l = 0; l < kLayers; ++l) {
+        const LayerDef& d = kDefs[l];
+        const ConvGeom g = make_geom(B, lg0 - d.level, d.taps, d.c1, d.c2, d.cout);
+        wpart = std::max(wpart, wgrad_scratch_floats(g));
+    }
+    L.wpart = take((size_t)wpart * 4);
     L.total = o;
     return L;
 }
@@ -223,7 +231,9 @@ lbm_status backward(lbm_nn* nn, int n) {
         layer_inputs(nn, l, &x1, &x2);
         float* dw = grad + nn->off[l];
         float* db = dw + (int64_t)d.cout * d.taps * (d.c1 + d.c2);
-        NN_TRY(conv_backward_weight(g, x1, x2, dact(l), nullptr, 0, dw, db, s), "weight grad");
+        NN_TRY(conv_backward_weight(g, x1, x2, dact(l), nullptr, 0, dw, db,
+                                    nn->at<float>(L.wpart), s),
+               "weight grad");
         if (l == 0) break;
         // where the input gradient goes, and the ReLU mask it takes there
         __bf16* dx;
