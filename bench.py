@@ -472,8 +472,20 @@ def cpu_baseline(n_full, ra, seconds_hint=15.0, log=print):
     O.set_threads(threads)
     single = side ** 3 * 2 / d1 / 1e6
     log(f"cpu oracle, one core: {single:.3f} MLUPS")
+    # the small parity case in full: 16^3, Ra 1e3, 2000 steps from rest (8.2 M cell updates)
+    from paper_1710_04751_amd import workloads as W
+    c = W.SMALL_PARITY
+    ps = O.cavity_params(c.n, c.Ra, Pr=c.Pr, u0=c.u0)
+    Fs, Gs = O.rest_state(ps)
+    t2 = time.perf_counter()
+    O.run(ps, c.steps, Fs, Gs)
+    d2 = time.perf_counter() - t2
+    small = {"workload": f"{c.n}^3, Ra {c.Ra:g}, {c.steps} steps from rest, D3Q7, FP64",
+             "cell_updates": c.n ** 3 * c.steps, "seconds": round(d2, 3),
+             "MLUPS": round(c.n ** 3 * c.steps / d2 / 1e6, 4), "threads": used}
+    log(f"cpu oracle, {small['workload']}: {d2:.2f} s, {small['MLUPS']} MLUPS")
     return {"value": mlups, "unit": "MLUPS", "cores": used, "kind": "oracle",
-            "single_core_MLUPS": round(single, 4),
+            "single_core_MLUPS": round(single, 4), "small_cavity_2000_steps": small,
             "sample": f"{side}^3 cells with the {n_full}^3 Ra={ra:g} lattice parameters, "
                       f"{steps} steps from rest ({dt:.1f} s) on {used} threads, then 2 steps on "
                       f"one core ({d1:.1f} s), FP64 oracle"}

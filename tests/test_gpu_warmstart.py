@@ -8,8 +8,8 @@ Range: Ra in [1e3, 8e3].  On the 32^3 grid the symmetric steady state stops
 being an attractor from Ra ~ 1e4 (the staggered and antisymmetric modes of
 the discrete model grow), and warm starts there can leave it.  The gain at
 this size is modest (medians of the per-cavity step ratio 0.77-0.85 in
-repeated runs; training is not bitwise repeatable because the weight
-gradient sums with atomics), since a start whose error is ~1e-2 of the field
+repeated runs of an earlier library whose weight gradients summed with
+atomics; they are reduced in a fixed order now), since a start whose error is ~1e-2 of the field
 saves about two of the eight decades the residual falls from rest; the bar
 is a median ratio below 0.95 over 24 held-out cavities.  The 64^3 study of
 the benchmark is the full-size measurement."""
