@@ -29,19 +29,18 @@ struct ConvGeom {
 
 ConvGeom make_geom(int n, int lg, int taps, int c1, int c2, int cout);
 
-// Master weight w[co][tap][ci] (ci over the c1 + c2 real channels) ->
-// packed BF16 rows wp[coutp][kpad] (k = tap * cin + stored channel) and the
-// transposed, tap-flipped copy wt[cinp][kpad_t] (k = tap * ys + co) that
-// turns the input gradient into a forward convolution.
-hipError_t pack_weights(const ConvGeom& g, const float* w, __bf16* wp, __bf16* wt,
-                        hipStream_t s);
+// Master weights of layer l at theta + woff[l], w[co][tap][ci] (ci over the
+// c1 + c2 real channels) -> packed BF16 rows wp[l][coutp][kpad] (k = tap *
+// cin + stored channel) and the transposed, tap-flipped copy
+// wt[l][cinp][kpad_t] (k = tap * ys + co) that turns the input gradient into
+// a forward convolution; all layers (at most kMaxPackLayers) in one launch.
+constexpr int kMaxPackLayers = 16;
+hipError_t pack_weights(int layers, const ConvGeom* g, const float* theta, const int64_t* woff,
+                        __bf16* const* wp, __bf16* const* wt, hipStream_t s);
 
-// out = conv(x1 (masked by mask > 0 when mask is given), x2) + bias, ReLU if
-// relu; BF16 channels-last [n][v][ys] (mode 0), or FP32 channel-first
-// [n][cout][v] times scale[c] (mode 1, cout <= 4).
-hipError_t conv_forward(const ConvGeom& g, const __bf16* x1, const __bf16* x2,
-                        const __bf16* mask, const __bf16* wp, const float* bias, int relu,
-                        int mode, void* out, const float* scale4, hipStream_t s);
+// out = conv(x1, x2) + bias, ReLU if relu; BF16 channels-last [n][v][ys].
+hipError_t conv_forward(const ConvGeom& g, const __bf16* x1, const __bf16* x2, const __bf16* wp,
+                        const float* bias, int relu, __bf16* out, hipStream_t s);
 
 // Input gradient: dx[n][v][cin] = sum over taps and co of dy at the
 // neighbour times the weight.  dy is the gradient of the pre-activation
@@ -77,13 +76,28 @@ hipError_t upsample_backward(int n, int lg, int c, const __bf16* dcat, int ctot,
 // log10_ra is a host array of n <= kMaxBatch values (passed by value).
 hipError_t make_inputs(int n, int lg, const float* log10_ra, __bf16* x, hipStream_t s);
 
-// MSE loss of out (FP32 channel-first [n][4][v]) against targets[idx[i]]
-// (idx: host array of n <= kMaxBatch, passed by value) times tscale; writes dy[n][v][8] = 2 (out - t) / count (channels 4..7
-// zero) and one partial sum per block into partial (double).
-hipError_t mse_forward_backward(int n, int lg, const float* out, const float* targets,
-                                const int32_t* idx, int64_t stride, const float* tscale4,
-                                __bf16* dy, double* partial, int* nblocks, hipStream_t s);
 hipError_t reduce_sum(const double* partial, int n, double* out, hipStream_t s);
+
+// The 1 x 1 x 1 head (16 BF16 input channels -> 4 FP32 outputs) on the
+// vector units with the FP32 master weights w[co][ci] and bias b[co]:
+// out[n][4][v] (channel-first) = (w x + b) * scale4[c] (scale4 NULL: 1).
+bool head_geometry(const ConvGeom& g);
+hipError_t head_forward(const ConvGeom& g, const __bf16* x, const float* w, const float* b,
+                        const float* scale4, float* out, hipStream_t s);
+// Loss and backward step of the head in one pass over the voxels: against
+// targets[idx[i]] (channel-first, stride floats apart, times tscale4), the
+// output gradient 2 (out - t) / count, the input gradient dx[n][v][16]
+// (BF16, 0 where x <= 0), the weight and bias gradients (grad: w[4][16] then
+// b[4], FP32) and the summed squared error (*loss, device, FP64).  Scratch:
+// head_scratch_floats(g) floats and head_backward_blocks(g) doubles at
+// lpartial.  Sums run in a fixed order.
+constexpr int kHeadBlocks = 1024;
+int head_backward_blocks(const ConvGeom& g);
+int64_t head_scratch_floats(const ConvGeom& g);
+hipError_t head_backward(const ConvGeom& g, const float* out, const float* targets,
+                         const int32_t* idx, int64_t stride, const float* tscale4,
+                         const __bf16* x, const float* w, __bf16* dx, float* grad,
+                         float* scratch, double* lpartial, double* loss, hipStream_t s);
 
 hipError_t adam_update(int64_t count, float* theta, float* m, float* v, const float* g, int t,
                        float lr, float beta1, float beta2, float eps, hipStream_t s);

@@ -1,6 +1,7 @@
 // gfx950 kernels of the warm-start network: 3D convolutions as implicit
 // GEMMs on the BF16 matrix cores (v_mfma_f32_16x16x32_bf16, FP32
-// accumulation), pooling, upsampling, the loss and Adam.
+// accumulation), the 1 x 1 x 1 head with the loss on the vector units,
+// pooling, upsampling and Adam.
 //
 // Matrix-core fragments (64 lanes, r = lane % 16, q = lane / 16):
 //   A (16 x 32): lane holds row r, k = 8q .. 8q+7;
@@ -41,15 +42,26 @@ struct SampleInts {
     int32_t v[kMaxBatch];
 };
 
+// One layer of the weight packing: destinations, the layer's offset in the
+// master parameters and its geometry.
+struct PackLayer {
+    __bf16* wp;
+    __bf16* wt;
+    int64_t woff;
+    int32_t coutp, kpad, cout, K, cin, c1, c1s, taps, cin_real, cinp, kpad_t, ys;
+};
+struct PackTable {
+    PackLayer l[kMaxPackLayers];
+    int64_t blk[2 * kMaxPackLayers];  // cumulative blocks of 256 over the segments
+};
+
 struct ConvArgs {
     const __bf16* x1;
     const __bf16* x2;
-    const __bf16* mask;
     const __bf16* w;
     const float* bias;
-    void* out;
-    const __bf16* omask;  // MODE 0: outputs where omask <= 0 are written as 0
-    float scale[4];
+    __bf16* out;
+    const __bf16* omask;  // outputs where omask <= 0 are written as 0
     int32_t n, lg, taps, c1s, c2, cin, K, kpad, cout, ys, relu;
 };
 
@@ -58,7 +70,7 @@ struct ConvArgs {
 // voxel tiles.  The KS waves of a block split the k range (wave w takes
 // every KS-th step of 32 from step w) and add their partial sums through
 // LDS; this keeps enough waves in flight on the coarse grids.
-template <int NSUB, int MODE, int MT, int KS>
+template <int NSUB, int MT, int KS>
 __global__ void __launch_bounds__(64 * KS) k_conv(ConvArgs a) {
     const int lane = threadIdx.x & 63, r = lane & 15, q = lane >> 4;
     const int wave = threadIdx.x >> 6;
@@ -85,51 +97,75 @@ __global__ void __launch_bounds__(64 * KS) k_conv(ConvArgs a) {
     for (int m = 0; m < MT; ++m)
 #pragma unroll
         for (int j = 0; j < NSUB; ++j) acc[m][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-    const int kfirst = q * 8 + 32 * wave;
-    int tap = kfirst / a.cin, c = kfirst - tap * a.cin;
-    for (int k0 = kfirst; k0 < a.kpad; k0 += 32 * KS) {
-        int dz = 0, dy = 0, dx = 0;
-        if (a.taps == 27) {
-            dz = tap / 9 - 1;
-            dy = (tap / 3) % 3 - 1;
-            dx = tap % 3 - 1;
-        }
-        bf16x8 av[MT];
+    // Wave w takes the k steps w, w + KS, ...: nst of them; at step s the
+    // lane's 8 k values start at kw + 32 KS s.  The fragments of a step are
+    // A (MT voxel tiles, 8 channels of one tap per lane) and B (NSUB weight
+    // tiles).  With one voxel tile two register sets take turns: the loads of
+    // step s + 1 go into one while the matrix cores work on step s in the
+    // other.  The loop body has no branches (a lane outside the grid loads
+    // voxel 0 and takes zeros; a step past the last reloads the last one's
+    // addresses with a zero A fragment, so its products add 0), so the
+    // compiler keeps the loads ahead of the products and the waits cover
+    // only the step in use.
+    const int kw = q * 8 + 32 * wave;
+    const int nst = kw < a.kpad ? (a.kpad - 1 - kw) / (32 * KS) + 1 : 0;
+    const float icin = 1.f / (float)a.cin;
+    const int h = lg - 1;
+    auto load_step = [&](int st, bf16x8* av, bf16x8* bv) __attribute__((always_inline)) {
+        const bool live = st < nst;
+        const int k = kw + (live ? st : nst - 1) * (32 * KS);
+        // tap = k / cin (exact: k < 2^13, so (k + 0.5) / cin is far from an integer)
+        const int tap = (int)(((float)k + 0.5f) * icin), c = k - tap * a.cin;
+        const bool t27 = a.taps == 27;
+        const int dz = t27 ? tap / 9 - 1 : 0, dy = t27 ? (tap / 3) % 3 - 1 : 0,
+                  dx = t27 ? tap % 3 - 1 : 0;
+        const bool lo = c < a.c1s;
+        const __bf16* base = lo ? a.x1 : a.x2;
 #pragma unroll
         for (int m = 0; m < MT; ++m) {
-#pragma unroll
-            for (int i = 0; i < 8; ++i) av[m][i] = (__bf16)0.f;
             const int zz = vz[m] + dz, yy = vy[m] + dy, xx = vx[m] + dx;
-            if (vok[m] && k0 < a.K && (unsigned)zz < (unsigned)G && (unsigned)yy < (unsigned)G &&
-                (unsigned)xx < (unsigned)G) {
-                if (c < a.c1s) {
-                    const int64_t vi = ((int64_t)vs[m] << (3 * lg)) + ((int64_t)zz << (2 * lg)) +
-                                       ((int64_t)yy << lg) + xx;
-                    av[m] = *(const bf16x8*)(a.x1 + vi * a.c1s + c);
-                    if (a.mask) {
-                        const bf16x8 mk = *(const bf16x8*)(a.mask + vi * a.c1s + c);
+            const bool ok = live && vok[m] && k < a.K && (unsigned)zz < (unsigned)G &&
+                            (unsigned)yy < (unsigned)G && (unsigned)xx < (unsigned)G;
+            const int zc = ok ? zz : 0, yc = ok ? yy : 0, xc = ok ? xx : 0;
+            const int64_t off =
+                lo ? (((int64_t)vs[m] << (3 * lg)) + ((int64_t)zc << (2 * lg)) +
+                      ((int64_t)yc << lg) + xc) * a.c1s + c
+                   : (((int64_t)vs[m] << (3 * h)) + ((int64_t)(zc >> 1) << (2 * h)) +
+                      ((int64_t)(yc >> 1) << h) + (xc >> 1)) * a.c2 + (c - a.c1s);
+            const bf16x8 v = *(const bf16x8*)(base + off);
 #pragma unroll
-                        for (int i = 0; i < 8; ++i)
-                            if (!((float)mk[i] > 0.f)) av[m][i] = (__bf16)0.f;
-                    }
-                } else {
-                    const int h = lg - 1;
-                    const int64_t vi = ((int64_t)vs[m] << (3 * h)) +
-                                       ((int64_t)(zz >> 1) << (2 * h)) +
-                                       ((int64_t)(yy >> 1) << h) + (xx >> 1);
-                    av[m] = *(const bf16x8*)(a.x2 + vi * a.c2 + (c - a.c1s));
-                }
-            }
+            for (int i = 0; i < 8; ++i) av[m][i] = ok ? v[i] : (__bf16)0.f;
         }
 #pragma unroll
-        for (int j = 0; j < NSUB; ++j) {
-            const bf16x8 bv = *(const bf16x8*)(a.w + (int64_t)(cobase + j * 16 + r) * a.kpad + k0);
+        for (int j = 0; j < NSUB; ++j)
+            bv[j] = *(const bf16x8*)(a.w + (int64_t)(cobase + j * 16 + r) * a.kpad + k);
+    };
+    auto products = [&](const bf16x8* av, const bf16x8* bv) __attribute__((always_inline)) {
+#pragma unroll
+        for (int j = 0; j < NSUB; ++j)
 #pragma unroll
             for (int m = 0; m < MT; ++m)
-                acc[m][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[m], bv, acc[m][j], 0, 0, 0);
+                acc[m][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[m], bv[j], acc[m][j], 0, 0, 0);
+    };
+    if constexpr (MT == 1) {
+        if (nst > 0) {
+            bf16x8 a0[MT], b0[NSUB], a1[MT], b1[NSUB];
+            load_step(0, a0, b0);
+            for (int st = 0; st < nst; st += 2) {
+                load_step(st + 1, a1, b1);
+                products(a0, b0);
+                load_step(st + 2, a0, b0);
+                products(a1, b1);
+            }
         }
-        c += 32 * KS;
-        while (c >= a.cin) c -= a.cin, ++tap;
+    } else {
+        // four voxel tiles: a second register set would cost more occupancy
+        // than its prefetch gains (measured), so each step loads and uses one
+        for (int st = 0; st < nst; ++st) {
+            bf16x8 a0[MT], b0[NSUB];
+            load_step(st, a0, b0);
+            products(a0, b0);
+        }
     }
     if constexpr (KS > 1) {
         __shared__ floatx4 part[KS - 1][MT * NSUB][64];
@@ -157,20 +193,14 @@ __global__ void __launch_bounds__(64 * KS) k_conv(ConvArgs a) {
 #pragma unroll
             for (int j = 0; j < NSUB; ++j) {
                 const int co = cobase + j * 16 + r;
-                if (MODE == 0) {
-                    if (co < a.ys) {
-                        float val = 0.f;
-                        if (co < a.cout) {
-                            val = acc[m][j][i] + (a.bias ? a.bias[co] : 0.f);
-                            if (a.relu) val = fmaxf(val, 0.f);
-                            if (a.omask && !((float)a.omask[vo * a.ys + co] > 0.f)) val = 0.f;
-                        }
-                        ((__bf16*)a.out)[vo * a.ys + co] = (__bf16)val;
+                if (co < a.ys) {
+                    float val = 0.f;
+                    if (co < a.cout) {
+                        val = acc[m][j][i] + (a.bias ? a.bias[co] : 0.f);
+                        if (a.relu) val = fmaxf(val, 0.f);
+                        if (a.omask && !((float)a.omask[vo * a.ys + co] > 0.f)) val = 0.f;
                     }
-                } else if (co < a.cout) {
-                    const float val = acc[m][j][i] + (a.bias ? a.bias[co] : 0.f);
-                    const int64_t sidx = vo >> (3 * lg), vin = vo & (V - 1);
-                    ((float*)a.out)[(sidx * a.cout + co) * V + vin] = val * a.scale[co];
+                    a.out[vo * a.ys + co] = (__bf16)val;
                 }
             }
         }
@@ -306,16 +336,25 @@ __global__ void __launch_bounds__(256) k_wgrad(WgradArgs a) {
     }
 }
 
-// First pass of the partial-sum reduction: out[j][w] = sum of in[g][w] over
-// the rows g of slice j (kRowSlice consecutive rows, fewer in the last), in
-// order; one thread per (slice, column), so the loads of many rows are in
-// flight at once.
+// First pass of the partial-sum reduction: for the weight partials (rows x
+// ww floats at in) and then the bias partials (rows x bw floats at in +
+// boff), out[j][w] = sum of in[g][w] over the rows g of slice j (kRowSlice
+// consecutive rows, fewer in the last), in order.  One thread per (slice,
+// column), so the loads of many rows are in flight at once; the weight
+// slices go to out, the bias slices after them.
 constexpr int kRowSlice = 16;
-__global__ void k_sum_row_slices(const float* __restrict__ in, int64_t rows, int64_t width,
-                                 float* __restrict__ out) {
+__global__ void k_sum_row_slices(const float* __restrict__ in, int64_t boff, int64_t rows,
+                                 int64_t ww, int64_t bw, float* __restrict__ out) {
     const int64_t slices = (rows + kRowSlice - 1) / kRowSlice;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= slices * width) return;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t width = ww;
+    if (i >= slices * ww) {
+        i -= slices * ww;
+        if (i >= slices * bw) return;
+        in += boff;
+        out += slices * ww;
+        width = bw;
+    }
     const int64_t j = i / width, w = i - j * width;
     const int64_t g0 = j * kRowSlice;
     const int n = (int)(rows - g0 < kRowSlice ? rows - g0 : kRowSlice);
@@ -526,6 +565,197 @@ __global__ void __launch_bounds__(256) k_wgrad_brick(WgradArgs a, int64_t bricks
     }
 }
 
+// Weight gradient on the same bricks with one copy of the input halo, for
+// 16 and 32 output channels.  Partial sums, bias product and reduction are
+// those of k_wgrad_brick; what differs:
+//   - the halo is stored once per channel, as 24 rows (hz, hy) of 18 cells
+//     (x0 - 1 .. x0 + 16; row stride kHaloRow, channel stride kHaloChan,
+//     which puts the 16-byte reads of 8 consecutive channels on distinct
+//     banks);
+//   - a block has 3 waves and wave w takes the 9 taps with dz = w - 1.  Per
+//     k step and dy a lane reads cells 8h .. 8h + 9 of its row (h: the
+//     lane's x half) with one 16-byte and one 4-byte LDS read; the B
+//     fragments of dx = -1, +1 are dwords 0-3 and 1-4 of those cells, the
+//     one of dx = 0 the byte-aligned dwords in between.
+// Against k_wgrad_brick: a third of the LDS stores and about half the LDS
+// reads per brick.
+constexpr int kHaloRow = 24;
+constexpr int kHaloChan = 24 * kHaloRow + 8;
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+template <int RS>
+__global__ void __launch_bounds__(192) k_wgrad_brick3(WgradArgs a, int64_t bricks_per_block) {
+    static_assert(RS == 1 || RS == 2, "96 halo loaders + 32 RS output-gradient loaders");
+    __shared__ __attribute__((aligned(16))) __bf16 xs[16 * kHaloChan];
+    __shared__ __attribute__((aligned(16))) __bf16 dT[RS * 16][136];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r = lane & 15, q = lane >> 4;
+    const int lg = a.lg, G = 1 << lg;
+    const int c0 = blockIdx.x * 16;
+    const int nbx = G >> 4, nby = G >> 2, nbz = G >> 1;
+    const int64_t nbricks = (int64_t)a.n * nbz * nby * nbx;
+    const int64_t b0 = (int64_t)blockIdx.y * bricks_per_block;
+    const int64_t b1 = b0 + bricks_per_block < nbricks ? b0 + bricks_per_block : nbricks;
+    floatx4 acc[3][3][RS];  // [dy + 1][dx + 1][row tile]
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int m = 0; m < RS; ++m) acc[i][j][m] = floatx4{0.f, 0.f, 0.f, 0.f};
+    floatx4 accb[RS];
+#pragma unroll
+    for (int m = 0; m < RS; ++m) accb[m] = floatx4{0.f, 0.f, 0.f, 0.f};
+    const bool bias_wave = blockIdx.x == 0 && wave == 0;
+    // Roles: threads 0-95 load the halo: row hr (hz = hr / 6, hy = hr % 6),
+    // channel group cgx, cells 0-7 (hx = 0) or 8-17 (hx = 1); consecutive
+    // lanes take consecutive rows, so each 8-lane LDS store cycle hits 8
+    // distinct bank groups.  The next 32 * RS threads load the output
+    // gradient (8 cells x 8 channels).  The global loads of brick b + 1 go
+    // into registers before the matrix-core phase of brick b.
+    const int hx = tid / 48, cgx = (tid % 48) / 24, hr = tid % 24;
+    const int td = tid - 96, vgd = td & 15, cgd = td >> 4, sd = vgd >> 2;
+    bf16x8 reg[8], ext0, ext1;  // ext: cells 16, 17 of the halo row (hx = 1)
+    auto fetch = [&](int64_t b) __attribute__((always_inline)) {
+        const int x0 = (int)(b % nbx) * 16;
+        int64_t rest = b / nbx;
+        const int y0 = (int)(rest % nby) * 4;
+        rest /= nby;
+        const int z0 = (int)(rest % nbz) * 2;
+        const int smp = (int)(rest / nbz);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+#pragma unroll
+            for (int m = 0; m < 8; ++m) reg[m][e] = (__bf16)0.f;
+            ext0[e] = ext1[e] = (__bf16)0.f;
+        }
+        if (tid < 96) {
+            const int yy = y0 + hr % 6 - 1, zz = z0 + hr / 6 - 1, cc = c0 + cgx * 8;
+            const bool row_ok = cc < a.cin && (unsigned)yy < (unsigned)G && (unsigned)zz < (unsigned)G;
+            auto cell = [&](int xx) __attribute__((always_inline)) {
+                bf16x8 v;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) v[e] = (__bf16)0.f;
+                if (row_ok && (unsigned)xx < (unsigned)G) {
+                    if (cc < a.c1s) {
+                        const int64_t vi = ((((int64_t)smp << lg) + zz) << (2 * lg)) +
+                                           ((int64_t)yy << lg) + xx;
+                        v = *(const bf16x8*)(a.x1 + vi * a.c1s + cc);
+                    } else {
+                        const int h = lg - 1;
+                        const int64_t vi = ((((int64_t)smp << h) + (zz >> 1)) << (2 * h)) +
+                                           ((int64_t)(yy >> 1) << h) + (xx >> 1);
+                        v = *(const bf16x8*)(a.x2 + vi * a.c2 + (cc - a.c1s));
+                    }
+                }
+                return v;
+            };
+            const int xb = x0 - 1 + 8 * hx;
+#pragma unroll
+            for (int m = 0; m < 8; ++m) reg[m] = cell(xb + m);
+            if (hx) {
+                ext0 = cell(xb + 8);
+                ext1 = cell(xb + 9);
+            }
+        } else if (tid < 96 + 32 * RS) {
+            const int yy = y0 + (sd & 1) * 2 + ((vgd & 3) >> 1), zz = z0 + (sd >> 1);
+            const int xb = x0 + (vgd & 1) * 8;
+            const int64_t v0 = ((((int64_t)smp << lg) + zz) << (2 * lg)) + ((int64_t)yy << lg) + xb;
+            if (cgd * 8 < a.ys) {
+#pragma unroll
+                for (int m = 0; m < 8; ++m) reg[m] = *(const bf16x8*)(a.dy + (v0 + m) * a.ys + cgd * 8);
+            }
+        }
+    };
+    if (b0 < b1) fetch(b0);
+    for (int64_t b = b0; b < b1; ++b) {
+        if (tid < 96) {
+            __bf16* row = &xs[(cgx * 8) * kHaloChan + hr * kHaloRow + 8 * hx];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                bf16x8 w;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) w[j] = reg[j][e];
+                *(bf16x8*)&row[e * kHaloChan] = w;
+                if (hx) {
+                    bf16x2 t2;
+                    t2[0] = ext0[e];
+                    t2[1] = ext1[e];
+                    *(bf16x2*)&row[e * kHaloChan + 8] = t2;
+                }
+            }
+        } else if (tid < 96 + 32 * RS) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                bf16x8 w;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) w[j] = reg[j][e];
+                *(bf16x8*)&dT[cgd * 8 + e][vgd * 8] = w;
+            }
+        }
+        __syncthreads();
+        if (b + 1 < b1) fetch(b + 1);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            bf16x8 av[RS];
+#pragma unroll
+            for (int m = 0; m < RS; ++m) av[m] = *(const bf16x8*)&dT[m * 16 + r][s * 32 + q * 8];
+            if (bias_wave) {
+#pragma unroll
+                for (int m = 0; m < RS; ++m)
+                    accb[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[m], ones_frag(), accb[m],
+                                                                      0, 0, 0);
+            }
+            // k step s covers plane s >> 1 and rows (s & 1) * 2 + {0, 1} of the
+            // brick; this lane's row is (s & 1) * 2 + (q >> 1), its x half q & 1
+            const int hz = (s >> 1) + wave, hy0 = (s & 1) * 2 + (q >> 1);
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const int base = r * kHaloChan + (hz * 6 + hy0 + i) * kHaloRow + (q & 1) * 8;
+                const u32x4 d = __builtin_bit_cast(u32x4, *(const bf16x8*)&xs[base]);
+                const uint32_t e4 = __builtin_bit_cast(uint32_t, *(const bf16x2*)&xs[base + 8]);
+                const u32x4 mid = {__builtin_amdgcn_alignbyte(d[1], d[0], 2),
+                                   __builtin_amdgcn_alignbyte(d[2], d[1], 2),
+                                   __builtin_amdgcn_alignbyte(d[3], d[2], 2),
+                                   __builtin_amdgcn_alignbyte(e4, d[3], 2)};
+                const u32x4 hi = {d[1], d[2], d[3], e4};
+                const bf16x8 blo = __builtin_bit_cast(bf16x8, d);
+                const bf16x8 bmid = __builtin_bit_cast(bf16x8, mid);
+                const bf16x8 bhi = __builtin_bit_cast(bf16x8, hi);
+#pragma unroll
+                for (int m = 0; m < RS; ++m) {
+                    acc[i][0][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[m], blo, acc[i][0][m], 0, 0, 0);
+                    acc[i][1][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[m], bmid, acc[i][1][m], 0, 0, 0);
+                    acc[i][2][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[m], bhi, acc[i][2][m], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    const int64_t blk = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+    float* pb = a.part + blk * (27 * RS * 16 * 16);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const int t = wave * 9 + i * 3 + j;
+#pragma unroll
+            for (int m = 0; m < RS; ++m)
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    pb[((t * RS + m) * 16 + q * 4 + k) * 16 + r] = acc[i][j][m][k];
+        }
+    if (bias_wave && r == 0) {
+        float* bb = a.part + a.bias_off + (int64_t)blockIdx.y * (RS * 16);
+#pragma unroll
+        for (int m = 0; m < RS; ++m)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) bb[m * 16 + q * 4 + k] = accb[m][k];
+    }
+}
+
 // Sum of the k_wgrad_brick partials over the brick ranges, into dw[co][tap]
 // [ci] (zero padding channels dropped) and db.  One thread per gradient
 // entry of (channel group, tap, co, channel) or per bias entry.
@@ -553,39 +783,45 @@ __global__ void k_wgrad_brick_reduce(WgradArgs a, int chunks, int groups, int rs
     }
 }
 
-__global__ void k_pack_w(int coutp, int kpad, int cout, int K, int cin, int c1, int c1s, int taps,
-                         int cin_real, const float* __restrict__ w, __bf16* __restrict__ wp) {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (int64_t)coutp * kpad) return;
-    const int co = (int)(idx / kpad), k = (int)(idx - (int64_t)co * kpad);
-    float val = 0.f;
-    if (co < cout && k < K) {
-        const int t = k / cin, cc = k - t * cin;
-        if (cc < c1s) {
-            if (cc < c1) val = w[((int64_t)co * taps + t) * cin_real + cc];
-        } else {
-            val = w[((int64_t)co * taps + t) * cin_real + c1 + (cc - c1s)];
-        }
-    }
-    wp[idx] = (__bf16)val;
+// Packed weight element idx of wp[coutp][kpad] (k = tap * cin + stored
+// channel; zero padding channels and k >= K hold 0).
+__device__ __forceinline__ float pack_w_elem(const PackLayer& L, int64_t idx,
+                                             const float* __restrict__ w) {
+    const int co = (int)(idx / L.kpad), k = (int)(idx - (int64_t)co * L.kpad);
+    if (co >= L.cout || k >= L.K) return 0.f;
+    const int t = k / L.cin, cc = k - t * L.cin;
+    if (cc < L.c1s) return cc < L.c1 ? w[((int64_t)co * L.taps + t) * L.cin_real + cc] : 0.f;
+    return w[((int64_t)co * L.taps + t) * L.cin_real + L.c1 + (cc - L.c1s)];
 }
 
-__global__ void k_pack_wt(int cinp, int kpad_t, int cin, int ys, int cout, int c1, int c1s,
-                          int taps, int cin_real, const float* __restrict__ w,
-                          __bf16* __restrict__ wt) {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (int64_t)cinp * kpad_t) return;
-    const int ci = (int)(idx / kpad_t), k = (int)(idx - (int64_t)ci * kpad_t);
-    float val = 0.f;
-    if (ci < cin && k < taps * ys) {
-        const int t = k / ys, co = k - t * ys;
-        const bool real = ci >= c1s || ci < c1;
-        if (co < cout && real) {
-            const int cir = ci < c1s ? ci : c1 + (ci - c1s);
-            val = w[((int64_t)co * taps + (taps - 1 - t)) * cin_real + cir];
-        }
+// Transposed, tap-flipped element idx of wt[cinp][kpad_t] (k = tap * ys + co).
+__device__ __forceinline__ float pack_wt_elem(const PackLayer& L, int64_t idx,
+                                              const float* __restrict__ w) {
+    const int ci = (int)(idx / L.kpad_t), k = (int)(idx - (int64_t)ci * L.kpad_t);
+    if (ci >= L.cin || k >= L.taps * L.ys) return 0.f;
+    const int t = k / L.ys, co = k - t * L.ys;
+    const bool real = ci >= L.c1s || ci < L.c1;
+    if (co >= L.cout || !real) return 0.f;
+    const int cir = ci < L.c1s ? ci : L.c1 + (ci - L.c1s);
+    return w[((int64_t)co * L.taps + (L.taps - 1 - t)) * L.cin_real + cir];
+}
+
+// Every layer's packed and transposed weights in one launch.  Segment 2l is
+// layer l's wp, segment 2l + 1 its wt; each block serves one segment (the
+// first whose cumulative block count exceeds blockIdx.x), so the table is
+// read with block-uniform indices.
+__global__ void __launch_bounds__(256) k_pack_all(PackTable t, const float* __restrict__ theta) {
+    int seg = 0;
+    while ((int64_t)blockIdx.x >= t.blk[seg]) ++seg;
+    const int64_t first = seg ? t.blk[seg - 1] : 0;
+    const int64_t i = ((int64_t)blockIdx.x - first) * 256 + threadIdx.x;
+    const PackLayer& L = t.l[seg >> 1];
+    const float* w = theta + L.woff;
+    if (seg & 1) {
+        if (i < (int64_t)L.cinp * L.kpad_t) L.wt[i] = (__bf16)pack_wt_elem(L, i, w);
+    } else {
+        if (i < (int64_t)L.coutp * L.kpad) L.wp[i] = (__bf16)pack_w_elem(L, i, w);
     }
-    wt[idx] = (__bf16)val;
 }
 
 __device__ __forceinline__ int64_t fine_index(int s, int z, int y, int x, int lg) {
@@ -703,39 +939,140 @@ __global__ void k_inputs(int n, int lg, SampleFloats lra, __bf16* __restrict__ x
     *(bf16x8*)(x + v * 8) = o;
 }
 
-__global__ void __launch_bounds__(256) k_mse(int n, int lg, const float* __restrict__ out,
-                                             const float* __restrict__ tg, SampleInts idx,
-                                             int64_t stride,
-                                             float4 ts, __bf16* __restrict__ dy,
-                                             double* __restrict__ partial) {
-    __shared__ double red[256];
+// The 1 x 1 x 1 head on the vector units (it reads 32 bytes and writes 16
+// per voxel, far too little work for the matrix cores): kHeadIn BF16
+// channels-last inputs -> kHeadOut FP32 outputs, channel-first, with the
+// FP32 master weights w[co][ci] and bias b[co].  One thread per voxel.
+constexpr int kHeadIn = 16, kHeadOut = 4, kHeadGrad = kHeadOut * kHeadIn + kHeadOut;
+
+__device__ __forceinline__ void load_head_input(const __bf16* __restrict__ x, int64_t v,
+                                                float* xf) {
+    const bf16x8 lo = *(const bf16x8*)(x + v * kHeadIn);
+    const bf16x8 hi = *(const bf16x8*)(x + v * kHeadIn + 8);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        xf[i] = (float)lo[i];
+        xf[8 + i] = (float)hi[i];
+    }
+}
+
+__global__ void __launch_bounds__(256) k_head_forward(int n, int lg, const __bf16* __restrict__ x,
+                                                      const float* __restrict__ w,
+                                                      const float* __restrict__ b, float4 sc,
+                                                      float* __restrict__ out) {
     const int64_t V = (int64_t)1 << (3 * lg);
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const double inv = 2.0 / ((double)n * 4.0 * (double)V);
-    double acc = 0.0;
-    if (v < (int64_t)n * V) {
+    if (v >= (int64_t)n * V) return;
+    const int64_t s = v >> (3 * lg), vin = v & (V - 1);
+    float xf[kHeadIn];
+    load_head_input(x, v, xf);
+    const float scale[kHeadOut] = {sc.x, sc.y, sc.z, sc.w};
+#pragma unroll
+    for (int c = 0; c < kHeadOut; ++c) {
+        float acc = b[c];
+#pragma unroll
+        for (int i = 0; i < kHeadIn; ++i) acc = fmaf(w[c * kHeadIn + i], xf[i], acc);
+        out[(s * kHeadOut + c) * V + vin] = acc * scale[c];
+    }
+}
+
+// Loss and the whole backward step of the head in one pass: per voxel the
+// output gradient d = 2 (out - t) / count (t = target times its scale), the
+// input gradient dx[ci] = sum_co w[co][ci] d[co] (0 where the ReLU output x
+// <= 0; written as BF16), and the contributions d[co] x[ci] and d[co] to the
+// weight and bias gradients.  Block b takes voxels [b chunk, (b + 1) chunk);
+// its sums (squared error in FP64, the kHeadGrad gradient entries in FP32)
+// are added over the block in a fixed order and written to lpart[b] and
+// gpart[b][kHeadGrad].
+__global__ void __launch_bounds__(256) k_head_backward(
+    int n, int lg, const float* __restrict__ out, const float* __restrict__ tg, SampleInts idx,
+    int64_t stride, float4 ts, const __bf16* __restrict__ x, const float* __restrict__ w,
+    int64_t chunk, __bf16* __restrict__ dx, double* __restrict__ lpart,
+    float* __restrict__ gpart) {
+    __shared__ float gred[4][kHeadGrad];
+    __shared__ double lred[256];
+    const int64_t V = (int64_t)1 << (3 * lg);
+    const int64_t M = (int64_t)n * V;
+    const float inv = (float)(2.0 / ((double)n * 4.0 * (double)V));
+    const float tsc[kHeadOut] = {ts.x, ts.y, ts.z, ts.w};
+    float g[kHeadGrad];
+#pragma unroll
+    for (int j = 0; j < kHeadGrad; ++j) g[j] = 0.f;
+    double lsum = 0.0;
+    const int64_t v0 = (int64_t)blockIdx.x * chunk;
+    const int64_t v1 = v0 + chunk < M ? v0 + chunk : M;
+    for (int64_t v = v0 + threadIdx.x; v < v1; v += blockDim.x) {
         const int s = (int)(v >> (3 * lg));
         const int64_t vin = v & (V - 1);
-        const float tsc[4] = {ts.x, ts.y, ts.z, ts.w};
-        bf16x8 o;
+        float d[kHeadOut];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const float ov = out[((int64_t)s * 4 + c) * V + vin];
+        for (int c = 0; c < kHeadOut; ++c) {
+            const float ov = out[((int64_t)s * kHeadOut + c) * V + vin];
             const float tv = tg[(int64_t)idx.v[s] * stride + c * V + vin] * tsc[c];
-            const double d = (double)ov - (double)tv;
-            acc += d * d;
-            o[c] = (__bf16)(float)(d * inv);
+            const double e = (double)ov - (double)tv;
+            lsum += e * e;
+            d[c] = (float)e * inv;
         }
-        o[4] = o[5] = o[6] = o[7] = (__bf16)0.f;
-        *(bf16x8*)(dy + v * 8) = o;
+        float xf[kHeadIn];
+        load_head_input(x, v, xf);
+        bf16x8 lo, hi;
+#pragma unroll
+        for (int i = 0; i < kHeadIn; ++i) {
+            float acc = 0.f;
+#pragma unroll
+            for (int c = 0; c < kHeadOut; ++c) acc = fmaf(w[c * kHeadIn + i], d[c], acc);
+            const __bf16 r = (__bf16)(xf[i] > 0.f ? acc : 0.f);
+            if (i < 8)
+                lo[i] = r;
+            else
+                hi[i - 8] = r;
+        }
+        *(bf16x8*)(dx + v * kHeadIn) = lo;
+        *(bf16x8*)(dx + v * kHeadIn + 8) = hi;
+#pragma unroll
+        for (int c = 0; c < kHeadOut; ++c) {
+#pragma unroll
+            for (int i = 0; i < kHeadIn; ++i) g[c * kHeadIn + i] = fmaf(d[c], xf[i], g[c * kHeadIn + i]);
+            g[kHeadOut * kHeadIn + c] += d[c];
+        }
     }
-    red[threadIdx.x] = acc;
+    // the wave's 64 lanes by an xor butterfly, then the 4 waves in order
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < kHeadGrad; ++j) {
+        float val = g[j];
+#pragma unroll
+        for (int m = 32; m > 0; m >>= 1) val += __shfl_xor(val, m, 64);
+        if (lane == 0) gred[wave][j] = val;
+    }
+    lred[threadIdx.x] = lsum;
     __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    for (int m = 128; m > 0; m >>= 1) {
+        if ((int)threadIdx.x < m) lred[threadIdx.x] += lred[threadIdx.x + m];
         __syncthreads();
     }
-    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+    if (threadIdx.x < kHeadGrad)
+        gpart[(int64_t)blockIdx.x * kHeadGrad + threadIdx.x] =
+            ((gred[0][threadIdx.x] + gred[1][threadIdx.x]) + gred[2][threadIdx.x]) +
+            gred[3][threadIdx.x];
+    if (threadIdx.x == 0) lpart[blockIdx.x] = lred[0];
+}
+
+// out[j] = sum over rows r of in[r][j] (rows x width), one block per column:
+// thread t adds rows t, t + 256, ... in order, then a fixed tree.
+__global__ void __launch_bounds__(256) k_column_sums(const float* __restrict__ in, int rows,
+                                                     int width, float* __restrict__ out) {
+    __shared__ float red[256];
+    const int j = blockIdx.x;
+    float acc = 0.f;
+    for (int r = threadIdx.x; r < rows; r += 256) acc += in[(int64_t)r * width + j];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int m = 128; m > 0; m >>= 1) {
+        if ((int)threadIdx.x < m) red[threadIdx.x] += red[threadIdx.x + m];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[j] = red[0];
 }
 
 __global__ void __launch_bounds__(1024) k_reduce(const double* __restrict__ p, int n,
@@ -900,24 +1237,24 @@ __global__ void __launch_bounds__(64 * kCvPlanes) k_conv_brick(ConvArgs a) {
                         if (a.relu) val = fmaxf(val, 0.f);
                         if (a.omask && !((float)a.omask[vo * a.ys + co] > 0.f)) val = 0.f;
                     }
-                    ((__bf16*)a.out)[vo * a.ys + co] = (__bf16)val;
+                    a.out[vo * a.ys + co] = (__bf16)val;
                 }
             }
         }
     }
 }
 
-template <int MODE, int MT, int KS>
+template <int MT, int KS>
 hipError_t launch_conv_mt(const ConvArgs& a, int coutp, hipStream_t s) {
     const int64_t M = (int64_t)a.n << (3 * a.lg);
     const int sub = coutp / 16;
     const int nsub = sub % 4 == 0 ? 4 : sub % 3 == 0 ? 3 : sub % 2 == 0 ? 2 : 1;
     const dim3 grid(ceil_div(M, 16 * MT), sub / nsub), block(64 * KS);
     switch (nsub) {
-        case 4: hipLaunchKernelGGL((k_conv<4, MODE, MT, KS>), grid, block, 0, s, a); break;
-        case 3: hipLaunchKernelGGL((k_conv<3, MODE, MT, KS>), grid, block, 0, s, a); break;
-        case 2: hipLaunchKernelGGL((k_conv<2, MODE, MT, KS>), grid, block, 0, s, a); break;
-        default: hipLaunchKernelGGL((k_conv<1, MODE, MT, KS>), grid, block, 0, s, a); break;
+        case 4: hipLaunchKernelGGL((k_conv<4, MT, KS>), grid, block, 0, s, a); break;
+        case 3: hipLaunchKernelGGL((k_conv<3, MT, KS>), grid, block, 0, s, a); break;
+        case 2: hipLaunchKernelGGL((k_conv<2, MT, KS>), grid, block, 0, s, a); break;
+        default: hipLaunchKernelGGL((k_conv<1, MT, KS>), grid, block, 0, s, a); break;
     }
     return hipGetLastError();
 }
@@ -926,13 +1263,11 @@ hipError_t launch_conv_mt(const ConvArgs& a, int coutp, hipStream_t s) {
 // each weight fragment serves 64 voxels).  Otherwise one tile, and the k
 // range is split over 2 or 4 waves per block when there are fewer than
 // 4096 or 1024 blocks and at least two steps of 32 per wave.
-template <int MODE>
 hipError_t launch_conv(const ConvArgs& a, int coutp, hipStream_t s) {
     const int64_t M = (int64_t)a.n << (3 * a.lg);
     const int sub = coutp / 16;
     const int nsub = sub % 4 == 0 ? 4 : sub % 3 == 0 ? 3 : sub % 2 == 0 ? 2 : 1;
-    if (MODE == 0 && a.taps == 27 && a.lg >= 4 && a.cin % 16 == 0 && !a.mask &&
-        a.kpad >= 27 * a.cin) {
+    if (a.taps == 27 && a.lg >= 4 && a.cin % 16 == 0 && a.kpad >= 27 * a.cin) {
         // on the 16-cell grid one output-channel group per block, for blocks
         const int64_t G = (int64_t)1 << a.lg;
         const int nb = a.lg >= 5 ? nsub : 1;
@@ -947,12 +1282,12 @@ hipError_t launch_conv(const ConvArgs& a, int coutp, hipStream_t s) {
         return hipGetLastError();
     }
     const int64_t waves4 = (int64_t)ceil_div(M, 64) * (sub / nsub);
-    if (waves4 >= 2048) return launch_conv_mt<MODE, 4, 1>(a, coutp, s);
+    if (waves4 >= 2048) return launch_conv_mt<4, 1>(a, coutp, s);
     const int64_t waves1 = (int64_t)ceil_div(M, 16) * (sub / nsub);
     const int ksteps = a.kpad / 32;
-    if (waves1 < 1024 && ksteps >= 8) return launch_conv_mt<MODE, 1, 4>(a, coutp, s);
-    if (waves1 < 4096 && ksteps >= 4) return launch_conv_mt<MODE, 1, 2>(a, coutp, s);
-    return launch_conv_mt<MODE, 1, 1>(a, coutp, s);
+    if (waves1 < 1024 && ksteps >= 8) return launch_conv_mt<1, 4>(a, coutp, s);
+    if (waves1 < 4096 && ksteps >= 4) return launch_conv_mt<1, 2>(a, coutp, s);
+    return launch_conv_mt<1, 1>(a, coutp, s);
 }
 
 }  // namespace
@@ -976,35 +1311,53 @@ ConvGeom make_geom(int n, int lg, int taps, int c1, int c2, int cout) {
     return g;
 }
 
-hipError_t pack_weights(const ConvGeom& g, const float* w, __bf16* wp, __bf16* wt,
-                        hipStream_t s) {
-    const int cin_real = g.c1 + g.c2;
-    const int64_t n1 = (int64_t)g.coutp * g.kpad;
-    hipLaunchKernelGGL(k_pack_w, dim3(ceil_div(n1, 256)), dim3(256), 0, s, g.coutp, g.kpad, g.cout,
-                       g.K, g.cin, g.c1, g.c1s, g.taps, cin_real, w, wp);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || !wt) return e;
-    const int64_t n2 = (int64_t)g.cinp * g.kpad_t;
-    hipLaunchKernelGGL(k_pack_wt, dim3(ceil_div(n2, 256)), dim3(256), 0, s, g.cinp, g.kpad_t, g.cin,
-                       g.ys, g.cout, g.c1, g.c1s, g.taps, cin_real, w, wt);
+hipError_t pack_weights(int layers, const ConvGeom* g, const float* theta, const int64_t* woff,
+                        __bf16* const* wp, __bf16* const* wt, hipStream_t s) {
+    if (layers < 1 || layers > kMaxPackLayers) return hipErrorInvalidValue;
+    PackTable t;
+    int64_t blocks = 0;
+    for (int l = 0; l < kMaxPackLayers; ++l) {
+        PackLayer& L = t.l[l];
+        if (l >= layers) {
+            L = PackLayer{};
+            t.blk[2 * l] = t.blk[2 * l + 1] = blocks;
+            continue;
+        }
+        L.wp = wp[l];
+        L.wt = wt[l];
+        L.woff = woff[l];
+        L.coutp = g[l].coutp;
+        L.kpad = g[l].kpad;
+        L.cout = g[l].cout;
+        L.K = g[l].K;
+        L.cin = g[l].cin;
+        L.c1 = g[l].c1;
+        L.c1s = g[l].c1s;
+        L.taps = g[l].taps;
+        L.cin_real = g[l].c1 + g[l].c2;
+        L.cinp = g[l].cinp;
+        L.kpad_t = g[l].kpad_t;
+        L.ys = g[l].ys;
+        blocks += ceil_div((int64_t)L.coutp * L.kpad, 256);
+        t.blk[2 * l] = blocks;
+        blocks += ceil_div((int64_t)L.cinp * L.kpad_t, 256);
+        t.blk[2 * l + 1] = blocks;
+    }
+    hipLaunchKernelGGL(k_pack_all, dim3((unsigned)blocks), dim3(256), 0, s, t, theta);
     return hipGetLastError();
 }
 
-hipError_t conv_forward(const ConvGeom& g, const __bf16* x1, const __bf16* x2,
-                        const __bf16* mask, const __bf16* wp, const float* bias, int relu,
-                        int mode, void* out, const float* scale4, hipStream_t s) {
-    if (!x1 || !wp || !out || (g.c2 > 0 && (!x2 || g.lg < 1)) || g.c1s % 8 || g.c2 % 8 ||
-        (mode == 1 && g.cout > 4))
+hipError_t conv_forward(const ConvGeom& g, const __bf16* x1, const __bf16* x2, const __bf16* wp,
+                        const float* bias, int relu, __bf16* out, hipStream_t s) {
+    if (!x1 || !wp || !out || (g.c2 > 0 && (!x2 || g.lg < 1)) || g.c1s % 8 || g.c2 % 8)
         return hipErrorInvalidValue;
     ConvArgs a;
     a.x1 = x1;
     a.x2 = x2;
-    a.mask = mask;
     a.w = wp;
     a.bias = bias;
     a.out = out;
     a.omask = nullptr;
-    for (int i = 0; i < 4; ++i) a.scale[i] = scale4 ? scale4[i] : 1.f;
     a.n = g.n;
     a.lg = g.lg;
     a.taps = g.taps;
@@ -1016,7 +1369,7 @@ hipError_t conv_forward(const ConvGeom& g, const __bf16* x1, const __bf16* x2,
     a.cout = g.cout;
     a.ys = g.ys;
     a.relu = relu;
-    return mode == 0 ? launch_conv<0>(a, g.coutp, s) : launch_conv<1>(a, g.coutp, s);
+    return launch_conv(a, g.coutp, s);
 }
 
 hipError_t conv_backward_data(const ConvGeom& g, const __bf16* dy, const __bf16* wt,
@@ -1025,12 +1378,10 @@ hipError_t conv_backward_data(const ConvGeom& g, const __bf16* dy, const __bf16*
     ConvArgs a;
     a.x1 = dy;
     a.x2 = nullptr;
-    a.mask = nullptr;
     a.w = wt;
     a.bias = nullptr;
     a.out = dx;
     a.omask = dxmask;
-    for (int i = 0; i < 4; ++i) a.scale[i] = 1.f;
     a.n = g.n;
     a.lg = g.lg;
     a.taps = g.taps;
@@ -1042,14 +1393,15 @@ hipError_t conv_backward_data(const ConvGeom& g, const __bf16* dy, const __bf16*
     a.cout = g.cin;
     a.ys = g.cin;
     a.relu = 0;
-    return launch_conv<0>(a, g.cinp, s);
+    return launch_conv(a, g.cinp, s);
 }
 
 namespace {
 
-// Launch plan of the weight gradient: the brick kernel (grids of at least 16
-// cells, 27 taps, >= 16 input channels, 16/32/64 output channels) or the
-// tiled kernel, its grid, and the floats of partial sums it writes.
+// Launch plan of the weight gradient: a brick kernel (grids of at least 16
+// cells, 27 taps, 16/32 output channels with >= 8 input channels, 64 with
+// >= 16) or the tiled kernel, its grid, and the floats of partial sums it
+// writes.
 struct WgradPlan {
     bool brick;
     int rs, cs;
@@ -1060,12 +1412,14 @@ struct WgradPlan {
     int64_t part_floats, bias_off;  // partial sums of every block
     int64_t rows, wwidth, bwidth;   // rows of partials, weight / bias floats per row
     int64_t scratch_floats;         // partials + the first reduction pass
+    bool slices;                    // whether the first reduction pass runs
 };
 
 // Scratch of the first reduction pass, after the partials: the weight rows
 // and the bias rows summed over slices of kRowSlice rows.
 void finish_plan(WgradPlan* p) {
-    const int64_t sl = (p->rows + kRowSlice - 1) / kRowSlice;
+    p->slices = p->rows > 2 * kRowSlice && !(p->wwidth >= 65536 && p->rows <= 128);
+    const int64_t sl = p->slices ? (p->rows + kRowSlice - 1) / kRowSlice : 0;
     p->scratch_floats = p->part_floats + sl * (p->wwidth + p->bwidth);
 }
 
@@ -1079,8 +1433,11 @@ constexpr int64_t kPartBlocks = 1024;
 WgradPlan wgrad_plan(const ConvGeom& g, int relu) {
     WgradPlan p = {};
     const int64_t M = (int64_t)g.n << (3 * g.lg);
-    p.brick = !relu && g.lg >= 4 && g.taps == 27 && g.cin >= 16 &&
-              (g.coutp == 16 || g.coutp == 32 || g.coutp == 64);
+    // (8 input channels, the network's first layer, takes a channel group
+    // of 16 whose upper half loads zeros; only k_wgrad_brick3 is checked for
+    // that, so 64 output channels need 16.)
+    p.brick = !relu && g.lg >= 4 && g.taps == 27 &&
+              ((g.cin >= 8 && (g.coutp == 16 || g.coutp == 32)) || (g.cin >= 16 && g.coutp == 64));
     if (p.brick) {
         p.rs = g.coutp / 16;
         p.chunks = ceil_div(g.cin, 16);
@@ -1120,18 +1477,21 @@ WgradPlan wgrad_plan(const ConvGeom& g, int relu) {
     return p;
 }
 
-// First reduction pass over the partials of plan p; returns the arguments
-// of the second pass (partials replaced by the slice sums, rows by slices).
+// First reduction pass over the partials of plan p, when they have more
+// rows than the second pass reads quickly (many rows, few gradient entries
+// per row: then one thread per entry would leave too few loads in flight).
+// Returns the arguments of the second pass: the partials, or their slice
+// sums with rows replaced by slices.
 hipError_t sum_slices(const WgradPlan& p, const WgradArgs& a, WgradArgs* b, int64_t* rows,
                       hipStream_t s) {
+    *b = a;
+    *rows = p.rows;
+    if (!p.slices) return hipSuccess;
     const int64_t sl = (p.rows + kRowSlice - 1) / kRowSlice;
     float* out = a.part + p.part_floats;
-    hipLaunchKernelGGL(k_sum_row_slices, dim3(ceil_div(sl * p.wwidth, 256)), dim3(256), 0, s,
-                       (const float*)a.part, p.rows, p.wwidth, out);
-    hipLaunchKernelGGL(k_sum_row_slices, dim3(ceil_div(sl * p.bwidth, 256)), dim3(256), 0, s,
-                       (const float*)(a.part + p.bias_off), p.rows, p.bwidth,
-                       out + sl * p.wwidth);
-    *b = a;
+    hipLaunchKernelGGL(k_sum_row_slices, dim3(ceil_div(sl * (p.wwidth + p.bwidth), 256)),
+                       dim3(256), 0, s, (const float*)a.part, p.bias_off, p.rows, p.wwidth,
+                       p.bwidth, out);
     b->part = out;
     b->bias_off = sl * p.wwidth;
     *rows = sl;
@@ -1175,8 +1535,8 @@ hipError_t conv_backward_weight(const ConvGeom& g, const __bf16* x1, const __bf1
         const dim3 grid(p.chunks, p.groups);
         switch (p.rs) {
             case 4: hipLaunchKernelGGL(k_wgrad_brick<4>, grid, dim3(256), 0, s, a, p.per); break;
-            case 2: hipLaunchKernelGGL(k_wgrad_brick<2>, grid, dim3(256), 0, s, a, p.per); break;
-            default: hipLaunchKernelGGL(k_wgrad_brick<1>, grid, dim3(256), 0, s, a, p.per); break;
+            case 2: hipLaunchKernelGGL(k_wgrad_brick3<2>, grid, dim3(192), 0, s, a, p.per); break;
+            default: hipLaunchKernelGGL(k_wgrad_brick3<1>, grid, dim3(192), 0, s, a, p.per); break;
         }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -1242,25 +1602,57 @@ hipError_t make_inputs(int n, int lg, const float* log10_ra, __bf16* x, hipStrea
     return hipGetLastError();
 }
 
-hipError_t mse_forward_backward(int n, int lg, const float* out, const float* targets,
-                                const int32_t* idx, int64_t stride, const float* tscale4,
-                                __bf16* dy, double* partial, int* nblocks, hipStream_t s) {
-    if (n < 1 || n > kMaxBatch || !out || !targets || !idx || !dy || !partial)
-        return hipErrorInvalidValue;
-    SampleInts ix;
-    for (int i = 0; i < kMaxBatch; ++i) ix.v[i] = i < n ? idx[i] : 0;
-    const int64_t t = (int64_t)n << (3 * lg);
-    const int nb = ceil_div(t, 256);
-    *nblocks = nb;
-    const float4 ts = make_float4(tscale4[0], tscale4[1], tscale4[2], tscale4[3]);
-    hipLaunchKernelGGL(k_mse, dim3(nb), dim3(256), 0, s, n, lg, out, targets, ix, stride, ts, dy,
-                       partial);
-    return hipGetLastError();
-}
-
 hipError_t reduce_sum(const double* partial, int n, double* out, hipStream_t s) {
     hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, s, partial, n, out);
     return hipGetLastError();
+}
+
+bool head_geometry(const ConvGeom& g) {
+    return g.taps == 1 && g.c1 == kHeadIn && g.c1s == kHeadIn && g.c2 == 0 && g.cout == kHeadOut;
+}
+
+hipError_t head_forward(const ConvGeom& g, const __bf16* x, const float* w, const float* b,
+                        const float* scale4, float* out, hipStream_t s) {
+    if (!head_geometry(g) || !x || !w || !b || !out) return hipErrorInvalidValue;
+    const float4 sc = scale4 ? make_float4(scale4[0], scale4[1], scale4[2], scale4[3])
+                             : make_float4(1.f, 1.f, 1.f, 1.f);
+    const int64_t M = (int64_t)g.n << (3 * g.lg);
+    hipLaunchKernelGGL(k_head_forward, dim3(ceil_div(M, 256)), dim3(256), 0, s, g.n, g.lg, x, w, b,
+                       sc, out);
+    return hipGetLastError();
+}
+
+int head_backward_blocks(const ConvGeom& g) {
+    const int64_t M = (int64_t)g.n << (3 * g.lg);
+    return (int)std::min<int64_t>(kHeadBlocks, ceil_div(M, 2048));
+}
+
+int64_t head_scratch_floats(const ConvGeom& g) {
+    return (int64_t)head_backward_blocks(g) * kHeadGrad;
+}
+
+hipError_t head_backward(const ConvGeom& g, const float* out, const float* targets,
+                         const int32_t* idx, int64_t stride, const float* tscale4,
+                         const __bf16* x, const float* w, __bf16* dx, float* grad,
+                         float* scratch, double* lpartial, double* loss, hipStream_t s) {
+    if (!head_geometry(g) || g.n < 1 || g.n > kMaxBatch || !out || !targets || !idx || !x ||
+        !w || !dx || !grad || !scratch || !lpartial || !loss)
+        return hipErrorInvalidValue;
+    SampleInts ix;
+    for (int i = 0; i < kMaxBatch; ++i) ix.v[i] = i < g.n ? idx[i] : 0;
+    const int64_t M = (int64_t)g.n << (3 * g.lg);
+    const int nb = head_backward_blocks(g);
+    const int64_t chunk = (int64_t)ceil_div(M, (int64_t)nb * 256) * 256;
+    const float4 ts = make_float4(tscale4[0], tscale4[1], tscale4[2], tscale4[3]);
+    hipLaunchKernelGGL(k_head_backward, dim3(nb), dim3(256), 0, s, g.n, g.lg, out, targets, ix,
+                       stride, ts, x, w, chunk, dx, lpartial, scratch);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_column_sums, dim3(kHeadGrad), dim3(256), 0, s, (const float*)scratch, nb,
+                       kHeadGrad, grad);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return reduce_sum(lpartial, nb, loss, s);
 }
 
 hipError_t adam_update(int64_t count, float* theta, float* m, float* v, const float* g, int t,

@@ -28,6 +28,7 @@ struct LayerDef {
     int c1, c2, cout, taps, level, relu;
 };
 constexpr int kLayers = 16;
+static_assert(kLayers <= kMaxPackLayers, "one packing launch covers every layer");
 constexpr LayerDef kDefs[kLayers] = {
     {"enc1a", 4, 0, 16, 27, 0, 1},    {"enc1b", 16, 0, 16, 27, 0, 1},
     {"enc2a", 16, 0, 32, 27, 1, 1},   {"enc2b", 32, 0, 32, 27, 1, 1},
@@ -59,10 +60,10 @@ struct Layout {
     size_t theta, m, v, grad;
     size_t wp[kLayers], wt[kLayers];
     size_t act[kLayers];   // outputs (head: FP32 channel-first)
-    size_t dact[kLayers];  // gradients of the outputs (head: dy with 8 channels)
+    size_t dact[kLayers];  // gradients of the pre-activations (none for the head)
     size_t in, pool[3], dpool[3], dcat[3];
     size_t partial, loss;
-    size_t wpart;  // weight-gradient partial sums (the largest layer's)
+    size_t wpart;  // weight-gradient partial sums (the largest layer's, or the head's)
     size_t total;
 };
 
@@ -122,8 +123,9 @@ Layout make_layout(const lbm_nn_config& c) {
         L.wp[l] = take((size_t)g.coutp * g.kpad * 2);
         L.wt[l] = take((size_t)g.cinp * g.kpad_t * 2);
         const size_t cells = (size_t)B << (3 * (lg0 - d.level));
-        L.act[l] = l == kLayers - 1 ? take(cells * 4 * 4) : take(cells * g.ys * 2);
-        L.dact[l] = take(cells * g.ys * 2);
+        const bool head = l == kLayers - 1;
+        L.act[l] = head ? take(cells * 4 * 4) : take(cells * g.ys * 2);
+        L.dact[l] = head ? 0 : take(cells * g.ys * 2);
     }
     const size_t c0 = (size_t)B << (3 * lg0);
     L.in = take(c0 * 8 * 2);
@@ -141,7 +143,8 @@ Layout make_layout(const lbm_nn_config& c) {
     for (int l = 0; l < kLayers; ++l) {
         const LayerDef& d = kDefs[l];
         const ConvGeom g = make_geom(B, lg0 - d.level, d.taps, d.c1, d.c2, d.cout);
-        wpart = std::max(wpart, wgrad_scratch_floats(g));
+        wpart = std::max(wpart, l == kLayers - 1 ? head_scratch_floats(g)
+                                                 : wgrad_scratch_floats(g));
     }
     L.wpart = take((size_t)wpart * 4);
     L.total = o;
@@ -157,13 +160,16 @@ lbm_status hipf(hipError_t e, const char* what) { return lbm::hip_fail(e, what);
     } while (0)
 
 lbm_status pack_all(lbm_nn* nn) {
+    ConvGeom g[kLayers];
+    __bf16* wp[kLayers];
+    __bf16* wt[kLayers];
     for (int l = 0; l < kLayers; ++l) {
-        const ConvGeom g = nn->geom(l, 1);
-        NN_TRY(pack_weights(g, nn->at<float>(nn->lay.theta) + nn->off[l],
-                            nn->at<__bf16>(nn->lay.wp[l]), nn->at<__bf16>(nn->lay.wt[l]),
-                            nn->stream),
-               "pack weights");
+        g[l] = nn->geom(l, 1);
+        wp[l] = nn->at<__bf16>(nn->lay.wp[l]);
+        wt[l] = nn->at<__bf16>(nn->lay.wt[l]);
     }
+    NN_TRY(pack_weights(kLayers, g, nn->at<float>(nn->lay.theta), nn->off, wp, wt, nn->stream),
+           "pack weights");
     return LBM_OK;
 }
 
@@ -198,9 +204,14 @@ lbm_status forward(lbm_nn* nn, int n, const float* log10_ra) {
         const ConvGeom g = nn->geom(l, n);
         const __bf16 *x1, *x2;
         layer_inputs(nn, l, &x1, &x2);
-        const bool head = l == kLayers - 1;
-        NN_TRY(conv_forward(g, x1, x2, nullptr, nn->at<__bf16>(L.wp[l]), bias_of(nn, l),
-                            kDefs[l].relu, head ? 1 : 0, nn->ws + L.act[l], nullptr, s),
+        if (l == kLayers - 1) {
+            NN_TRY(head_forward(g, x1, nn->at<float>(L.theta) + nn->off[l], bias_of(nn, l),
+                                nullptr, nn->at<float>(L.act[l]), s),
+                   "head forward");
+            break;
+        }
+        NN_TRY(conv_forward(g, x1, x2, nn->at<__bf16>(L.wp[l]), bias_of(nn, l), kDefs[l].relu,
+                            nn->at<__bf16>(L.act[l]), s),
                "conv forward");
         if (l == 1 || l == 3 || l == 5) {
             const int i = (l - 1) / 2;
@@ -213,18 +224,18 @@ lbm_status forward(lbm_nn* nn, int n, const float* log10_ra) {
     return LBM_OK;
 }
 
-// Backward pass from the output gradient in dact[head]: gradients of every
-// parameter into grad (zeroed first).  Each dact[l] holds the gradient of
-// layer l's pre-activation: the kernel that writes it applies the ReLU mask
-// of act[l] once, so the convolutions read it unmasked.
+// Backward pass below the head, from the gradient in dact[head - 1] that
+// the head's backward step wrote: gradients of the parameters of layers
+// head - 1 .. 0 into grad.  Each dact[l] holds the gradient of layer l's
+// pre-activation: the kernel that writes it applies the ReLU mask of act[l]
+// once, so the convolutions read it unmasked.
 lbm_status backward(lbm_nn* nn, int n) {
     const Layout& L = nn->lay;
     hipStream_t s = nn->stream;
     float* grad = nn->at<float>(L.grad);
-    NN_TRY(fill_zero_f32(grad, nn->P, s), "zero grad");
     auto act = [&](int i) { return nn->at<__bf16>(L.act[i]); };
     auto dact = [&](int i) { return nn->at<__bf16>(L.dact[i]); };
-    for (int l = kLayers - 1; l >= 0; --l) {
+    for (int l = kLayers - 2; l >= 0; --l) {
         const LayerDef& d = kDefs[l];
         const ConvGeom g = nn->geom(l, n);
         const __bf16 *x1, *x2;
@@ -279,13 +290,15 @@ lbm_status loss_and_backward(lbm_nn* nn, int n, const float* log10_ra, const flo
     const Layout& L = nn->lay;
     lbm_status st = forward(nn, n, log10_ra);
     if (st != LBM_OK) return st;
-    int nb = 0;
-    NN_TRY(mse_forward_backward(n, nn->lg0, nn->at<float>(L.act[kLayers - 1]), targets, idx,
-                                stride, nn->cfg.target_scale, nn->at<__bf16>(L.dact[kLayers - 1]),
-                                nn->at<double>(L.partial), &nb, nn->stream),
-           "loss");
-    NN_TRY(reduce_sum(nn->at<double>(L.partial), nb, nn->at<double>(L.loss), nn->stream),
-           "loss sum");
+    const int h = kLayers - 1;
+    float* grad = nn->at<float>(L.grad);
+    NN_TRY(fill_zero_f32(grad, nn->P, nn->stream), "zero grad");
+    NN_TRY(head_backward(nn->geom(h, n), nn->at<float>(L.act[h]), targets, idx, stride,
+                         nn->cfg.target_scale, nn->at<__bf16>(L.act[h - 1]),
+                         nn->at<float>(L.theta) + nn->off[h], nn->at<__bf16>(L.dact[h - 1]),
+                         grad + nn->off[h], nn->at<float>(L.wpart), nn->at<double>(L.partial),
+                         nn->at<double>(L.loss), nn->stream),
+           "loss and head backward");
     return backward(nn, n);
 }
 
@@ -402,15 +415,12 @@ lbm_status lbm_nn_forward(lbm_nn* nn, int32_t n, const float* log10_ra, float* o
     lbm_status st = check_call(nn, n, log10_ra);
     if (st != LBM_OK) return st;
     if (!out) return lbm::fail(LBM_ERR_ARG, "null output");
-    const float one[4] = {1.f, 1.f, 1.f, 1.f};
     st = forward(nn, n, log10_ra);
     if (st != LBM_OK) return st;
     // the head once more, into the caller's buffer with the scale
-    const ConvGeom g = nn->geom(kLayers - 1, n);
-    const __bf16 *x1, *x2;
-    layer_inputs(nn, kLayers - 1, &x1, &x2);
-    NN_TRY(conv_forward(g, x1, nullptr, nullptr, nn->at<__bf16>(nn->lay.wp[kLayers - 1]),
-                        bias_of(nn, kLayers - 1), 0, 1, out, out_scale ? out_scale : one,
+    const int h = kLayers - 1;
+    NN_TRY(head_forward(nn->geom(h, n), nn->at<__bf16>(nn->lay.act[h - 1]),
+                        nn->at<float>(nn->lay.theta) + nn->off[h], bias_of(nn, h), out_scale, out,
                         nn->stream),
            "head");
     return LBM_OK;

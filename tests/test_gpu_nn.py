@@ -120,7 +120,7 @@ def test_each_layer_at_the_production_shape(net_mod, N):
     variant of the forward pass at its production size -- the brick kernel
     with one output group on 64^3 (16 and 48 input channels), two groups on
     32^3, the 16^3 brick grid, the four-tile kernel of the 4-channel input
-    layer and of the head, the split-k kernel on 8^3 -- checked per layer on
+    layer, the split-k kernel on 8^3, the head on the vector units -- checked per layer on
     the GPU's own inputs at sampled voxels (every sample's corners, edge and
     face centres and 200 random voxels), which the oracle sums directly.
     Same per-element bar as the small grids: 2^-8 |ref| + 1e-4 sum|terms|."""
