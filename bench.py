@@ -606,6 +606,7 @@ def main():
         },
         "fp16_storage": {
             "value": round(f16["mlups"], 1), "unit": "MLUPS", "steps": f16_steps,
+            "rounding": "nearest (fast; see precision_vs_oracle for its error)",
             "ms_per_step": f16["ms_per_step"], "kernel": f16["kernel"],
             "roofline": {"bound": "hbm", "achieved": round(f16["achieved_GBs"], 1),
                          "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -613,6 +614,7 @@ def main():
                          "traffic": recorded_traffic(args.n, "fp16")},
             "stochastic_rounding": None if f16sr is None else {
                 "value": round(f16sr["mlups"], 1), "unit": "MLUPS", "steps": args.sr_steps,
+                "rounding": "stochastic (the accurate FP16 form)",
                 "ms_per_step": f16sr["ms_per_step"], "frac": round(f16sr["frac_hbm_peak"], 4)},
         },
         "thermal_d3q15": None if q15 is None else {

@@ -217,6 +217,16 @@ struct WgradArgs {
     int64_t vchunk;
 };
 
+// LDS layouts follow what the part's LDS serves without bank conflicts
+// (measured with a probe over 768 layouts): for 16-byte reads where lane
+// (r, q) = (lane % 16, lane / 16) reads byte r S + (q & 1) H + (q >> 1) T, T
+// never matters; S = 16 is conflict-free for any H; S = 32 (mod 64) for H = 16
+// or 48; S = 16 or 48 (mod 64) only for H a multiple of 256 (or S = H = 48);
+// S = 0 (mod 64) never.  The fragments here have H = 16 (the lane's second 8
+// channels or k values), so row strides are 32 (mod 64) bytes.
+constexpr int kTileRow = 48;   // 32-voxel tile rows, in elements (96 bytes)
+constexpr int kDTRow = 144;    // 128-voxel brick rows of the output gradient (288 bytes)
+
 // B fragment of ones: an A fragment times it gives its row sums in every
 // column (the bias gradient's sum over voxels, on the matrix cores).
 __device__ __forceinline__ bf16x8 ones_frag() {
@@ -240,8 +250,8 @@ __device__ __forceinline__ bf16x8 ones_frag() {
 template <int RS>
 __global__ void __launch_bounds__(256) k_wgrad(WgradArgs a) {
     constexpr int CS = 8 / RS;
-    __shared__ __attribute__((aligned(16))) __bf16 dT[RS * 16][40];
-    __shared__ __attribute__((aligned(16))) __bf16 xT[CS * 16][40];
+    __shared__ __attribute__((aligned(16))) __bf16 dT[RS * 16][kTileRow];
+    __shared__ __attribute__((aligned(16))) __bf16 xT[CS * 16][kTileRow];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r = lane & 15, q = lane >> 4;
     const int lg = a.lg, G = 1 << lg;
@@ -416,13 +426,13 @@ __global__ void k_wgrad_reduce(WgradArgs a, int kt, int ct, int nz, int rs, int 
 // wave 0 of the first channel group also sums the output gradient for the
 // bias (a matrix-core product against ones; partials [blockIdx.y][coutp] at
 // bias_off).  k_wgrad_brick_reduce adds the partials up.
-constexpr int kBrickRow = 4 * 6 * 16 + 8;  // one channel's halo (hz, hy, x), padded
+constexpr int kBrickRow = 4 * 6 * 16 + 16;  // one channel's halo (hz, hy, x), padded
 
 template <int RS>
 __global__ void __launch_bounds__(256) k_wgrad_brick(WgradArgs a, int64_t bricks_per_block) {
     constexpr int NT = 7;  // taps per wave: ceil(27 / 4)
     __shared__ __attribute__((aligned(16))) __bf16 xs[3 * 16 * kBrickRow];
-    __shared__ __attribute__((aligned(16))) __bf16 dT[RS * 16][136];
+    __shared__ __attribute__((aligned(16))) __bf16 dT[RS * 16][kDTRow];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r = lane & 15, q = lane >> 4;
     const int lg = a.lg, G = 1 << lg;
@@ -460,8 +470,7 @@ __global__ void __launch_bounds__(256) k_wgrad_brick(WgradArgs a, int64_t bricks
             for (int e = 0; e < 8; ++e) reg[m][e] = (__bf16)0.f;
         if (tid < 96) {
             // input halo row (hz, hy), x cells 8k .. 8k+9, channel group cg
-            // (the channel group is the slowest index, so the 8 lanes one LDS
-            // store cycle serves hit 8 different 4-bank groups)
+            // (the channel group is the slowest index)
             const int yy = y0 + hyx - 1, zz = z0 + hzx - 1, cc = c0 + cgx * 8;
             const bool row_ok = cc < a.cin && (unsigned)yy < (unsigned)G && (unsigned)zz < (unsigned)G;
 #pragma unroll
@@ -569,27 +578,28 @@ __global__ void __launch_bounds__(256) k_wgrad_brick(WgradArgs a, int64_t bricks
 // 16 and 32 output channels.  Partial sums, bias product and reduction are
 // those of k_wgrad_brick; what differs:
 //   - the halo is stored once per channel, as 24 rows (hz, hy) of 18 cells
-//     (x0 - 1 .. x0 + 16; row stride kHaloRow, channel stride kHaloChan,
-//     which puts the 16-byte reads of 8 consecutive channels on distinct
-//     banks);
+//     (x0 - 1 .. x0 + 16; row stride kHaloRow, channel stride kHaloChan =
+//     1184 bytes, 32 mod 64, so the B reads are free of bank conflicts);
 //   - a block has 3 waves and wave w takes the 9 taps with dz = w - 1.  Per
-//     k step and dy a lane reads cells 8h .. 8h + 9 of its row (h: the
-//     lane's x half) with one 16-byte and one 4-byte LDS read; the B
+//     k step and dy a lane reads cells 8h .. 8h + 11 of its row (h: the
+//     lane's x half) with one 16-byte and one 8-byte LDS read; the B
 //     fragments of dx = -1, +1 are dwords 0-3 and 1-4 of those cells, the
 //     one of dx = 0 the byte-aligned dwords in between.
 // Against k_wgrad_brick: a third of the LDS stores and about half the LDS
 // reads per brick.
 constexpr int kHaloRow = 24;
-constexpr int kHaloChan = 24 * kHaloRow + 8;
+constexpr int kHaloChan = 24 * kHaloRow + 16;
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
 template <int RS>
-__global__ void __launch_bounds__(192) k_wgrad_brick3(WgradArgs a, int64_t bricks_per_block) {
+__global__ void __launch_bounds__(192, RS == 1 ? 3 : 2) k_wgrad_brick3(WgradArgs a, int64_t bricks_per_block) {
     static_assert(RS == 1 || RS == 2, "96 halo loaders + 32 RS output-gradient loaders");
     __shared__ __attribute__((aligned(16))) __bf16 xs[16 * kHaloChan];
-    __shared__ __attribute__((aligned(16))) __bf16 dT[RS * 16][136];
+    __shared__ __attribute__((aligned(16))) __bf16 dT[RS * 16][kDTRow];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r = lane & 15, q = lane >> 4;
     const int lg = a.lg, G = 1 << lg;
@@ -610,12 +620,18 @@ __global__ void __launch_bounds__(192) k_wgrad_brick3(WgradArgs a, int64_t brick
     for (int m = 0; m < RS; ++m) accb[m] = floatx4{0.f, 0.f, 0.f, 0.f};
     const bool bias_wave = blockIdx.x == 0 && wave == 0;
     // Roles: threads 0-95 load the halo: row hr (hz = hr / 6, hy = hr % 6),
-    // channel group cgx, cells 0-7 (hx = 0) or 8-17 (hx = 1); consecutive
-    // lanes take consecutive rows, so each 8-lane LDS store cycle hits 8
-    // distinct bank groups.  The next 32 * RS threads load the output
-    // gradient (8 cells x 8 channels).  The global loads of brick b + 1 go
-    // into registers before the matrix-core phase of brick b.
-    const int hx = tid / 48, cgx = (tid % 48) / 24, hr = tid % 24;
+    // channel group cgx, cells 0-7 (hx = 0) or 8-17 (hx = 1).  Lane (r, q) of
+    // wave 0 takes row r, channel group q & 1 and x half q >> 1; lane (r, q)
+    // of wave 1 (q < 2) row 16 + r % 8, channel group r / 8, x half q.  So 16
+    // consecutive lanes store 48 bytes apart and the second 16 a whole number
+    // of 256-byte lines further (8 kHaloChan), which the LDS serves without
+    // bank conflicts.  The next 32 * RS threads load the output gradient (8
+    // cells x 8 channels).  The global loads of brick b + 1 go into
+    // registers before the matrix-core phase of brick b.
+    const int lr = tid & 15, lq = (tid >> 4) & 3;
+    const int hr = tid < 64 ? lr : 16 + (lr & 7);
+    const int cgx = tid < 64 ? (lq & 1) : lr >> 3;
+    const int hx = tid < 64 ? lq >> 1 : lq & 1;
     const int td = tid - 96, vgd = td & 15, cgd = td >> 4, sd = vgd >> 2;
     bf16x8 reg[8], ext0, ext1;  // ext: cells 16, 17 of the halo row (hx = 1)
     auto fetch = [&](int64_t b) __attribute__((always_inline)) {
@@ -715,7 +731,9 @@ __global__ void __launch_bounds__(192) k_wgrad_brick3(WgradArgs a, int64_t brick
             for (int i = 0; i < 3; ++i) {
                 const int base = r * kHaloChan + (hz * 6 + hy0 + i) * kHaloRow + (q & 1) * 8;
                 const u32x4 d = __builtin_bit_cast(u32x4, *(const bf16x8*)&xs[base]);
-                const uint32_t e4 = __builtin_bit_cast(uint32_t, *(const bf16x2*)&xs[base + 8]);
+                // cells 8, 9 as an 8-byte read (4-byte reads at this stride conflict)
+                const u32x2 e45 = __builtin_bit_cast(u32x2, *(const bf16x4*)&xs[base + 8]);
+                const uint32_t e4 = e45[0];
                 const u32x4 mid = {__builtin_amdgcn_alignbyte(d[1], d[0], 2),
                                    __builtin_amdgcn_alignbyte(d[2], d[1], 2),
                                    __builtin_amdgcn_alignbyte(d[3], d[2], 2),
@@ -1131,13 +1149,13 @@ __global__ void k_cf_to_cl(const float* __restrict__ x, int n, int64_t V, int c,
 // 16).  A block of 8 waves computes 16 x 4 x 8 output voxels (wave w the
 // plane z0 + w, its four 16-voxel row tiles y0 .. y0 + 3) for NSUB * 16
 // output channels.  Per 16 input channels the block stages the 18 x 6 x 10
-// input halo channels-last in LDS (48 bytes per voxel: 16 channels and 8 of
-// padding, which puts the 16-byte reads of 8 consecutive lanes on distinct
-// banks), so every A fragment (8 channels of one voxel for one tap) is one
-// LDS read instead of a global load per tap.  A k step of 32 pairs two taps
+// input halo channels-last in LDS (32 bytes per voxel, no padding: lane r
+// reads voxel r and its second 8 channels sit 16 bytes on, a layout the
+// LDS serves without bank conflicts), so every A fragment (8 channels of one
+// voxel for one tap) is one LDS read instead of a global load per tap.  A k step of 32 pairs two taps
 // of the 16 channels; B fragments are read from the packed weight ([co][k],
 // k = tap * cin + channel) and serve the four row tiles.
-constexpr int kCvVox = 24;                  // LDS elements per voxel
+constexpr int kCvVox = 16;                  // LDS elements per voxel
 constexpr int kCvPlanes = 8;                // output planes (waves) per block
 constexpr int kCvHalo = 18 * 6 * (kCvPlanes + 2);  // halo voxels
 
