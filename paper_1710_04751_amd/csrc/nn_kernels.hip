@@ -619,70 +619,82 @@ __global__ void __launch_bounds__(192, RS == 1 ? 3 : 2) k_wgrad_brick3(WgradArgs
 #pragma unroll
     for (int m = 0; m < RS; ++m) accb[m] = floatx4{0.f, 0.f, 0.f, 0.f};
     const bool bias_wave = blockIdx.x == 0 && wave == 0;
-    // Roles: threads 0-95 load the halo: row hr (hz = hr / 6, hy = hr % 6),
-    // channel group cgx, cells 0-7 (hx = 0) or 8-17 (hx = 1).  Lane (r, q) of
-    // wave 0 takes row r, channel group q & 1 and x half q >> 1; lane (r, q)
-    // of wave 1 (q < 2) row 16 + r % 8, channel group r / 8, x half q.  So 16
-    // consecutive lanes store 48 bytes apart and the second 16 a whole number
-    // of 256-byte lines further (8 kHaloChan), which the LDS serves without
-    // bank conflicts.  The next 32 * RS threads load the output gradient (8
-    // cells x 8 channels).  The global loads of brick b + 1 go into
-    // registers before the matrix-core phase of brick b.
+    // Roles, one per wave, so that no wave waits on loads issued for
+    // another role into the same registers: threads 0-95 (waves 0 and 1) load
+    // the halo: row hr (hz = hr / 6, hy = hr % 6), channel group cgx, cells 0-7
+    // (hx = 0) or 8-17 (hx = 1).  Lane (r, q) of wave 0 takes row r, channel
+    // group q & 1 and x half q >> 1; lane (r, q) of wave 1 (q < 2) row
+    // 16 + r % 8, channel group r / 8, x half q.  So 16 consecutive lanes
+    // store 48 bytes apart and the second 16 a whole number of 256-byte lines
+    // further (8 kHaloChan), which the LDS serves without bank conflicts.
+    // The first 32 * RS threads of wave 2 load the output gradient (8 cells x
+    // 8 channels).  The global loads of brick b + 1 go into registers before
+    // the matrix-core phase of brick b.
     const int lr = tid & 15, lq = (tid >> 4) & 3;
     const int hr = tid < 64 ? lr : 16 + (lr & 7);
     const int cgx = tid < 64 ? (lq & 1) : lr >> 3;
     const int hx = tid < 64 ? lq >> 1 : lq & 1;
-    const int td = tid - 96, vgd = td & 15, cgd = td >> 4, sd = vgd >> 2;
+    const int td = tid - 128, vgd = td & 15, cgd = td >> 4, sd = vgd >> 2;
+    // The loads go through range-checked buffer resources over one sample of
+    // the channel group's input tensor and of the output gradient: a load at
+    // an offset past the end returns zeros, so a cell outside the grid (or a
+    // channel group past the input channels) needs no branch or select, and
+    // the compiler keeps all of a thread's loads in flight.  The group's
+    // channels lie in one tensor (x1 when c0 < c1s; the plan requires c1s to
+    // be a multiple of 16 when there is an x2).
+    const int h = lg - 1;
+    const bool lo = c0 < a.c1s;
+    const int chans = lo ? a.c1s : a.c2;
+    const int64_t vs = lo ? ((int64_t)1 << (3 * lg)) : ((int64_t)1 << (3 * h));
+    const uint32_t xbytes = (uint32_t)(vs * chans * 2);
+    const uint32_t dbytes = (uint32_t)(((int64_t)1 << (3 * lg)) * a.ys * 2);
+    const int cloc = lo ? c0 : c0 - a.c1s;  // the group's first channel in its tensor
     bf16x8 reg[8], ext0, ext1;  // ext: cells 16, 17 of the halo row (hx = 1)
+    auto ld16 = [](__amdgpu_buffer_rsrc_t rs, uint32_t off) __attribute__((always_inline)) {
+        return __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
+    };
+    // bit 31 for a load that must read zeros: every tensor sample is below
+    // 2^31 bytes, so the offset then lies past the resource's end (arithmetic,
+    // not a select, which the compiler would turn into a branch)
+    auto oob = [](bool ok) __attribute__((always_inline)) { return (uint32_t)!ok << 31; };
     auto fetch = [&](int64_t b) __attribute__((always_inline)) {
-        const int x0 = (int)(b % nbx) * 16;
-        int64_t rest = b / nbx;
-        const int y0 = (int)(rest % nby) * 4;
-        rest /= nby;
-        const int z0 = (int)(rest % nbz) * 2;
-        const int smp = (int)(rest / nbz);
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-#pragma unroll
-            for (int m = 0; m < 8; ++m) reg[m][e] = (__bf16)0.f;
-            ext0[e] = ext1[e] = (__bf16)0.f;
-        }
+        uint32_t bb = (uint32_t)b;
+        const int x0 = (int)(bb % (uint32_t)nbx) * 16;
+        bb /= (uint32_t)nbx;
+        const int y0 = (int)(bb % (uint32_t)nby) * 4;
+        bb /= (uint32_t)nby;
+        const int z0 = (int)(bb % (uint32_t)nbz) * 2;
+        const int smp = (int)(bb / (uint32_t)nbz);
         if (tid < 96) {
-            const int yy = y0 + hr % 6 - 1, zz = z0 + hr / 6 - 1, cc = c0 + cgx * 8;
-            const bool row_ok = cc < a.cin && (unsigned)yy < (unsigned)G && (unsigned)zz < (unsigned)G;
+            const __bf16* xt = (lo ? a.x1 : a.x2) + (int64_t)smp * vs * chans;
+            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                const_cast<__bf16*>(xt), (short)0, (int)xbytes, 0x00020000);
+            const int yy = y0 + hr % 6 - 1, zz = z0 + hr / 6 - 1, cc = cloc + cgx * 8;
+            const bool row_ok = c0 + cgx * 8 < a.cin && (unsigned)yy < (unsigned)G &&
+                                (unsigned)zz < (unsigned)G;
+            const uint32_t rowv = lo ? ((uint32_t)zz << (2 * lg)) + ((uint32_t)yy << lg)
+                                     : ((uint32_t)(zz >> 1) << (2 * h)) + ((uint32_t)(yy >> 1) << h);
             auto cell = [&](int xx) __attribute__((always_inline)) {
-                bf16x8 v;
-#pragma unroll
-                for (int e = 0; e < 8; ++e) v[e] = (__bf16)0.f;
-                if (row_ok && (unsigned)xx < (unsigned)G) {
-                    if (cc < a.c1s) {
-                        const int64_t vi = ((((int64_t)smp << lg) + zz) << (2 * lg)) +
-                                           ((int64_t)yy << lg) + xx;
-                        v = *(const bf16x8*)(a.x1 + vi * a.c1s + cc);
-                    } else {
-                        const int h = lg - 1;
-                        const int64_t vi = ((((int64_t)smp << h) + (zz >> 1)) << (2 * h)) +
-                                           ((int64_t)(yy >> 1) << h) + (xx >> 1);
-                        v = *(const bf16x8*)(a.x2 + vi * a.c2 + (cc - a.c1s));
-                    }
-                }
-                return v;
+                const bool ok = row_ok && (unsigned)xx < (unsigned)G;
+                const uint32_t vox = rowv + (uint32_t)(lo ? xx : xx >> 1);
+                return ld16(rs, ((vox * (uint32_t)chans + (uint32_t)cc) * 2u) | oob(ok));
             };
             const int xb = x0 - 1 + 8 * hx;
 #pragma unroll
             for (int m = 0; m < 8; ++m) reg[m] = cell(xb + m);
-            if (hx) {
-                ext0 = cell(xb + 8);
-                ext1 = cell(xb + 9);
-            }
-        } else if (tid < 96 + 32 * RS) {
+            ext0 = cell(xb + 8);  // used by the threads with hx = 1
+            ext1 = cell(xb + 9);
+        } else if (tid >= 128 && tid < 128 + 32 * RS) {
+            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                const_cast<__bf16*>(a.dy + ((int64_t)smp << (3 * lg)) * a.ys), (short)0,
+                (int)dbytes, 0x00020000);
             const int yy = y0 + (sd & 1) * 2 + ((vgd & 3) >> 1), zz = z0 + (sd >> 1);
             const int xb = x0 + (vgd & 1) * 8;
-            const int64_t v0 = ((((int64_t)smp << lg) + zz) << (2 * lg)) + ((int64_t)yy << lg) + xb;
-            if (cgd * 8 < a.ys) {
+            const uint32_t v0 = ((uint32_t)zz << (2 * lg)) + ((uint32_t)yy << lg) + (uint32_t)xb;
+            const uint32_t bad = oob(cgd * 8 < a.ys);
 #pragma unroll
-                for (int m = 0; m < 8; ++m) reg[m] = *(const bf16x8*)(a.dy + (v0 + m) * a.ys + cgd * 8);
-            }
+            for (int m = 0; m < 8; ++m)
+                reg[m] = ld16(rs, (((v0 + m) * (uint32_t)a.ys + (uint32_t)(cgd * 8)) * 2u) | bad);
         }
     };
     if (b0 < b1) fetch(b0);
@@ -702,7 +714,7 @@ __global__ void __launch_bounds__(192, RS == 1 ? 3 : 2) k_wgrad_brick3(WgradArgs
                     *(bf16x2*)&row[e * kHaloChan + 8] = t2;
                 }
             }
-        } else if (tid < 96 + 32 * RS) {
+        } else if (tid >= 128 && tid < 128 + 32 * RS) {
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
                 bf16x8 w;
@@ -1286,17 +1298,18 @@ hipError_t launch_conv(const ConvArgs& a, int coutp, hipStream_t s) {
     const int sub = coutp / 16;
     const int nsub = sub % 4 == 0 ? 4 : sub % 3 == 0 ? 3 : sub % 2 == 0 ? 2 : 1;
     if (a.taps == 27 && a.lg >= 4 && a.cin % 16 == 0 && a.kpad >= 27 * a.cin) {
-        // on the 16-cell grid one output-channel group per block, for blocks
+        // one output-channel group per block (more blocks, fewer registers),
+        // except for 3 groups of 16 on grids of 32 and more, where one block
+        // serving all three was faster (measured: 48 channels on 64^3 243
+        // against 257 us, 96 on 32^3 75 against 98 us; 32 channels 40 -> 36 us)
         const int64_t G = (int64_t)1 << a.lg;
-        const int nb = a.lg >= 5 ? nsub : 1;
+        const int nb = a.lg >= 5 && nsub == 3 ? 3 : 1;
         const dim3 grid((unsigned)((G / 16) * (G / 4) * (G / kCvPlanes) * a.n), sub / nb);
         const dim3 block(64 * kCvPlanes);
-        switch (nb) {
-            case 4: hipLaunchKernelGGL(k_conv_brick<4>, grid, block, 0, s, a); break;
-            case 3: hipLaunchKernelGGL(k_conv_brick<3>, grid, block, 0, s, a); break;
-            case 2: hipLaunchKernelGGL(k_conv_brick<2>, grid, block, 0, s, a); break;
-            default: hipLaunchKernelGGL(k_conv_brick<1>, grid, block, 0, s, a); break;
-        }
+        if (nb == 3)
+            hipLaunchKernelGGL(k_conv_brick<3>, grid, block, 0, s, a);
+        else
+            hipLaunchKernelGGL(k_conv_brick<1>, grid, block, 0, s, a);
         return hipGetLastError();
     }
     const int64_t waves4 = (int64_t)ceil_div(M, 64) * (sub / nsub);
@@ -1455,7 +1468,8 @@ WgradPlan wgrad_plan(const ConvGeom& g, int relu) {
     // of 16 whose upper half loads zeros; only k_wgrad_brick3 is checked for
     // that, so 64 output channels need 16.)
     p.brick = !relu && g.lg >= 4 && g.taps == 27 &&
-              ((g.cin >= 8 && (g.coutp == 16 || g.coutp == 32)) || (g.cin >= 16 && g.coutp == 64));
+              ((g.cin >= 8 && (g.coutp == 16 || g.coutp == 32) && (g.c2 == 0 || g.c1s % 16 == 0)) ||
+               (g.cin >= 16 && g.coutp == 64));
     if (p.brick) {
         p.rs = g.coutp / 16;
         p.chunks = ceil_div(g.cin, 16);
