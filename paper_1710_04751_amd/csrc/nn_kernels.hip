@@ -429,7 +429,7 @@ __global__ void k_wgrad_reduce(WgradArgs a, int kt, int ct, int nz, int rs, int 
 constexpr int kBrickRow = 4 * 6 * 16 + 16;  // one channel's halo (hz, hy, x), padded
 
 template <int RS>
-__global__ void __launch_bounds__(256) k_wgrad_brick(WgradArgs a, int64_t bricks_per_block) {
+__global__ void __launch_bounds__(256, 2) k_wgrad_brick(WgradArgs a, int64_t bricks_per_block) {
     constexpr int NT = 7;  // taps per wave: ceil(27 / 4)
     __shared__ __attribute__((aligned(16))) __bf16 xs[3 * 16 * kBrickRow];
     __shared__ __attribute__((aligned(16))) __bf16 dT[RS * 16][kDTRow];
@@ -456,48 +456,61 @@ __global__ void __launch_bounds__(256) k_wgrad_brick(WgradArgs a, int64_t bricks
     const int cgx = tid / 48, remx = tid - cgx * 48;
     const int kx = remx & 1, hyx = (remx >> 1) % 6, hzx = (remx >> 1) / 6;
     const int td = tid - 96, vgd = td & 15, cgd = td >> 4, sd = vgd >> 2;
+    // Loads through range-checked buffer resources over one sample of the
+    // channel group's tensor and of the output gradient (zeros past the end:
+    // no branch, select or zero fill, so no load waits on another).
+    const int h = lg - 1;
+    const bool lo = c0 < a.c1s;
+    const int chans = lo ? a.c1s : a.c2;
+    const int hl = lo ? lg : h;
+    const int64_t vs = (int64_t)1 << (3 * hl);
+    const uint32_t xbytes = (uint32_t)(vs * chans * 2);
+    const uint32_t dbytes = (uint32_t)(((int64_t)1 << (3 * lg)) * a.ys * 2);
+    const int cloc = lo ? c0 : c0 - a.c1s;
     bf16x8 reg[10];
     auto fetch = [&](int64_t b) __attribute__((always_inline)) {
-        const int x0 = (int)(b % nbx) * 16;
-        int64_t rest = b / nbx;
-        const int y0 = (int)(rest % nby) * 4;
-        rest /= nby;
-        const int z0 = (int)(rest % nbz) * 2;
-        const int smp = (int)(rest / nbz);
-#pragma unroll
-        for (int m = 0; m < 10; ++m)
-#pragma unroll
-            for (int e = 0; e < 8; ++e) reg[m][e] = (__bf16)0.f;
+        uint32_t bb = (uint32_t)b;
+        const int x0 = (int)(bb % (uint32_t)nbx) * 16;
+        bb /= (uint32_t)nbx;
+        const int y0 = (int)(bb % (uint32_t)nby) * 4;
+        bb /= (uint32_t)nby;
+        const int z0 = (int)(bb % (uint32_t)nbz) * 2;
+        const int smp = (int)(bb / (uint32_t)nbz);
         if (tid < 96) {
             // input halo row (hz, hy), x cells 8k .. 8k+9, channel group cg
             // (the channel group is the slowest index)
-            const int yy = y0 + hyx - 1, zz = z0 + hzx - 1, cc = c0 + cgx * 8;
-            const bool row_ok = cc < a.cin && (unsigned)yy < (unsigned)G && (unsigned)zz < (unsigned)G;
+            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                const_cast<__bf16*>((lo ? a.x1 : a.x2) + (int64_t)smp * vs * chans), (short)0,
+                (int)xbytes, 0x00020000);
+            const int yy = y0 + hyx - 1, zz = z0 + hzx - 1;
+            const bool row_ok = c0 + cgx * 8 < a.cin && (unsigned)yy < (unsigned)G &&
+                                (unsigned)zz < (unsigned)G;
+            const int sh = lo ? 0 : 1;
+            const uint32_t rowv = ((uint32_t)(zz >> sh) << (2 * hl)) + ((uint32_t)(yy >> sh) << hl);
 #pragma unroll
             for (int m = 0; m < 10; ++m) {
                 const int xx = x0 + 8 * kx + m - 1;
-                if (row_ok && (unsigned)xx < (unsigned)G) {
-                    if (cc < a.c1s) {
-                        const int64_t vi = ((((int64_t)smp << lg) + zz) << (2 * lg)) +
-                                           ((int64_t)yy << lg) + xx;
-                        reg[m] = *(const bf16x8*)(a.x1 + vi * a.c1s + cc);
-                    } else {
-                        const int h = lg - 1;
-                        const int64_t vi = ((((int64_t)smp << h) + (zz >> 1)) << (2 * h)) +
-                                           ((int64_t)(yy >> 1) << h) + (xx >> 1);
-                        reg[m] = *(const bf16x8*)(a.x2 + vi * a.c2 + (cc - a.c1s));
-                    }
-                }
+                const bool ok = row_ok && (unsigned)xx < (unsigned)G;
+                const uint32_t off =
+                    (((rowv + (uint32_t)(xx >> sh)) * (uint32_t)chans + (uint32_t)(cloc + cgx * 8)) * 2u) |
+                    ((uint32_t)!ok << 31);
+                reg[m] = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
             }
         } else if (tid < 96 + 32 * RS) {
             // output gradient: 8 cells (one k group) x 8 channels
+            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                const_cast<__bf16*>(a.dy + ((int64_t)smp << (3 * lg)) * a.ys), (short)0,
+                (int)dbytes, 0x00020000);
             const int yy = y0 + (sd & 1) * 2 + ((vgd & 3) >> 1), zz = z0 + (sd >> 1);
             const int xb = x0 + (vgd & 1) * 8;
-            const int64_t v0 = ((((int64_t)smp << lg) + zz) << (2 * lg)) + ((int64_t)yy << lg) + xb;
-            if (cgd * 8 < a.ys) {
+            const uint32_t v0 = ((uint32_t)zz << (2 * lg)) + ((uint32_t)yy << lg) + (uint32_t)xb;
+            const uint32_t bad = (uint32_t)!(cgd * 8 < a.ys) << 31;
 #pragma unroll
-                for (int m = 0; m < 8; ++m) reg[m] = *(const bf16x8*)(a.dy + (v0 + m) * a.ys + cgd * 8);
-            }
+            for (int m = 0; m < 8; ++m)
+                reg[m] = __builtin_bit_cast(
+                    bf16x8, __builtin_amdgcn_raw_buffer_load_b128(
+                                rs, (((v0 + m) * (uint32_t)a.ys + (uint32_t)(cgd * 8)) * 2u) | bad,
+                                0, 0));
         }
     };
     if (b0 < b1) fetch(b0);
@@ -1468,8 +1481,8 @@ WgradPlan wgrad_plan(const ConvGeom& g, int relu) {
     // of 16 whose upper half loads zeros; only k_wgrad_brick3 is checked for
     // that, so 64 output channels need 16.)
     p.brick = !relu && g.lg >= 4 && g.taps == 27 &&
-              ((g.cin >= 8 && (g.coutp == 16 || g.coutp == 32) && (g.c2 == 0 || g.c1s % 16 == 0)) ||
-               (g.cin >= 16 && g.coutp == 64));
+              (g.c2 == 0 || g.c1s % 16 == 0) &&
+              ((g.cin >= 8 && (g.coutp == 16 || g.coutp == 32)) || (g.cin >= 16 && g.coutp == 64));
     if (p.brick) {
         p.rs = g.coutp / 16;
         p.chunks = ceil_div(g.cin, 16);
