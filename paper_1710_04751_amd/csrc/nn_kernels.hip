@@ -1183,10 +1183,14 @@ __global__ void k_cf_to_cl(const float* __restrict__ x, int n, int64_t V, int c,
 constexpr int kCvVox = 16;                  // LDS elements per voxel
 constexpr int kCvPlanes = 8;                // output planes (waves) per block
 constexpr int kCvHalo = 18 * 6 * (kCvPlanes + 2);  // halo voxels
+constexpr int kCvWRow = 27 * 16;            // LDS elements per weight row (864 bytes)
 
 template <int NSUB>
 __global__ void __launch_bounds__(64 * kCvPlanes) k_conv_brick(ConvArgs a) {
     __shared__ __attribute__((aligned(16))) __bf16 xs[kCvHalo * kCvVox];
+    // the chunk's weights: row co (NSUB * 16), tap t, 16 channels (864-byte
+    // rows, 32 mod 64, so the B-fragment reads are free of bank conflicts)
+    __shared__ __attribute__((aligned(16))) __bf16 wl[NSUB * 16 * kCvWRow];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r = lane & 15, q = lane >> 4;
     const int lg = a.lg, G = 1 << lg;
@@ -1229,6 +1233,12 @@ __global__ void __launch_bounds__(64 * kCvPlanes) k_conv_brick(ConvArgs a) {
             }
             *(bf16x8*)&xs[hv * kCvVox + half * 8] = v;
         }
+        for (int t = tid; t < NSUB * 16 * 27 * 2; t += 64 * kCvPlanes) {
+            const int row = t / 54, rem = t - row * 54, tap = rem >> 1, half = rem & 1;
+            *(bf16x8*)&wl[row * kCvWRow + tap * 16 + half * 8] =
+                *(const bf16x8*)(a.w + (int64_t)(cobase + row) * a.kpad + tap * a.cin + c0 +
+                                 half * 8);
+        }
         __syncthreads();
 #pragma unroll 2
         for (int p = 0; p < 14; ++p) {
@@ -1239,8 +1249,7 @@ __global__ void __launch_bounds__(64 * kCvPlanes) k_conv_brick(ConvArgs a) {
                 const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
 #pragma unroll
                 for (int j = 0; j < NSUB; ++j)
-                    bv[j] = *(const bf16x8*)(a.w + (int64_t)(cobase + j * 16 + r) * a.kpad +
-                                             t * a.cin + c0 + ch);
+                    bv[j] = *(const bf16x8*)&wl[(j * 16 + r) * kCvWRow + t * 16 + ch];
                 const int base = ((wave + dz + 1) * 6 + dy + 1) * 18 + r + dx + 1;
 #pragma unroll
                 for (int m = 0; m < 4; ++m)
