@@ -1209,35 +1209,74 @@ __global__ void __launch_bounds__(64 * kCvPlanes) k_conv_brick(ConvArgs a) {
 #pragma unroll
         for (int j = 0; j < NSUB; ++j) acc[m][j] = floatx4{0.f, 0.f, 0.f, 0.f};
     const int ch = (q & 1) * 8;
+    // Halo loads through a range-checked buffer resource over the block's
+    // sample of the chunk's tensor (x1 when c0 < c1s; c1s is a multiple of
+    // 16 when there is an x2): a position outside the grid reads past the
+    // end and gets zeros, so the loads carry no branch or select.  All of a
+    // thread's halo and weight loads are issued before its LDS stores.
+    constexpr int kThreads = 64 * kCvPlanes;
+    constexpr int kHaloItems = 2 * kCvHalo, kHaloPer = (kHaloItems + kThreads - 1) / kThreads;
+    constexpr int kWItems = NSUB * 16 * 27 * 2, kWPer = (kWItems + kThreads - 1) / kThreads;
+    const int h = lg - 1;
     for (int c0 = 0; c0 < a.cin; c0 += 16) {
-        for (int t = tid; t < 2 * kCvHalo; t += 64 * kCvPlanes) {
+        const bool lo = c0 < a.c1s;
+        const int chans = lo ? a.c1s : a.c2;
+        const int hl = lo ? lg : h;  // the tensor's grid: 2^hl cells a side
+        const int sh = lo ? 0 : 1;   // coarse tensor: the fine cell's parent
+        const int64_t vs = (int64_t)1 << (3 * hl);
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<__bf16*>((lo ? a.x1 : a.x2) + (int64_t)smp * vs * chans), (short)0,
+            (int)(uint32_t)(vs * chans * 2), 0x00020000);
+        const int cloc = lo ? c0 : c0 - a.c1s;
+        auto halo_load = [&](int i) __attribute__((always_inline)) {
+            const int t = tid + i * kThreads;
             const int half = t & 1, hv = t >> 1;
             const int hx = hv % 18, hy = (hv / 18) % 6, hz = hv / 108;
             const int xx = x0 + hx - 1, yy = y0 + hy - 1, zz = z0 + hz - 1;
-            const int cc = c0 + half * 8;
-            bf16x8 v;
-#pragma unroll
-            for (int e = 0; e < 8; ++e) v[e] = (__bf16)0.f;
-            if ((unsigned)xx < (unsigned)G && (unsigned)yy < (unsigned)G &&
-                (unsigned)zz < (unsigned)G) {
-                if (cc < a.c1s) {
-                    const int64_t vi = ((((int64_t)smp << lg) + zz) << (2 * lg)) +
-                                       ((int64_t)yy << lg) + xx;
-                    v = *(const bf16x8*)(a.x1 + vi * a.c1s + cc);
-                } else {
-                    const int h = lg - 1;
-                    const int64_t vi = ((((int64_t)smp << h) + (zz >> 1)) << (2 * h)) +
-                                       ((int64_t)(yy >> 1) << h) + (xx >> 1);
-                    v = *(const bf16x8*)(a.x2 + vi * a.c2 + (cc - a.c1s));
-                }
-            }
-            *(bf16x8*)&xs[hv * kCvVox + half * 8] = v;
-        }
-        for (int t = tid; t < NSUB * 16 * 27 * 2; t += 64 * kCvPlanes) {
+            const bool ok = t < kHaloItems && (unsigned)xx < (unsigned)G &&
+                            (unsigned)yy < (unsigned)G && (unsigned)zz < (unsigned)G;
+            const uint32_t vox = ((uint32_t)(zz >> sh) << (2 * hl)) + ((uint32_t)(yy >> sh) << hl) +
+                                 (uint32_t)(xx >> sh);
+            const uint32_t off = ((vox * (uint32_t)chans + (uint32_t)(cloc + half * 8)) * 2u) |
+                                 ((uint32_t)!ok << 31);
+            return __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
+        };
+        auto halo_store = [&](int i, const bf16x8& v) __attribute__((always_inline)) {
+            const int t = tid + i * kThreads;
+            if (t < kHaloItems) *(bf16x8*)&xs[(t >> 1) * kCvVox + (t & 1) * 8] = v;
+        };
+        auto w_load = [&](int i) __attribute__((always_inline)) {
+            const int t = tid + i * kThreads, tt = t < kWItems ? t : 0;
+            const int row = tt / 54, rem = tt - row * 54, tap = rem >> 1, half = rem & 1;
+            return *(const bf16x8*)(a.w + (int64_t)(cobase + row) * a.kpad + tap * a.cin + c0 +
+                                    half * 8);
+        };
+        auto w_store = [&](int i, const bf16x8& v) __attribute__((always_inline)) {
+            const int t = tid + i * kThreads;
             const int row = t / 54, rem = t - row * 54, tap = rem >> 1, half = rem & 1;
-            *(bf16x8*)&wl[row * kCvWRow + tap * 16 + half * 8] =
-                *(const bf16x8*)(a.w + (int64_t)(cobase + row) * a.kpad + tap * a.cin + c0 +
-                                 half * 8);
+            if (t < kWItems) *(bf16x8*)&wl[row * kCvWRow + tap * 16 + half * 8] = v;
+        };
+        if constexpr (NSUB == 1) {
+            // two batches of loads, each issued before its stores (at most 4
+            // fragments in registers, so 6 waves per SIMD still fit)
+            static_assert(kHaloPer == 5 && kWPer == 2, "batch split assumes these counts");
+            {
+                const bf16x8 v0 = halo_load(0), v1 = halo_load(1), v2 = halo_load(2);
+                halo_store(0, v0);
+                halo_store(1, v1);
+                halo_store(2, v2);
+            }
+            const bf16x8 v3 = halo_load(3), v4 = halo_load(4), w0 = w_load(0), w1 = w_load(1);
+            halo_store(3, v3);
+            halo_store(4, v4);
+            w_store(0, w0);
+            w_store(1, w1);
+        } else {
+            // three output groups need their registers for the products
+#pragma unroll 1
+            for (int i = 0; i < kHaloPer; ++i) halo_store(i, halo_load(i));
+#pragma unroll 1
+            for (int i = 0; i < kWPer; ++i) w_store(i, w_load(i));
         }
         __syncthreads();
 #pragma unroll 2
@@ -1319,7 +1358,8 @@ hipError_t launch_conv(const ConvArgs& a, int coutp, hipStream_t s) {
     const int64_t M = (int64_t)a.n << (3 * a.lg);
     const int sub = coutp / 16;
     const int nsub = sub % 4 == 0 ? 4 : sub % 3 == 0 ? 3 : sub % 2 == 0 ? 2 : 1;
-    if (a.taps == 27 && a.lg >= 4 && a.cin % 16 == 0 && a.kpad >= 27 * a.cin) {
+    if (a.taps == 27 && a.lg >= 4 && a.cin % 16 == 0 && a.kpad >= 27 * a.cin &&
+        (a.c2 == 0 || a.c1s % 16 == 0)) {
         // one output-channel group per block (more blocks, fewer registers),
         // except for 3 groups of 16 on grids of 32 and more, where one block
         // serving all three was faster (measured: 48 channels on 64^3 243
