@@ -1233,7 +1233,7 @@ __global__ void __launch_bounds__(64 * kCvPlanes) k_conv_brick(ConvArgs a) {
             const int half = t & 1, hv = t >> 1;
             const int hx = hv % 18, hy = (hv / 18) % 6, hz = hv / 108;
             const int xx = x0 + hx - 1, yy = y0 + hy - 1, zz = z0 + hz - 1;
-            const bool ok = t < kHaloItems && (unsigned)xx < (unsigned)G &&
+            const bool ok = t < kHaloItems && c0 + half * 8 < a.cin && (unsigned)xx < (unsigned)G &&
                             (unsigned)yy < (unsigned)G && (unsigned)zz < (unsigned)G;
             const uint32_t vox = ((uint32_t)(zz >> sh) << (2 * hl)) + ((uint32_t)(yy >> sh) << hl) +
                                  (uint32_t)(xx >> sh);
@@ -1353,13 +1353,18 @@ hipError_t launch_conv_mt(const ConvArgs& a, int coutp, hipStream_t s) {
 // Four voxel tiles per wave when that still leaves at least 2048 blocks (so
 // each weight fragment serves 64 voxels).  Otherwise one tile, and the k
 // range is split over 2 or 4 waves per block when there are fewer than
-// 4096 or 1024 blocks and at least two steps of 32 per wave.
+// 4096 or 1024 blocks and at least two steps of 32 per wave (8 waves were
+// measured no faster on the 8^3 layers).
 hipError_t launch_conv(const ConvArgs& a, int coutp, hipStream_t s) {
     const int64_t M = (int64_t)a.n << (3 * a.lg);
     const int sub = coutp / 16;
     const int nsub = sub % 4 == 0 ? 4 : sub % 3 == 0 ? 3 : sub % 2 == 0 ? 2 : 1;
-    if (a.taps == 27 && a.lg >= 4 && a.cin % 16 == 0 && a.kpad >= 27 * a.cin &&
-        (a.c2 == 0 || a.c1s % 16 == 0)) {
+    // (8 input channels, the first layer, take a 16-channel group whose upper
+    // half reads zeros; its weight rows there hold the next tap's weights,
+    // which multiply those zeros, and stay inside the row since 27 * 8 + 8 <=
+    // kpad.)
+    if (a.taps == 27 && a.lg >= 4 && a.kpad >= 27 * a.cin &&
+        (a.cin % 16 == 0 || (a.cin == 8 && a.c2 == 0)) && (a.c2 == 0 || a.c1s % 16 == 0)) {
         // one output-channel group per block (more blocks, fewer registers),
         // except for 3 groups of 16 on grids of 32 and more, where one block
         // serving all three was faster (measured: 48 channels on 64^3 243
