@@ -377,34 +377,53 @@ __global__ void k_sum_row_slices(const float* __restrict__ in, int64_t boff, int
     out[i] = sum;
 }
 
+// Sum over the rows of a partial-sum table by L consecutive lanes per
+// gradient entry (L = 8 for tables of many rows, 1 for few): lane j adds rows
+// j, j + L, ... in order, then a fixed xor butterfly adds the L lane sums
+// (lane 0's result is written), so the order of every addition is fixed and,
+// for many rows, many loads are in flight.
+template <int L>
+__device__ __forceinline__ float lane_group_sum(float v) {
+    if constexpr (L >= 2) v += __shfl_xor(v, 1, L);
+    if constexpr (L >= 4) v += __shfl_xor(v, 2, L);
+    if constexpr (L >= 8) v += __shfl_xor(v, 4, L);
+    return v;
+}
+constexpr int kRedManyRows = 32;  // rows from which a table takes 8 lanes per entry
+
 // Sum of the k_wgrad partials over the voxel chunks, into the master layout
-// dw[co][tap][ci] (zero padding channels dropped) and db.  One thread per
-// (row, column) of the gradient matrix or per bias entry.
+// dw[co][tap][ci] (zero padding channels dropped) and db.  One group of L
+// lanes per (row, column) of the gradient matrix or per bias entry.
+template <int L>
 __global__ void k_wgrad_reduce(WgradArgs a, int kt, int ct, int nz, int rs, int cs, float* dw,
                                float* db) {
-    const int64_t rows = (int64_t)ct * rs * 16, cols = (int64_t)kt * cs * 16;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // 32-bit index arithmetic: the host launches fewer than 2^31 lanes
+    const uint32_t rows = (uint32_t)(ct * rs * 16), cols = (uint32_t)(kt * cs * 16);
+    const uint32_t i = (blockIdx.x * blockDim.x + threadIdx.x) / L;
+    const int j = threadIdx.x % L;
     if (i < rows * cols) {
-        const int row = (int)(i / cols), col = (int)(i - (int64_t)row * cols);
-        const int cty = row / (rs * 16), rl = row - cty * rs * 16;
-        const int ktx = col / (cs * 16), cl = col - ktx * cs * 16;
-        if (row >= a.cout || col >= a.K) return;
-        const int t = col / a.cin, cc = col - t * a.cin;
-        if (cc < a.c1s && cc >= a.c1) return;  // zero padding channels of x1
-        const int ci = cc < a.c1s ? cc : a.c1 + (cc - a.c1s);
+        const uint32_t row = i / cols, col = i - row * cols;
+        const uint32_t cty = row / (uint32_t)(rs * 16), rl = row - cty * (uint32_t)(rs * 16);
+        const uint32_t ktx = col / (uint32_t)(cs * 16), cl = col - ktx * (uint32_t)(cs * 16);
+        if (row >= (uint32_t)a.cout || col >= (uint32_t)a.K) return;
+        const uint32_t t = col / (uint32_t)a.cin, cc = col - t * (uint32_t)a.cin;
+        if (cc < (uint32_t)a.c1s && cc >= (uint32_t)a.c1) return;  // zero padding channels of x1
+        const uint32_t ci = cc < (uint32_t)a.c1s ? cc : a.c1 + (cc - a.c1s);
         const int64_t per = (int64_t)rs * 16 * cs * 16;
         float sum = 0.f;
-#pragma unroll 8
-        for (int z = 0; z < nz; ++z)
+#pragma unroll 4
+        for (int z = j; z < nz; z += L)
             sum += a.part[(((int64_t)z * ct + cty) * kt + ktx) * per + rl * (cs * 16) + cl];
-        dw[((int64_t)row * a.taps + t) * a.cin_real + ci] = sum;
-    } else if (i < rows * cols + a.cout) {
-        const int co = (int)(i - rows * cols);
-        const int cty = co / (rs * 16), rl = co - cty * rs * 16;
+        sum = lane_group_sum<L>(sum);
+        if (j == 0) dw[((int64_t)row * a.taps + t) * a.cin_real + ci] = sum;
+    } else if (i < rows * cols + (uint32_t)a.cout) {
+        const uint32_t co = i - rows * cols;
+        const uint32_t cty = co / (uint32_t)(rs * 16), rl = co - cty * (uint32_t)(rs * 16);
         float sum = 0.f;
-        for (int z = 0; z < nz; ++z)
+        for (int z = j; z < nz; z += L)
             sum += a.part[a.bias_off + ((int64_t)z * ct + cty) * (rs * 16) + rl];
-        db[co] = sum;
+        sum = lane_group_sum<L>(sum);
+        if (j == 0) db[co] = sum;
     }
 }
 
@@ -800,29 +819,37 @@ __global__ void __launch_bounds__(192, RS == 1 ? 3 : 2) k_wgrad_brick3(WgradArgs
 }
 
 // Sum of the k_wgrad_brick partials over the brick ranges, into dw[co][tap]
-// [ci] (zero padding channels dropped) and db.  One thread per gradient
-// entry of (channel group, tap, co, channel) or per bias entry.
+// [ci] (zero padding channels dropped) and db.  One group of L lanes per
+// gradient entry of (channel group, tap, co, channel) or per bias entry.
+template <int L>
 __global__ void k_wgrad_brick_reduce(WgradArgs a, int chunks, int groups, int rs, float* dw,
                                      float* db) {
-    const int64_t per = (int64_t)27 * rs * 16 * 16;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < per * chunks) {
-        const int chunk = (int)(i / per);
-        const int e = (int)(i - (int64_t)chunk * per);
-        const int t = e / (rs * 256), rem = e - t * rs * 256;
-        const int co = rem >> 4, cl = rem & 15;
-        const int cc = chunk * 16 + cl;
-        if (co >= a.cout || cc >= a.cin || (cc < a.c1s && cc >= a.c1)) return;
-        const int ci = cc < a.c1s ? cc : a.c1 + (cc - a.c1s);
+    // 32-bit index arithmetic: the host launches fewer than 2^31 lanes
+    const uint32_t per = (uint32_t)(27 * rs * 16 * 16);
+    const uint32_t i = (blockIdx.x * blockDim.x + threadIdx.x) / L;
+    const int j = threadIdx.x % L;
+    if (i < per * (uint32_t)chunks) {
+        const uint32_t chunk = i / per, e = i - chunk * per;
+        const uint32_t t = e / (uint32_t)(rs * 256), rem = e - t * (uint32_t)(rs * 256);
+        const uint32_t co = rem >> 4, cl = rem & 15;
+        const uint32_t cc = chunk * 16 + cl;
+        if (co >= (uint32_t)a.cout || cc >= (uint32_t)a.cin ||
+            (cc < (uint32_t)a.c1s && cc >= (uint32_t)a.c1))
+            return;
+        const uint32_t ci = cc < (uint32_t)a.c1s ? cc : a.c1 + (cc - a.c1s);
         float sum = 0.f;
-#pragma unroll 8
-        for (int g = 0; g < groups; ++g) sum += a.part[((int64_t)g * chunks + chunk) * per + e];
-        dw[((int64_t)co * 27 + t) * a.cin_real + ci] = sum;
-    } else if (i < per * chunks + a.cout) {
-        const int co = (int)(i - per * chunks);
+#pragma unroll 4
+        for (int g = j; g < groups; g += L)
+            sum += a.part[((int64_t)g * chunks + chunk) * per + e];
+        sum = lane_group_sum<L>(sum);
+        if (j == 0) dw[((int64_t)co * 27 + t) * a.cin_real + ci] = sum;
+    } else if (i < per * (uint32_t)chunks + (uint32_t)a.cout) {
+        const uint32_t co = i - per * (uint32_t)chunks;
         float sum = 0.f;
-        for (int g = 0; g < groups; ++g) sum += a.part[a.bias_off + (int64_t)g * rs * 16 + co];
-        db[co] = sum;
+        for (int g = j; g < groups; g += L)
+            sum += a.part[a.bias_off + (int64_t)g * rs * 16 + co];
+        sum = lane_group_sum<L>(sum);
+        if (j == 0) db[co] = sum;
     }
 }
 
@@ -1516,7 +1543,7 @@ struct WgradPlan {
 // Scratch of the first reduction pass, after the partials: the weight rows
 // and the bias rows summed over slices of kRowSlice rows.
 void finish_plan(WgradPlan* p) {
-    p->slices = p->rows > 2 * kRowSlice && !(p->wwidth >= 65536 && p->rows <= 128);
+    p->slices = p->rows > 2 * kRowSlice;
     const int64_t sl = p->slices ? (p->rows + kRowSlice - 1) / kRowSlice : 0;
     p->scratch_floats = p->part_floats + sl * (p->wwidth + p->bwidth);
 }
@@ -1577,8 +1604,8 @@ WgradPlan wgrad_plan(const ConvGeom& g, int relu) {
 }
 
 // First reduction pass over the partials of plan p, when they have more
-// rows than the second pass reads quickly (many rows, few gradient entries
-// per row: then one thread per entry would leave too few loads in flight).
+// than 2 kRowSlice rows (more than the second pass's lane groups read
+// quickly).
 // Returns the arguments of the second pass: the partials, or their slice
 // sums with rows replaced by slices.
 hipError_t sum_slices(const WgradPlan& p, const WgradArgs& a, WgradArgs* b, int64_t* rows,
@@ -1644,8 +1671,13 @@ hipError_t conv_backward_weight(const ConvGeom& g, const __bf16* x1, const __bf1
         e = sum_slices(p, a, &b, &rows, s);
         if (e != hipSuccess) return e;
         const int64_t nred = (int64_t)27 * g.coutp * 16 * p.chunks + g.cout;
-        hipLaunchKernelGGL(k_wgrad_brick_reduce, dim3(ceil_div(nred, 256)), dim3(256), 0, s, b,
-                           p.chunks, (int)rows, p.rs, dw, db);
+        if (nred * 8 >= ((int64_t)1 << 31)) return hipErrorInvalidValue;  // 32-bit lane index
+        if (rows >= kRedManyRows)
+            hipLaunchKernelGGL(k_wgrad_brick_reduce<8>, dim3(ceil_div(nred * 8, 256)), dim3(256), 0,
+                               s, b, p.chunks, (int)rows, p.rs, dw, db);
+        else
+            hipLaunchKernelGGL(k_wgrad_brick_reduce<1>, dim3(ceil_div(nred, 256)), dim3(256), 0, s,
+                               b, p.chunks, (int)rows, p.rs, dw, db);
         return hipGetLastError();
     }
     const dim3 grid(p.kt, p.ct, p.nz);
@@ -1661,8 +1693,13 @@ hipError_t conv_backward_weight(const ConvGeom& g, const __bf16* x1, const __bf1
     e = sum_slices(p, a, &b, &rows, s);
     if (e != hipSuccess) return e;
     const int64_t nred = (int64_t)p.ct * p.rs * 16 * p.kt * p.cs * 16 + g.cout;
-    hipLaunchKernelGGL(k_wgrad_reduce, dim3(ceil_div(nred, 256)), dim3(256), 0, s, b, p.kt, p.ct,
-                       (int)rows, p.rs, p.cs, dw, db);
+    if (nred * 8 >= ((int64_t)1 << 31)) return hipErrorInvalidValue;  // 32-bit lane index
+    if (rows >= kRedManyRows)
+        hipLaunchKernelGGL(k_wgrad_reduce<8>, dim3(ceil_div(nred * 8, 256)), dim3(256), 0, s, b,
+                           p.kt, p.ct, (int)rows, p.rs, p.cs, dw, db);
+    else
+        hipLaunchKernelGGL(k_wgrad_reduce<1>, dim3(ceil_div(nred, 256)), dim3(256), 0, s, b, p.kt,
+                           p.ct, (int)rows, p.rs, p.cs, dw, db);
     return hipGetLastError();
 }
 
