@@ -63,6 +63,7 @@ struct ConvArgs {
     __bf16* out;
     const __bf16* omask;  // outputs where omask <= 0 are written as 0
     int32_t n, lg, taps, c1s, c2, cin, K, kpad, cout, ys, relu;
+    int32_t wrows;        // rows of the packed weight w (set by launch_conv)
 };
 
 // One block: MT * 16 voxels x (NSUB * 16) output channels, channel group
@@ -1197,32 +1198,60 @@ __global__ void k_cf_to_cl(const float* __restrict__ x, int n, int64_t V, int c,
 }
 
 // Forward / input-gradient convolution on LDS-staged bricks (3x3x3 taps,
-// BF16 output, grids of at least 16 cells, input channels a multiple of
-// 16).  A block of 8 waves computes 16 x 4 x 8 output voxels (wave w the
-// plane z0 + w, its four 16-voxel row tiles y0 .. y0 + 3) for NSUB * 16
-// output channels.  Per 16 input channels the block stages the 18 x 6 x 10
-// input halo channels-last in LDS (32 bytes per voxel, no padding: lane r
-// reads voxel r and its second 8 channels sit 16 bytes on, a layout the
-// LDS serves without bank conflicts), so every A fragment (8 channels of one
-// voxel for one tap) is one LDS read instead of a global load per tap.  A k step of 32 pairs two taps
-// of the 16 channels; B fragments are read from the packed weight ([co][k],
-// k = tap * cin + channel) and serve the four row tiles.
+// BF16 output, grids of at least 16 cells, input channels a multiple of 16,
+// or 8 with no second tensor).  A block of 8 waves computes 16 x 4 x 8 output
+// voxels (wave w the plane z0 + w, its four 16-voxel row tiles y0 .. y0 + 3)
+// for NSUB * 16 output channels.  Per 16 input channels the block copies the
+// 18 x 6 x 10 input halo (channels-last, 32 bytes per voxel: lane r reads
+// voxel r and its second 8 channels sit 16 bytes on, which the LDS serves
+// without bank conflicts) and the chunk's weights into LDS with direct-to-LDS
+// buffer loads (no register staging, every load of the chunk in flight at
+// once), so every A fragment (8 channels of one voxel for one tap) is one LDS
+// read.  A k step of 32 takes two taps of the 16 channels, paired so that
+// the second lies a fixed displacement from the first within each group of
+// steps (two planes on, two rows on, two voxels on, or a slot of zero
+// weights): a lane's LDS addresses are then a base register per group plus
+// a compile-time offset, with no per-step index arithmetic.
 constexpr int kCvVox = 16;                  // LDS elements per voxel
 constexpr int kCvPlanes = 8;                // output planes (waves) per block
 constexpr int kCvHalo = 18 * 6 * (kCvPlanes + 2);  // halo voxels
-constexpr int kCvWRow = 27 * 16;            // LDS elements per weight row (864 bytes)
+constexpr int kCvHaloItems = 2 * kCvHalo;   // 16-byte halo items of a chunk
+constexpr int kCvHaloBuf = kCvHaloItems + 16;  // + the tail of the last partial wave
+constexpr int kCvSlots = 28;                // 27 taps + a zero-weight slot
+constexpr int kCvWItemsRow = 2 * kCvSlots + 2;  // 16-byte weight items per row (+ 32 B pad)
+constexpr int kCvWRow = 8 * kCvWItemsRow;   // elements per LDS weight row (928 B, 32 mod 64)
+
+// Step p (0..13) of the k loop takes tap p in lanes q < 2 and tap
+// cv_pair_tap(p) in lanes q >= 2 (-1: the zero slot); cv_pair_shift(p) is
+// the second tap's halo position minus the first's, in voxels.
+__device__ constexpr int cv_pair_tap(int p) {
+    return p <= 8 ? p + 18 : p <= 11 ? p + 6 : p == 12 ? 14 : -1;
+}
+__device__ constexpr int cv_pair_shift(int p) {
+    return p <= 8 ? 2 * 108 : p <= 11 ? 2 * 18 : p == 12 ? 2 : 0;
+}
+// halo position of tap t = (dz + 1) * 9 + (dy + 1) * 3 + dx + 1, relative to
+// the output voxel's (-1, -1, -1) neighbour
+__device__ constexpr int cv_tap_offset(int t) { return (t / 9) * 108 + ((t / 3) % 3) * 18 + t % 3; }
+
+typedef __attribute__((address_space(3))) void* lds_void_ptr;
 
 template <int NSUB>
-__global__ void __launch_bounds__(64 * kCvPlanes) k_conv_brick(ConvArgs a) {
-    __shared__ __attribute__((aligned(16))) __bf16 xs[kCvHalo * kCvVox];
-    // the chunk's weights: row co (NSUB * 16), tap t, 16 channels (864-byte
-    // rows, 32 mod 64, so the B-fragment reads are free of bank conflicts)
-    __shared__ __attribute__((aligned(16))) __bf16 wl[NSUB * 16 * kCvWRow];
+__global__ void __launch_bounds__(64 * kCvPlanes)
+    __attribute__((amdgpu_waves_per_eu(NSUB == 1 ? 6 : 4))) k_conv_brick(ConvArgs a) {
+    constexpr int kThreads = 64 * kCvPlanes;
+    constexpr int kWItems = NSUB * 16 * kCvWItemsRow;
+    constexpr int kWBuf = (kWItems + 63) / 64 * 64;  // whole waves of 16-byte items
+    __shared__ __attribute__((aligned(16))) __bf16 xs[kCvHaloBuf * 8];
+    __shared__ __attribute__((aligned(16))) __bf16 wl[kWBuf * 8];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int r = lane & 15, q = lane >> 4;
+    const int r = lane & 15, q = lane >> 4, hi = q >> 1;
     const int lg = a.lg, G = 1 << lg;
     const int nbx = G >> 4, nby = G >> 2, nbz = G / kCvPlanes;
-    int64_t bid = blockIdx.x;
+    // blocks i, i + 8, ... run on one XCD (dispatch is round-robin over the
+    // eight): give each XCD a contiguous range of bricks, whose halos overlap
+    // in its L2 (the grid's x size is a multiple of 8 for G >= 16)
+    int64_t bid = (int64_t)(blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8;
     const int x0 = (int)(bid % nbx) * 16;
     bid /= nbx;
     const int y0 = (int)(bid % nby) * 4;
@@ -1236,17 +1265,21 @@ __global__ void __launch_bounds__(64 * kCvPlanes) k_conv_brick(ConvArgs a) {
 #pragma unroll
         for (int j = 0; j < NSUB; ++j) acc[m][j] = floatx4{0.f, 0.f, 0.f, 0.f};
     const int ch = (q & 1) * 8;
-    // Halo loads through a range-checked buffer resource over the block's
-    // sample of the chunk's tensor (x1 when c0 < c1s; c1s is a multiple of
-    // 16 when there is an x2): a position outside the grid reads past the
-    // end and gets zeros, so the loads carry no branch or select.  All of a
-    // thread's halo and weight loads are issued before its LDS stores.
-    constexpr int kThreads = 64 * kCvPlanes;
-    constexpr int kHaloItems = 2 * kCvHalo, kHaloPer = (kHaloItems + kThreads - 1) / kThreads;
-    constexpr int kWItems = NSUB * 16 * 27 * 2, kWPer = (kWItems + kThreads - 1) / kThreads;
+    // LDS byte addresses of this lane: A (halo) per shift group, B (weights)
+    const uint32_t lb = (uint32_t)(wave * 108 + r);
+    const uint32_t vA0 = ((lb + hi * 2 * 108) * kCvVox + ch) * 2;
+    const uint32_t vA1 = ((lb + hi * 2 * 18) * kCvVox + ch) * 2;
+    const uint32_t vA2 = ((lb + hi * 2) * kCvVox + ch) * 2;
+    const uint32_t vA3 = (lb * kCvVox + ch) * 2;
+    const uint32_t vB = (uint32_t)(r * kCvWRow + hi * 16 + ch) * 2;
+    const char* xsb = (const char*)xs;
+    const char* wlb = (const char*)wl;
+    // Loads go through range-checked buffer resources: a position outside
+    // the grid (or the tensor, or a weight item of the zero slot or padding)
+    // reads past the end and lands as zeros.
     const int h = lg - 1;
     for (int c0 = 0; c0 < a.cin; c0 += 16) {
-        const bool lo = c0 < a.c1s;
+        const bool lo = c0 < a.c1s;  // x1's channels, else x2's (c1s is then a multiple of 16)
         const int chans = lo ? a.c1s : a.c2;
         const int hl = lo ? lg : h;  // the tensor's grid: 2^hl cells a side
         const int sh = lo ? 0 : 1;   // coarse tensor: the fine cell's parent
@@ -1255,80 +1288,61 @@ __global__ void __launch_bounds__(64 * kCvPlanes) k_conv_brick(ConvArgs a) {
             const_cast<__bf16*>((lo ? a.x1 : a.x2) + (int64_t)smp * vs * chans), (short)0,
             (int)(uint32_t)(vs * chans * 2), 0x00020000);
         const int cloc = lo ? c0 : c0 - a.c1s;
-        auto halo_load = [&](int i) __attribute__((always_inline)) {
-            const int t = tid + i * kThreads;
+        const int wv = __builtin_amdgcn_readfirstlane(wave);
+        // halo item t (voxel t / 2, channel half t % 2) lands at LDS byte 16 t
+#pragma unroll
+        for (int i = 0; i < (kCvHaloItems + kThreads - 1) / kThreads; ++i) {
+            const int tb = i * kThreads + wv * 64;
+            if (tb >= kCvHaloItems) continue;
+            const int t = tb + lane;
             const int half = t & 1, hv = t >> 1;
             const int hx = hv % 18, hy = (hv / 18) % 6, hz = hv / 108;
             const int xx = x0 + hx - 1, yy = y0 + hy - 1, zz = z0 + hz - 1;
-            const bool ok = t < kHaloItems && c0 + half * 8 < a.cin && (unsigned)xx < (unsigned)G &&
+            const bool ok = t < kCvHaloItems && c0 + half * 8 < a.cin && (unsigned)xx < (unsigned)G &&
                             (unsigned)yy < (unsigned)G && (unsigned)zz < (unsigned)G;
             const uint32_t vox = ((uint32_t)(zz >> sh) << (2 * hl)) + ((uint32_t)(yy >> sh) << hl) +
                                  (uint32_t)(xx >> sh);
             const uint32_t off = ((vox * (uint32_t)chans + (uint32_t)(cloc + half * 8)) * 2u) |
                                  ((uint32_t)!ok << 31);
-            return __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
-        };
-        auto halo_store = [&](int i, const bf16x8& v) __attribute__((always_inline)) {
-            const int t = tid + i * kThreads;
-            if (t < kHaloItems) *(bf16x8*)&xs[(t >> 1) * kCvVox + (t & 1) * 8] = v;
-        };
-        auto w_load = [&](int i) __attribute__((always_inline)) {
-            const int t = tid + i * kThreads, tt = t < kWItems ? t : 0;
-            const int row = tt / 54, rem = tt - row * 54, tap = rem >> 1, half = rem & 1;
-            return *(const bf16x8*)(a.w + (int64_t)(cobase + row) * a.kpad + tap * a.cin + c0 +
-                                    half * 8);
-        };
-        auto w_store = [&](int i, const bf16x8& v) __attribute__((always_inline)) {
-            const int t = tid + i * kThreads;
-            const int row = t / 54, rem = t - row * 54, tap = rem >> 1, half = rem & 1;
-            if (t < kWItems) *(bf16x8*)&wl[row * kCvWRow + tap * 16 + half * 8] = v;
-        };
-        if constexpr (NSUB == 1) {
-            // two batches of loads, each issued before its stores (at most 4
-            // fragments in registers, so 6 waves per SIMD still fit)
-            static_assert(kHaloPer == 5 && kWPer == 2, "batch split assumes these counts");
-            {
-                const bf16x8 v0 = halo_load(0), v1 = halo_load(1), v2 = halo_load(2);
-                halo_store(0, v0);
-                halo_store(1, v1);
-                halo_store(2, v2);
-            }
-            const bf16x8 v3 = halo_load(3), v4 = halo_load(4), w0 = w_load(0), w1 = w_load(1);
-            halo_store(3, v3);
-            halo_store(4, v4);
-            w_store(0, w0);
-            w_store(1, w1);
-        } else {
-            // three output groups need their registers for the products
-#pragma unroll 1
-            for (int i = 0; i < kHaloPer; ++i) halo_store(i, halo_load(i));
-#pragma unroll 1
-            for (int i = 0; i < kWPer; ++i) w_store(i, w_load(i));
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void_ptr)&xs[tb * 8], 16, off, 0, 0, 0);
         }
+        const __amdgpu_buffer_rsrc_t rw = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<__bf16*>(a.w), (short)0, (int)(uint32_t)((int64_t)a.wrows * a.kpad * 2),
+            0x00020000);
+        // weight item t: row t / 58 (output channel cobase + row), slot s =
+        // (t % 58) / 2 (tap s / 2 for even s, the paired tap for odd s), 8
+        // channels of half t % 2; items 56, 57 of a row are padding.  (With 8
+        // input channels the upper half holds the next tap's weights, which
+        // meet zero inputs, and stays inside the row since 27 * 8 + 8 <= kpad.)
+#pragma unroll
+        for (int i = 0; i < (kWBuf + kThreads - 1) / kThreads; ++i) {
+            const int tb = i * kThreads + wv * 64;
+            if (tb >= kWBuf) continue;
+            const int t = tb + lane;
+            const int row = t / kCvWItemsRow, rem = t - row * kCvWItemsRow;
+            const int slot = rem >> 1, half = rem & 1, p = slot >> 1;
+            const int tap = (slot & 1) ? cv_pair_tap(p) : p;
+            const bool ok = t < kWItems && rem < 2 * kCvSlots && tap >= 0 && cobase + row < a.wrows;
+            const uint32_t off =
+                ((uint32_t)((cobase + row) * a.kpad + tap * a.cin + c0 + half * 8) * 2u) |
+                ((uint32_t)!ok << 31);
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rw, (lds_void_ptr)&wl[tb * 8], 16, off, 0, 0, 0);
+        }
+        // this wave's copies have landed (vmcnt 0; expcnt and lgkmcnt left at their maxima)
+        __builtin_amdgcn_s_waitcnt((7 << 4) | (15 << 8));
         __syncthreads();
-#pragma unroll 2
+#pragma unroll
         for (int p = 0; p < 14; ++p) {
-            const int t = 2 * p + (q >> 1);  // this lane's tap
-            bf16x8 bv[NSUB];
-            bf16x8 av[4];
-            if (t < 27) {
-                const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
+            const int d = cv_pair_shift(p);
+            const uint32_t va = d == 2 * 108 ? vA0 : d == 2 * 18 ? vA1 : d == 2 ? vA2 : vA3;
+            const int toff = cv_tap_offset(p);
+            bf16x8 bv[NSUB], av[4];
 #pragma unroll
-                for (int j = 0; j < NSUB; ++j)
-                    bv[j] = *(const bf16x8*)&wl[(j * 16 + r) * kCvWRow + t * 16 + ch];
-                const int base = ((wave + dz + 1) * 6 + dy + 1) * 18 + r + dx + 1;
+            for (int j = 0; j < NSUB; ++j)
+                bv[j] = *(const bf16x8*)(wlb + vB + (j * 16 * kCvWRow + p * 32) * 2);
 #pragma unroll
-                for (int m = 0; m < 4; ++m)
-                    av[m] = *(const bf16x8*)&xs[(base + m * 18) * kCvVox + ch];
-            } else {
-#pragma unroll
-                for (int e = 0; e < 8; ++e) {
-#pragma unroll
-                    for (int j = 0; j < NSUB; ++j) bv[j][e] = (__bf16)0.f;
-#pragma unroll
-                    for (int m = 0; m < 4; ++m) av[m][e] = (__bf16)0.f;
-                }
-            }
+            for (int m = 0; m < 4; ++m)
+                av[m] = *(const bf16x8*)(xsb + va + (toff + m * 18) * kCvVox * 2);
 #pragma unroll
             for (int m = 0; m < 4; ++m)
 #pragma unroll
@@ -1400,10 +1414,12 @@ hipError_t launch_conv(const ConvArgs& a, int coutp, hipStream_t s) {
         const int nb = a.lg >= 5 && nsub == 3 ? 3 : 1;
         const dim3 grid((unsigned)((G / 16) * (G / 4) * (G / kCvPlanes) * a.n), sub / nb);
         const dim3 block(64 * kCvPlanes);
+        ConvArgs b = a;
+        b.wrows = coutp;
         if (nb == 3)
-            hipLaunchKernelGGL(k_conv_brick<3>, grid, block, 0, s, a);
+            hipLaunchKernelGGL(k_conv_brick<3>, grid, block, 0, s, b);
         else
-            hipLaunchKernelGGL(k_conv_brick<1>, grid, block, 0, s, a);
+            hipLaunchKernelGGL(k_conv_brick<1>, grid, block, 0, s, b);
         return hipGetLastError();
     }
     const int64_t waves4 = (int64_t)ceil_div(M, 64) * (sub / nsub);
