@@ -28,6 +28,7 @@ namespace lbmnn {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) void* lds_void_ptr;  // LDS destination of direct loads
 
 namespace {
 
@@ -607,209 +608,178 @@ __global__ void __launch_bounds__(256, 2) k_wgrad_brick(WgradArgs a, int64_t bri
     }
 }
 
-// Weight gradient on the same bricks with one copy of the input halo, for
-// 16 and 32 output channels.  Partial sums, bias product and reduction are
-// those of k_wgrad_brick; what differs:
-//   - the halo is stored once per channel, as 24 rows (hz, hy) of 18 cells
-//     (x0 - 1 .. x0 + 16; row stride kHaloRow, channel stride kHaloChan =
-//     1184 bytes, 32 mod 64, so the B reads are free of bank conflicts);
-//   - a block has 3 waves and wave w takes the 9 taps with dz = w - 1.  Per
-//     k step and dy a lane reads cells 8h .. 8h + 11 of its row (h: the
-//     lane's x half) with one 16-byte and one 8-byte LDS read; the B
-//     fragments of dx = -1, +1 are dwords 0-3 and 1-4 of those cells, the
-//     one of dx = 0 the byte-aligned dwords in between.
-// Against k_wgrad_brick: a third of the LDS stores and about half the LDS
-// reads per brick.
-constexpr int kHaloRow = 24;
-constexpr int kHaloChan = 24 * kHaloRow + 16;
+// Weight gradient on 16 x 4 x 4 bricks through transposing LDS reads, for
+// 16 and 32 output channels.  dW[tap][co][ci] sums dY[v][co] X[v + tap][ci]
+// over voxels v, so both matrix-core operands need 8 consecutive voxels of one
+// channel per lane, while the tensors are stored channels-last.  The block
+// copies the brick's output gradient and the 18 x 6 x 6 input halo of one
+// 16-channel group into LDS as they are stored (direct-to-LDS loads, 32 bytes
+// per voxel and 16 channels), and ds_read_b64_tr_b16 transposes on the way
+// out: within each 16 lanes, lane 4a + b receives element b of the 8-byte
+// pieces addressed by lanes a, a + 4, a + 8, a + 12.  So when lane L of a
+// group addresses voxel k0 + L / 4, channels 4 (L % 4) .. + 3, lane n gets
+// voxels k0 .. k0 + 3 of channel n: two such reads give an operand fragment.
+// Nine waves, wave w the three taps with dz = w / 3 - 1, dy = w % 3 - 1; a
+// lane's LDS addresses are a register plus a compile-time offset.  Lane groups
+// q and q ^ 1 of a k step take neighbouring rows, and the LDS rows are padded
+// so that their reads fall in opposite halves of the banks (a row of the halo
+// or of a one-group output gradient holds 20 voxels, 640 bytes; of a
+// two-group output gradient 1056 bytes).  Blocks walk a range of bricks
+// (partial sums as k_wgrad_brick).
+constexpr int kWtWaves = 9;
+constexpr int kWtHaloRow = 20;                 // voxels per LDS halo row (18 + 2 padding)
+constexpr int kWtHaloItems = 2 * kWtHaloRow * 6 * 6;  // 16-byte items, padding included
+constexpr int kWtHaloBuf = 23 * 64;            // whole waves of items
+typedef short shortx4 __attribute__((ext_vector_type(4)));
+typedef short shortx8 __attribute__((ext_vector_type(8)));
+typedef __attribute__((address_space(3))) shortx4* lds_shortx4_ptr;
 
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
-typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
-typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ bf16x8 tr_fragment(const char* lds, uint32_t byte0, uint32_t byte1) {
+    const shortx4 lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_shortx4_ptr)(lds + byte0));
+    const shortx4 hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_shortx4_ptr)(lds + byte1));
+    return __builtin_bit_cast(bf16x8, __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7));
+}
 
 template <int RS>
-__global__ void __launch_bounds__(192, RS == 1 ? 3 : 2) k_wgrad_brick3(WgradArgs a, int64_t bricks_per_block) {
-    static_assert(RS == 1 || RS == 2, "96 halo loaders + 32 RS output-gradient loaders");
-    __shared__ __attribute__((aligned(16))) __bf16 xs[16 * kHaloChan];
-    __shared__ __attribute__((aligned(16))) __bf16 dT[RS * 16][kDTRow];
+__global__ void __launch_bounds__(64 * kWtWaves) k_wgrad_tr(WgradArgs a, int64_t bricks_per_block) {
+    constexpr int kDyRow = RS == 1 ? 40 : 66;   // 16-byte items per output-gradient row (padded)
+    constexpr int kDyItems = 16 * kDyRow;       // 4 planes x 4 rows
+    constexpr int kDyBuf = (kDyItems + 63) / 64 * 64;
+    // The LDS set: the halo (items 0 ..), the output gradient (from
+    // kWtHaloBuf) and zero padding, every wave issuing kCopies copies.
+    constexpr int kCopies = ((kWtHaloBuf + kDyBuf) / 64 + kWtWaves - 1) / kWtWaves;  // per wave
+    constexpr int kSetItems = kCopies * kWtWaves * 64;
+    constexpr int kDyByte = kWtHaloBuf * 16;  // byte offset of the output gradient in the set
+    __shared__ __attribute__((aligned(16))) __bf16 set[kSetItems * 8];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r = lane & 15, q = lane >> 4;
     const int lg = a.lg, G = 1 << lg;
     const int c0 = blockIdx.x * 16;
-    const int nbx = G >> 4, nby = G >> 2, nbz = G >> 1;
+    const int nbx = G >> 4, nby = G >> 2, nbz = G >> 2;
     const int64_t nbricks = (int64_t)a.n * nbz * nby * nbx;
     const int64_t b0 = (int64_t)blockIdx.y * bricks_per_block;
     const int64_t b1 = b0 + bricks_per_block < nbricks ? b0 + bricks_per_block : nbricks;
-    floatx4 acc[3][3][RS];  // [dy + 1][dx + 1][row tile]
+    floatx4 acc[3][RS];
 #pragma unroll
-    for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
 #pragma unroll
-        for (int j = 0; j < 3; ++j)
-#pragma unroll
-            for (int m = 0; m < RS; ++m) acc[i][j][m] = floatx4{0.f, 0.f, 0.f, 0.f};
+        for (int m = 0; m < RS; ++m) acc[j][m] = floatx4{0.f, 0.f, 0.f, 0.f};
     floatx4 accb[RS];
 #pragma unroll
     for (int m = 0; m < RS; ++m) accb[m] = floatx4{0.f, 0.f, 0.f, 0.f};
     const bool bias_wave = blockIdx.x == 0 && wave == 0;
-    // Roles, one per wave, so that no wave waits on loads issued for
-    // another role into the same registers: threads 0-95 (waves 0 and 1) load
-    // the halo: row hr (hz = hr / 6, hy = hr % 6), channel group cgx, cells 0-7
-    // (hx = 0) or 8-17 (hx = 1).  Lane (r, q) of wave 0 takes row r, channel
-    // group q & 1 and x half q >> 1; lane (r, q) of wave 1 (q < 2) row
-    // 16 + r % 8, channel group r / 8, x half q.  So 16 consecutive lanes
-    // store 48 bytes apart and the second 16 a whole number of 256-byte lines
-    // further (8 kHaloChan), which the LDS serves without bank conflicts.
-    // The first 32 * RS threads of wave 2 load the output gradient (8 cells x
-    // 8 channels).  The global loads of brick b + 1 go into registers before
-    // the matrix-core phase of brick b.
-    const int lr = tid & 15, lq = (tid >> 4) & 3;
-    const int hr = tid < 64 ? lr : 16 + (lr & 7);
-    const int cgx = tid < 64 ? (lq & 1) : lr >> 3;
-    const int hx = tid < 64 ? lq >> 1 : lq & 1;
-    const int td = tid - 128, vgd = td & 15, cgd = td >> 4, sd = vgd >> 2;
-    // The loads go through range-checked buffer resources over one sample of
-    // the channel group's input tensor and of the output gradient: a load at
-    // an offset past the end returns zeros, so a cell outside the grid (or a
-    // channel group past the input channels) needs no branch or select, and
-    // the compiler keeps all of a thread's loads in flight.  The group's
-    // channels lie in one tensor (x1 when c0 < c1s; the plan requires c1s to
-    // be a multiple of 16 when there is an x2).
+    // k value 8 q + 4 h + e of k step s (h: which of the two reads, e = r / 4)
+    // is the brick voxel (plane s / 2, row 2 (s % 2) + q % 2, cell 8 (q / 2) +
+    // 4 h + e); the lane reads channels 4 (r % 4) .. + 3 of it
+    const int e = r >> 2, ac = r & 3;
+    const uint32_t laneA =
+        (uint32_t)(kDyByte + ((q & 1) * kDyRow + (8 * (q >> 1) + e) * 2 * RS) * 16 + ac * 8);
+    const int dzw = wave / 3, dyw = wave % 3;  // this wave's taps: dz + 1, dy + 1
+    const uint32_t laneB = (uint32_t)((((q & 1) + dyw) * kWtHaloRow + dzw * 6 * kWtHaloRow +
+                                       8 * (q >> 1) + e) * 32 + ac * 8);
     const int h = lg - 1;
-    const bool lo = c0 < a.c1s;
+    const bool lo = c0 < a.c1s;  // the group's channels lie in x1 (else x2; c1s is then a multiple of 16)
     const int chans = lo ? a.c1s : a.c2;
-    const int64_t vs = lo ? ((int64_t)1 << (3 * lg)) : ((int64_t)1 << (3 * h));
-    const uint32_t xbytes = (uint32_t)(vs * chans * 2);
-    const uint32_t dbytes = (uint32_t)(((int64_t)1 << (3 * lg)) * a.ys * 2);
-    const int cloc = lo ? c0 : c0 - a.c1s;  // the group's first channel in its tensor
-    bf16x8 reg[8], ext0, ext1;  // ext: cells 16, 17 of the halo row (hx = 1)
-    auto ld16 = [](__amdgpu_buffer_rsrc_t rs, uint32_t off) __attribute__((always_inline)) {
-        return __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
-    };
-    // bit 31 for a load that must read zeros: every tensor sample is below
-    // 2^31 bytes, so the offset then lies past the resource's end (arithmetic,
-    // not a select, which the compiler would turn into a branch)
-    auto oob = [](bool ok) __attribute__((always_inline)) { return (uint32_t)!ok << 31; };
-    auto fetch = [&](int64_t b) __attribute__((always_inline)) {
+    const int hl = lo ? lg : h, sh = lo ? 0 : 1;
+    const int64_t vs = (int64_t)1 << (3 * hl);
+    const int cloc = lo ? c0 : c0 - a.c1s;
+    const int wv = __builtin_amdgcn_readfirstlane(wave);
+    auto issue = [&](int64_t b, __bf16* dst) __attribute__((always_inline)) {
         uint32_t bb = (uint32_t)b;
         const int x0 = (int)(bb % (uint32_t)nbx) * 16;
         bb /= (uint32_t)nbx;
         const int y0 = (int)(bb % (uint32_t)nby) * 4;
         bb /= (uint32_t)nby;
-        const int z0 = (int)(bb % (uint32_t)nbz) * 2;
+        const int z0 = (int)(bb % (uint32_t)nbz) * 4;
         const int smp = (int)(bb / (uint32_t)nbz);
-        if (tid < 96) {
-            const __bf16* xt = (lo ? a.x1 : a.x2) + (int64_t)smp * vs * chans;
-            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-                const_cast<__bf16*>(xt), (short)0, (int)xbytes, 0x00020000);
-            const int yy = y0 + hr % 6 - 1, zz = z0 + hr / 6 - 1, cc = cloc + cgx * 8;
-            const bool row_ok = c0 + cgx * 8 < a.cin && (unsigned)yy < (unsigned)G &&
+        // range-checked buffer resources: positions outside the grid, channel
+        // halves past the input channels, output channels past ys and padding
+        // items read zeros
+        const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<__bf16*>((lo ? a.x1 : a.x2) + (int64_t)smp * vs * chans), (short)0,
+            (int)(uint32_t)(vs * chans * 2), 0x00020000);
+        const __amdgpu_buffer_rsrc_t rd = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<__bf16*>(a.dy + ((int64_t)smp << (3 * lg)) * a.ys), (short)0,
+            (int)(uint32_t)(((int64_t)1 << (3 * lg)) * a.ys * 2), 0x00020000);
+        // copy j of wave w: items (j kWtWaves + w) 64 .. + 63 of the set (the
+        // lane's item decode is redone per brick rather than held in registers)
+        int ln = lane;
+        __asm__ volatile("" : "+v"(ln));
+#pragma unroll
+        for (int j = 0; j < kCopies; ++j) {
+            const int tb = (j * kWtWaves + wv) * 64;
+            if (tb < kWtHaloBuf) {
+                // halo item t: slot t / 2 of 20 x 6 x 6, channel half t % 2
+                const int t = tb + ln;
+                const int half = t & 1, hv = t >> 1;
+                const int hx = hv % kWtHaloRow, hy = (hv / kWtHaloRow) % 6, hz = hv / (6 * kWtHaloRow);
+                const int xx = x0 + hx - 1, yy = y0 + hy - 1, zz = z0 + hz - 1;
+                const bool ok = t < kWtHaloItems && hx < 18 && c0 + half * 8 < a.cin &&
+                                (unsigned)xx < (unsigned)G && (unsigned)yy < (unsigned)G &&
                                 (unsigned)zz < (unsigned)G;
-            const uint32_t rowv = lo ? ((uint32_t)zz << (2 * lg)) + ((uint32_t)yy << lg)
-                                     : ((uint32_t)(zz >> 1) << (2 * h)) + ((uint32_t)(yy >> 1) << h);
-            auto cell = [&](int xx) __attribute__((always_inline)) {
-                const bool ok = row_ok && (unsigned)xx < (unsigned)G;
-                const uint32_t vox = rowv + (uint32_t)(lo ? xx : xx >> 1);
-                return ld16(rs, ((vox * (uint32_t)chans + (uint32_t)cc) * 2u) | oob(ok));
-            };
-            const int xb = x0 - 1 + 8 * hx;
-#pragma unroll
-            for (int m = 0; m < 8; ++m) reg[m] = cell(xb + m);
-            ext0 = cell(xb + 8);  // used by the threads with hx = 1
-            ext1 = cell(xb + 9);
-        } else if (tid >= 128 && tid < 128 + 32 * RS) {
-            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-                const_cast<__bf16*>(a.dy + ((int64_t)smp << (3 * lg)) * a.ys), (short)0,
-                (int)dbytes, 0x00020000);
-            const int yy = y0 + (sd & 1) * 2 + ((vgd & 3) >> 1), zz = z0 + (sd >> 1);
-            const int xb = x0 + (vgd & 1) * 8;
-            const uint32_t v0 = ((uint32_t)zz << (2 * lg)) + ((uint32_t)yy << lg) + (uint32_t)xb;
-            const uint32_t bad = oob(cgd * 8 < a.ys);
-#pragma unroll
-            for (int m = 0; m < 8; ++m)
-                reg[m] = ld16(rs, (((v0 + m) * (uint32_t)a.ys + (uint32_t)(cgd * 8)) * 2u) | bad);
+                const uint32_t vox = ((uint32_t)(zz >> sh) << (2 * hl)) +
+                                     ((uint32_t)(yy >> sh) << hl) + (uint32_t)(xx >> sh);
+                const uint32_t off = ((vox * (uint32_t)chans + (uint32_t)(cloc + half * 8)) * 2u) |
+                                     ((uint32_t)!ok << 31);
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(rx, (lds_void_ptr)&dst[tb * 8], 16, off, 0, 0, 0);
+            } else {
+                // output-gradient item t: row t / kDyRow (4 plane + row), voxel
+                // and 8 channels of item t % kDyRow (the last items of a row
+                // pad); past the output gradient, padding
+                const int t = tb - kWtHaloBuf + ln;
+                const int row = t / kDyRow, it = t - row * kDyRow;
+                const int px = it / (2 * RS), c8 = it % (2 * RS);
+                const uint32_t vox = ((uint32_t)(z0 + ((row >> 2) & 3)) << (2 * lg)) +
+                                     ((uint32_t)(y0 + (row & 3)) << lg) + (uint32_t)(x0 + (px & 15));
+                const bool ok = t < kDyItems && px < 16 && c8 * 8 < a.ys;
+                const uint32_t off = ((vox * (uint32_t)a.ys + (uint32_t)(c8 * 8)) * 2u) |
+                                     ((uint32_t)!ok << 31);
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(rd, (lds_void_ptr)&dst[tb * 8], 16, off, 0, 0, 0);
+            }
         }
     };
-    if (b0 < b1) fetch(b0);
-    for (int64_t b = b0; b < b1; ++b) {
-        if (tid < 96) {
-            __bf16* row = &xs[(cgx * 8) * kHaloChan + hr * kHaloRow + 8 * hx];
+    auto products = [&](const __bf16* src) __attribute__((always_inline)) {
+        const char* sb = (const char*)src;
+        // k step s: plane s / 2, rows 2 (s % 2) + {0, 1}
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                bf16x8 w;
-#pragma unroll
-                for (int j = 0; j < 8; ++j) w[j] = reg[j][e];
-                *(bf16x8*)&row[e * kHaloChan] = w;
-                if (hx) {
-                    bf16x2 t2;
-                    t2[0] = ext0[e];
-                    t2[1] = ext1[e];
-                    *(bf16x2*)&row[e * kHaloChan + 8] = t2;
-                }
-            }
-        } else if (tid >= 128 && tid < 128 + 32 * RS) {
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                bf16x8 w;
-#pragma unroll
-                for (int j = 0; j < 8; ++j) w[j] = reg[j][e];
-                *(bf16x8*)&dT[cgd * 8 + e][vgd * 8] = w;
-            }
-        }
-        __syncthreads();
-        if (b + 1 < b1) fetch(b + 1);
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
+        for (int s = 0; s < 8; ++s) {
+            const int ra = ((s >> 1) * 4 + 2 * (s & 1)) * kDyRow * 16;  // the step's first row
+            const int vb = ((s >> 1) * 6 + 2 * (s & 1)) * kWtHaloRow;  // halo slot of its first cell
             bf16x8 av[RS];
 #pragma unroll
-            for (int m = 0; m < RS; ++m) av[m] = *(const bf16x8*)&dT[m * 16 + r][s * 32 + q * 8];
+            for (int m = 0; m < RS; ++m)
+                av[m] = tr_fragment(sb, laneA + ra + m * 32, laneA + ra + 4 * 32 * RS + m * 32);
             if (bias_wave) {
 #pragma unroll
                 for (int m = 0; m < RS; ++m)
-                    accb[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[m], ones_frag(), accb[m],
-                                                                      0, 0, 0);
+                    accb[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[m], ones_frag(), accb[m], 0, 0, 0);
             }
-            // k step s covers plane s >> 1 and rows (s & 1) * 2 + {0, 1} of the
-            // brick; this lane's row is (s & 1) * 2 + (q >> 1), its x half q & 1
-            const int hz = (s >> 1) + wave, hy0 = (s & 1) * 2 + (q >> 1);
 #pragma unroll
-            for (int i = 0; i < 3; ++i) {
-                const int base = r * kHaloChan + (hz * 6 + hy0 + i) * kHaloRow + (q & 1) * 8;
-                const u32x4 d = __builtin_bit_cast(u32x4, *(const bf16x8*)&xs[base]);
-                // cells 8, 9 as an 8-byte read (4-byte reads at this stride conflict)
-                const u32x2 e45 = __builtin_bit_cast(u32x2, *(const bf16x4*)&xs[base + 8]);
-                const uint32_t e4 = e45[0];
-                const u32x4 mid = {__builtin_amdgcn_alignbyte(d[1], d[0], 2),
-                                   __builtin_amdgcn_alignbyte(d[2], d[1], 2),
-                                   __builtin_amdgcn_alignbyte(d[3], d[2], 2),
-                                   __builtin_amdgcn_alignbyte(e4, d[3], 2)};
-                const u32x4 hi = {d[1], d[2], d[3], e4};
-                const bf16x8 blo = __builtin_bit_cast(bf16x8, d);
-                const bf16x8 bmid = __builtin_bit_cast(bf16x8, mid);
-                const bf16x8 bhi = __builtin_bit_cast(bf16x8, hi);
+            for (int dx = 0; dx < 3; ++dx) {
+                const bf16x8 bv = tr_fragment(sb, laneB + (vb + dx) * 32, laneB + (vb + dx + 4) * 32);
 #pragma unroll
-                for (int m = 0; m < RS; ++m) {
-                    acc[i][0][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[m], blo, acc[i][0][m], 0, 0, 0);
-                    acc[i][1][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[m], bmid, acc[i][1][m], 0, 0, 0);
-                    acc[i][2][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[m], bhi, acc[i][2][m], 0, 0, 0);
-                }
+                for (int m = 0; m < RS; ++m)
+                    acc[dx][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[m], bv, acc[dx][m], 0, 0, 0);
             }
         }
+    };
+    for (int64_t b = b0; b < b1; ++b) {
+        issue(b, set);
+        __builtin_amdgcn_s_waitcnt((7 << 4) | (15 << 8));  // vmcnt 0: this wave's copies landed
+        __syncthreads();
+        products(set);
         __syncthreads();
     }
     const int64_t blk = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
     float* pb = a.part + blk * (27 * RS * 16 * 16);
 #pragma unroll
-    for (int i = 0; i < 3; ++i)
+    for (int dx = 0; dx < 3; ++dx) {
+        const int t = wave * 3 + dx;
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            const int t = wave * 9 + i * 3 + j;
+        for (int m = 0; m < RS; ++m)
 #pragma unroll
-            for (int m = 0; m < RS; ++m)
-#pragma unroll
-                for (int k = 0; k < 4; ++k)
-                    pb[((t * RS + m) * 16 + q * 4 + k) * 16 + r] = acc[i][j][m][k];
-        }
+            for (int k = 0; k < 4; ++k) pb[((t * RS + m) * 16 + q * 4 + k) * 16 + r] = acc[dx][m][k];
+    }
     if (bias_wave && r == 0) {
         float* bb = a.part + a.bias_off + (int64_t)blockIdx.y * (RS * 16);
 #pragma unroll
@@ -1234,8 +1204,6 @@ __device__ constexpr int cv_pair_shift(int p) {
 // the output voxel's (-1, -1, -1) neighbour
 __device__ constexpr int cv_tap_offset(int t) { return (t / 9) * 108 + ((t / 3) % 3) * 18 + t % 3; }
 
-typedef __attribute__((address_space(3))) void* lds_void_ptr;
-
 template <int NSUB>
 __global__ void __launch_bounds__(64 * kCvPlanes)
     __attribute__((amdgpu_waves_per_eu(NSUB == 1 ? 6 : 4))) k_conv_brick(ConvArgs a) {
@@ -1569,13 +1537,34 @@ void finish_plan(WgradPlan* p) {
 constexpr int64_t kPartFloats = 8 << 20;
 constexpr int64_t kPartBlocks = 1024;
 
+// Blocks of k_wgrad_tr<rs> (rs 1 or 2) for one generation on the device:
+// the compute units times the blocks each holds at once, at most 2 (asked
+// once per process; 512 if the runtime cannot say).  With 48-64 registers 3-4
+// fit, but fewer blocks each walking more bricks were faster (64^3, batch 8:
+// 16 -> 16 channels 70 -> 53 us, 32 -> 48 channels 77 -> 53 us): neighbouring
+// bricks of a range share halo cells and output rows in L2.
+int64_t wgrad_tr_resident(int rs) {
+    static int64_t cached[2] = {0, 0};
+    int64_t& c = cached[rs == 2];
+    if (c == 0) {
+        int dev = 0, cus = 0, per = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e == hipSuccess)
+            e = rs == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_wgrad_tr<2>, 64 * kWtWaves, 0)
+                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_wgrad_tr<1>, 64 * kWtWaves, 0);
+        c = e == hipSuccess && cus > 0 && per > 0 ? (int64_t)cus * std::min(per, 2) : 512;
+    }
+    return c;
+}
+
 // (The brick kernel reads the output gradient unmasked: relu != 0 takes the
 // tiled kernel.)
 WgradPlan wgrad_plan(const ConvGeom& g, int relu) {
     WgradPlan p = {};
     const int64_t M = (int64_t)g.n << (3 * g.lg);
     // (8 input channels, the network's first layer, takes a channel group
-    // of 16 whose upper half loads zeros; only k_wgrad_brick3 is checked for
+    // of 16 whose upper half loads zeros; only k_wgrad_tr is checked for
     // that, so 64 output channels need 16.)
     p.brick = !relu && g.lg >= 4 && g.taps == 27 &&
               (g.c2 == 0 || g.c1s % 16 == 0) &&
@@ -1583,10 +1572,13 @@ WgradPlan wgrad_plan(const ConvGeom& g, int relu) {
     if (p.brick) {
         p.rs = g.coutp / 16;
         p.chunks = ceil_div(g.cin, 16);
-        const int64_t nbricks = M / 128;
+        // bricks of 16 x 4 x 4 voxels (k_wgrad_tr) or 16 x 4 x 2 (k_wgrad_brick)
+        const int64_t nbricks = M / (p.rs == 4 ? 128 : 256);
         const int64_t blk_floats = (int64_t)27 * g.coutp * 16;
+        // k_wgrad_tr: one generation of resident blocks
+        const int64_t blocks = p.rs == 4 ? kPartBlocks : wgrad_tr_resident(p.rs);
         const int64_t cap = std::max<int64_t>(
-            1, std::min<int64_t>(kPartBlocks, kPartFloats / blk_floats) / p.chunks);
+            1, std::min<int64_t>(blocks, kPartFloats / blk_floats) / p.chunks);
         const int64_t groups = std::max<int64_t>(1, std::min<int64_t>(nbricks, cap));
         p.per = (nbricks + groups - 1) / groups;
         p.groups = ceil_div(nbricks, p.per);
@@ -1677,8 +1669,8 @@ hipError_t conv_backward_weight(const ConvGeom& g, const __bf16* x1, const __bf1
         const dim3 grid(p.chunks, p.groups);
         switch (p.rs) {
             case 4: hipLaunchKernelGGL(k_wgrad_brick<4>, grid, dim3(256), 0, s, a, p.per); break;
-            case 2: hipLaunchKernelGGL(k_wgrad_brick3<2>, grid, dim3(192), 0, s, a, p.per); break;
-            default: hipLaunchKernelGGL(k_wgrad_brick3<1>, grid, dim3(192), 0, s, a, p.per); break;
+            case 2: hipLaunchKernelGGL(k_wgrad_tr<2>, grid, dim3(64 * kWtWaves), 0, s, a, p.per); break;
+            default: hipLaunchKernelGGL(k_wgrad_tr<1>, grid, dim3(64 * kWtWaves), 0, s, a, p.per); break;
         }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
