@@ -38,9 +38,17 @@ constexpr int kMaxPackLayers = 16;
 hipError_t pack_weights(int layers, const ConvGeom* g, const float* theta, const int64_t* woff,
                         __bf16* const* wp, __bf16* const* wt, hipStream_t s);
 
+// Device FP32 scratch a convolution of geometry g may use (forward or input
+// gradient): 8-cell grids split the products over the input channel groups
+// and keep partial sums there.  0 when no launch needs any.
+int64_t conv_scratch_floats(const ConvGeom& g);
+
 // out = conv(x1, x2) + bias, ReLU if relu; BF16 channels-last [n][v][ys].
+// scratch: scratch_floats device floats (conv_scratch_floats(g) or more), or
+// null (the tiled kernel then runs on 8-cell grids).
 hipError_t conv_forward(const ConvGeom& g, const __bf16* x1, const __bf16* x2, const __bf16* wp,
-                        const float* bias, int relu, __bf16* out, hipStream_t s);
+                        const float* bias, int relu, __bf16* out, float* scratch,
+                        int64_t scratch_floats, hipStream_t s);
 
 // Input gradient: dx[n][v][cin] = sum over taps and co of dy at the
 // neighbour times the weight.  dy is the gradient of the pre-activation
@@ -48,7 +56,8 @@ hipError_t conv_forward(const ConvGeom& g, const __bf16* x1, const __bf16* x2, c
 // the layer that produced x), dx is written as 0 where dxmask <= 0, so the
 // result is again a pre-activation gradient.
 hipError_t conv_backward_data(const ConvGeom& g, const __bf16* dy, const __bf16* wt,
-                              const __bf16* dxmask, __bf16* dx, hipStream_t s);
+                              const __bf16* dxmask, __bf16* dx, float* scratch,
+                              int64_t scratch_floats, hipStream_t s);
 
 // Weight and bias gradients, written into the master layout:
 // dw[co][tap][ci] = sum_v dpre[v][co] x(v + tap)[ci], db[co] = sum_v

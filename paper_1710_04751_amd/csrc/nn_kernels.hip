@@ -1344,6 +1344,135 @@ __global__ void __launch_bounds__(64 * kCvPlanes)
     }
 }
 
+// Forward / input-gradient convolution on grids of 8 cells (3x3x3 taps,
+// input channels a multiple of 16, one input tensor), split over the input
+// channel groups: a block of 8 waves computes one sample's 8 x 8 x 8 outputs
+// (wave w the plane z = w: four 16-voxel tiles of two 8-cell rows) for 16
+// output channels from one 16-channel input group and writes FP32 partial
+// sums, which k_conv_small_sum adds in a fixed order (with the bias, ReLU and
+// mask).  Split this way a 128-channel layer of batch 8 has 512 blocks
+// instead of 64.  The 10 x 10 x 10 halo (channels-last, 32 bytes a voxel)
+// and the group's weights (in the brick convolution's tap-pair order) are
+// copied with direct-to-LDS loads; the pairs' displacements are two planes
+// (200 voxels), two rows (20) or two voxels.
+constexpr int kSmHaloItems = 2 * 1000;   // 16-byte halo items
+constexpr int kSmHaloBuf = 32 * 64;      // whole waves of items
+
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6)))
+k_conv_small(ConvArgs a, float* __restrict__ part) {
+    constexpr int kThreads = 512;
+    constexpr int kWItems = 16 * kCvWItemsRow;
+    constexpr int kWBuf = (kWItems + 63) / 64 * 64;
+    __shared__ __attribute__((aligned(16))) __bf16 xs[kSmHaloBuf * 8];
+    __shared__ __attribute__((aligned(16))) __bf16 wl[kWBuf * 8];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r = lane & 15, q = lane >> 4, hi = q >> 1;
+    const int nch = a.cin / 16;
+    const int smp = blockIdx.x / nch, chunk = blockIdx.x % nch;
+    const int c0 = chunk * 16;
+    const int cobase = blockIdx.y * 16;
+    const int ch = (q & 1) * 8;
+    const int wv = __builtin_amdgcn_readfirstlane(wave);
+    // halo item t (voxel t / 2 of 10 x 10 x 10, channel half t % 2) -> LDS byte 16 t;
+    // positions outside the grid, channel halves past cin and the padding items read zeros
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<__bf16*>(a.x1 + (int64_t)smp * 512 * a.c1s), (short)0, 512 * a.c1s * 2,
+        0x00020000);
+#pragma unroll
+    for (int i = 0; i < kSmHaloBuf / kThreads; ++i) {
+        const int tb = i * kThreads + wv * 64;
+        const int t = tb + lane;
+        const int half = t & 1, hv = t >> 1;
+        const int xx = hv % 10 - 1, yy = (hv / 10) % 10 - 1, zz = hv / 100 - 1;
+        const bool ok = t < kSmHaloItems && c0 + half * 8 < a.cin && (unsigned)xx < 8u &&
+                        (unsigned)yy < 8u && (unsigned)zz < 8u;
+        const uint32_t vox = ((uint32_t)zz << 6) + ((uint32_t)yy << 3) + (uint32_t)xx;
+        const uint32_t off = ((vox * (uint32_t)a.c1s + (uint32_t)(c0 + half * 8)) * 2u) |
+                             ((uint32_t)!ok << 31);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void_ptr)&xs[tb * 8], 16, off, 0, 0, 0);
+    }
+    // weight item t: row t / 58 (output channel cobase + row), tap-pair slot
+    // (t % 58) / 2, channel half t % 2; items 56, 57 of a row pad
+    const __amdgpu_buffer_rsrc_t rw = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<__bf16*>(a.w), (short)0, (int)(uint32_t)((int64_t)a.wrows * a.kpad * 2), 0x00020000);
+#pragma unroll
+    for (int i = 0; i < (kWBuf + kThreads - 1) / kThreads; ++i) {
+        const int tb = i * kThreads + wv * 64;
+        if (tb >= kWBuf) continue;
+        const int t = tb + lane;
+        const int row = t / kCvWItemsRow, rem = t - row * kCvWItemsRow;
+        const int slot = rem >> 1, half = rem & 1, p = slot >> 1;
+        const int tap = (slot & 1) ? cv_pair_tap(p) : p;
+        const bool ok = t < kWItems && rem < 2 * kCvSlots && tap >= 0 && cobase + row < a.wrows;
+        const uint32_t off =
+            ((uint32_t)((cobase + row) * a.kpad + tap * a.cin + c0 + half * 8) * 2u) |
+            ((uint32_t)!ok << 31);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rw, (lds_void_ptr)&wl[tb * 8], 16, off, 0, 0, 0);
+    }
+    __builtin_amdgcn_s_waitcnt((7 << 4) | (15 << 8));  // vmcnt 0: this wave's copies landed
+    __syncthreads();
+    // lane r of tile m is the output voxel (z = w, y = 2 m + r / 8, x = r % 8)
+    const uint32_t lb = (uint32_t)(wave * 100 + (r >> 3) * 10 + (r & 7));
+    const uint32_t vA0 = ((lb + hi * 200) * kCvVox + ch) * 2;
+    const uint32_t vA1 = ((lb + hi * 20) * kCvVox + ch) * 2;
+    const uint32_t vA2 = ((lb + hi * 2) * kCvVox + ch) * 2;
+    const uint32_t vA3 = (lb * kCvVox + ch) * 2;
+    const uint32_t vB = (uint32_t)(r * kCvWRow + hi * 16 + ch) * 2;
+    const char* xsb = (const char*)xs;
+    const char* wlb = (const char*)wl;
+    floatx4 acc[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) acc[m] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int p = 0; p < 14; ++p) {
+        const uint32_t va = p <= 8 ? vA0 : p <= 11 ? vA1 : p == 12 ? vA2 : vA3;
+        const int toff = (p / 9) * 100 + ((p / 3) % 3) * 10 + p % 3;  // halo position of tap p
+        const bf16x8 bv = *(const bf16x8*)(wlb + vB + p * 64);
+        bf16x8 av[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) av[m] = *(const bf16x8*)(xsb + va + (toff + m * 20) * kCvVox * 2);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[m], bv, acc[m], 0, 0, 0);
+    }
+    // D rows 4q .. 4q+3 of tile m are voxels 16 m + 4 q + i of the plane, column r a channel
+    const int Cp = gridDim.y * 16;
+    float* pp = part + ((int64_t)chunk * a.n + smp) * 512 * Cp;
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            pp[(int64_t)(wave * 64 + 16 * m + 4 * q + i) * Cp + cobase + r] = acc[m][i];
+}
+
+// out[v][co] = (ReLU)(bias + sum over the nch input groups of the partials,
+// in group order), 0 where omask <= 0 and for co >= cout; one thread per output.
+__global__ void k_conv_small_sum(const float* __restrict__ part, int nch, int64_t cells, int Cp,
+                                 const float* __restrict__ bias, int relu,
+                                 const __bf16* __restrict__ omask, int cout, int ys,
+                                 __bf16* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cells * ys) return;
+    const int64_t v = i / ys;
+    const int co = (int)(i - v * ys);
+    float val = 0.f;
+    if (co < cout) {
+        float sum = 0.f;
+        for (int c = 0; c < nch; ++c) sum += part[((int64_t)c * cells + v) * Cp + co];
+        val = sum + (bias ? bias[co] : 0.f);
+        if (relu) val = fmaxf(val, 0.f);
+        if (omask && !((float)omask[i] > 0.f)) val = 0.f;
+    }
+    out[i] = (__bf16)val;
+}
+
+// Partial-sum floats k_conv_small needs for the convolution a describes
+// (coutp output rows), or 0 if it does not apply.
+int64_t conv_small_floats(const ConvArgs& a, int coutp) {
+    if (a.lg != 3 || a.taps != 27 || a.c2 != 0 || a.cin % 16 != 0 || a.kpad < 27 * a.cin)
+        return 0;
+    return (int64_t)(a.cin / 16) * a.n * 512 * coutp;
+}
+
 template <int MT, int KS>
 hipError_t launch_conv_mt(const ConvArgs& a, int coutp, hipStream_t s) {
     const int64_t M = (int64_t)a.n << (3 * a.lg);
@@ -1364,9 +1493,24 @@ hipError_t launch_conv_mt(const ConvArgs& a, int coutp, hipStream_t s) {
 // range is split over 2 or 4 waves per block when there are fewer than
 // 4096 or 1024 blocks and at least two steps of 32 per wave (8 waves were
 // measured no faster on the 8^3 layers).
-hipError_t launch_conv(const ConvArgs& a, int coutp, hipStream_t s) {
+hipError_t launch_conv(const ConvArgs& a, int coutp, float* scratch, int64_t scratch_floats,
+                       hipStream_t s) {
     const int64_t M = (int64_t)a.n << (3 * a.lg);
     const int sub = coutp / 16;
+    const int64_t small = conv_small_floats(a, coutp);
+    if (small > 0 && scratch && small <= scratch_floats) {
+        // grids of 8 cells: split over the input channel groups, then summed
+        ConvArgs b = a;
+        b.wrows = coutp;
+        hipLaunchKernelGGL(k_conv_small, dim3(a.n * (a.cin / 16), sub), dim3(512), 0, s, b, scratch);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        const int64_t outs = M * a.ys;
+        hipLaunchKernelGGL(k_conv_small_sum, dim3((unsigned)ceil_div(outs, 256)), dim3(256), 0, s,
+                           scratch, a.cin / 16, M, coutp, a.bias, a.relu, a.omask, a.cout, a.ys,
+                           a.out);
+        return hipGetLastError();
+    }
     const int nsub = sub % 4 == 0 ? 4 : sub % 3 == 0 ? 3 : sub % 2 == 0 ? 2 : 1;
     // (8 input channels, the first layer, take a 16-channel group whose upper
     // half reads zeros; its weight rows there hold the next tap's weights,
@@ -1457,7 +1601,8 @@ hipError_t pack_weights(int layers, const ConvGeom* g, const float* theta, const
 }
 
 hipError_t conv_forward(const ConvGeom& g, const __bf16* x1, const __bf16* x2, const __bf16* wp,
-                        const float* bias, int relu, __bf16* out, hipStream_t s) {
+                        const float* bias, int relu, __bf16* out, float* scratch,
+                        int64_t scratch_floats, hipStream_t s) {
     if (!x1 || !wp || !out || (g.c2 > 0 && (!x2 || g.lg < 1)) || g.c1s % 8 || g.c2 % 8)
         return hipErrorInvalidValue;
     ConvArgs a;
@@ -1478,11 +1623,12 @@ hipError_t conv_forward(const ConvGeom& g, const __bf16* x1, const __bf16* x2, c
     a.cout = g.cout;
     a.ys = g.ys;
     a.relu = relu;
-    return launch_conv(a, g.coutp, s);
+    return launch_conv(a, g.coutp, scratch, scratch_floats, s);
 }
 
 hipError_t conv_backward_data(const ConvGeom& g, const __bf16* dy, const __bf16* wt,
-                              const __bf16* dxmask, __bf16* dx, hipStream_t s) {
+                              const __bf16* dxmask, __bf16* dx, float* scratch,
+                              int64_t scratch_floats, hipStream_t s) {
     if (!dy || !wt || !dx) return hipErrorInvalidValue;
     ConvArgs a;
     a.x1 = dy;
@@ -1502,7 +1648,15 @@ hipError_t conv_backward_data(const ConvGeom& g, const __bf16* dy, const __bf16*
     a.cout = g.cin;
     a.ys = g.cin;
     a.relu = 0;
-    return launch_conv(a, g.cinp, s);
+    return launch_conv(a, g.cinp, scratch, scratch_floats, s);
+}
+
+int64_t conv_scratch_floats(const ConvGeom& g) {
+    ConvArgs f = {};
+    f.n = g.n, f.lg = g.lg, f.taps = g.taps, f.c2 = g.c2, f.cin = g.cin, f.kpad = g.kpad;
+    ConvArgs b = f;
+    b.c2 = 0, b.cin = g.ys, b.kpad = g.kpad_t;
+    return std::max(conv_small_floats(f, g.coutp), conv_small_floats(b, g.cinp));
 }
 
 namespace {

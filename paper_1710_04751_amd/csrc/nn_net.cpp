@@ -63,7 +63,9 @@ struct Layout {
     size_t dact[kLayers];  // gradients of the pre-activations (none for the head)
     size_t in, pool[3], dpool[3], dcat[3];
     size_t partial, loss;
-    size_t wpart;  // weight-gradient partial sums (the largest layer's, or the head's)
+    size_t wpart;  // weight-gradient partial sums (the largest layer's, or the head's);
+                   // also the 8-cell convolutions' partial sums (wpart_floats floats)
+    int64_t wpart_floats;
     size_t total;
 };
 
@@ -144,9 +146,11 @@ Layout make_layout(const lbm_nn_config& c) {
         const LayerDef& d = kDefs[l];
         const ConvGeom g = make_geom(B, lg0 - d.level, d.taps, d.c1, d.c2, d.cout);
         wpart = std::max(wpart, l == kLayers - 1 ? head_scratch_floats(g)
-                                                 : wgrad_scratch_floats(g));
+                                                 : std::max(wgrad_scratch_floats(g),
+                                                            conv_scratch_floats(g)));
     }
     L.wpart = take((size_t)wpart * 4);
+    L.wpart_floats = wpart;
     L.total = o;
     return L;
 }
@@ -211,7 +215,7 @@ lbm_status forward(lbm_nn* nn, int n, const float* log10_ra) {
             break;
         }
         NN_TRY(conv_forward(g, x1, x2, nn->at<__bf16>(L.wp[l]), bias_of(nn, l), kDefs[l].relu,
-                            nn->at<__bf16>(L.act[l]), s),
+                            nn->at<__bf16>(L.act[l]), nn->at<float>(L.wpart), L.wpart_floats, s),
                "conv forward");
         if (l == 1 || l == 3 || l == 5) {
             const int i = (l - 1) / 2;
@@ -261,7 +265,9 @@ lbm_status backward(lbm_nn* nn, int n) {
                 dxmask = kDefs[l - 1].relu ? act(l - 1) : nullptr;
                 break;
         }
-        NN_TRY(conv_backward_data(g, dact(l), nn->at<__bf16>(L.wt[l]), dxmask, dx, s),
+        // (the weight gradient above has finished with wpart: same stream)
+        NN_TRY(conv_backward_data(g, dact(l), nn->at<__bf16>(L.wt[l]), dxmask, dx,
+                                  nn->at<float>(L.wpart), L.wpart_floats, s),
                "data grad");
         if (l == 9 || l == 11 || l == 13) {
             // the upsampled half of the concatenation -> the coarse layer
