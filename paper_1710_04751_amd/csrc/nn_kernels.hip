@@ -446,7 +446,7 @@ __global__ void k_wgrad_reduce(WgradArgs a, int kt, int ct, int nz, int rs, int 
 // (block b = blockIdx.y * gridDim.x + blockIdx.x: [tap][co][16 channels]);
 // wave 0 of the first channel group also sums the output gradient for the
 // bias (a matrix-core product against ones; partials [blockIdx.y][coutp] at
-// bias_off).  k_wgrad_brick_reduce adds the partials up.
+// bias_off).  k_brick_partials_sum adds the partials up.
 constexpr int kBrickRow = 4 * 6 * 16 + 16;  // one channel's halo (hz, hy, x), padded
 
 template <int RS>
@@ -789,39 +789,50 @@ __global__ void __launch_bounds__(64 * kWtWaves) k_wgrad_tr(WgradArgs a, int64_t
     }
 }
 
-// Sum of the k_wgrad_brick partials over the brick ranges, into dw[co][tap]
-// [ci] (zero padding channels dropped) and db.  One group of L lanes per
-// gradient entry of (channel group, tap, co, channel) or per bias entry.
-template <int L>
-__global__ void k_wgrad_brick_reduce(WgradArgs a, int chunks, int groups, int rs, float* dw,
-                                     float* db) {
-    // 32-bit index arithmetic: the host launches fewer than 2^31 lanes
-    const uint32_t per = (uint32_t)(27 * rs * 16 * 16);
-    const uint32_t i = (blockIdx.x * blockDim.x + threadIdx.x) / L;
-    const int j = threadIdx.x % L;
-    if (i < per * (uint32_t)chunks) {
-        const uint32_t chunk = i / per, e = i - chunk * per;
-        const uint32_t t = e / (uint32_t)(rs * 256), rem = e - t * (uint32_t)(rs * 256);
-        const uint32_t co = rem >> 4, cl = rem & 15;
-        const uint32_t cc = chunk * 16 + cl;
-        if (co >= (uint32_t)a.cout || cc >= (uint32_t)a.cin ||
-            (cc < (uint32_t)a.c1s && cc >= (uint32_t)a.c1))
-            return;
-        const uint32_t ci = cc < (uint32_t)a.c1s ? cc : a.c1 + (cc - a.c1s);
-        float sum = 0.f;
+// Sum of the brick kernels' partials over the brick ranges in one pass, into
+// dw[co][tap][ci] (zero padding channels dropped) and db.  A block takes 32
+// entries (consecutive in a partial row) and 8 row lanes: lane j adds rows
+// j, j + 8, ... in order, then a fixed tree adds the 8 lane sums, so every
+// sum has one fixed order.  Blocks past the weight entries take the bias.
+constexpr int kPsEntries = 32, kPsLanes = 8;
+
+__global__ void __launch_bounds__(kPsEntries * kPsLanes)
+k_brick_partials_sum(WgradArgs a, int chunks, int rows, int rs, float* dw, float* db) {
+    __shared__ float red[kPsLanes][kPsEntries + 1];
+    const uint32_t per = (uint32_t)(27 * rs * 16 * 16);  // entries of one channel group
+    const uint32_t W = per * (uint32_t)chunks;           // weight entries of a row
+    const uint32_t nbw = (W + kPsEntries - 1) / kPsEntries;
+    const int el = threadIdx.x % kPsEntries, j = threadIdx.x / kPsEntries;
+    const bool bias = blockIdx.x >= nbw;
+    const uint32_t e = (bias ? blockIdx.x - nbw : blockIdx.x) * kPsEntries + el;
+    const bool valid = bias ? e < (uint32_t)a.cout : e < W;
+    const float* base = bias ? a.part + a.bias_off : a.part;
+    const uint32_t stride = bias ? (uint32_t)(rs * 16) : W;
+    float sum = 0.f;
+    if (valid) {
 #pragma unroll 4
-        for (int g = j; g < groups; g += L)
-            sum += a.part[((int64_t)g * chunks + chunk) * per + e];
-        sum = lane_group_sum<L>(sum);
-        if (j == 0) dw[((int64_t)co * 27 + t) * a.cin_real + ci] = sum;
-    } else if (i < per * (uint32_t)chunks + (uint32_t)a.cout) {
-        const uint32_t co = i - per * (uint32_t)chunks;
-        float sum = 0.f;
-        for (int g = j; g < groups; g += L)
-            sum += a.part[a.bias_off + (int64_t)g * rs * 16 + co];
-        sum = lane_group_sum<L>(sum);
-        if (j == 0) db[co] = sum;
+        for (int g = j; g < rows; g += kPsLanes) sum += base[(int64_t)g * stride + e];
     }
+    red[j][el] = sum;
+    __syncthreads();
+#pragma unroll
+    for (int h = kPsLanes / 2; h > 0; h >>= 1) {
+        if (j < h) red[j][el] += red[j + h][el];
+        __syncthreads();
+    }
+    if (j != 0 || !valid) return;
+    const float v = red[0][el];
+    if (bias) {
+        db[e] = v;
+        return;
+    }
+    const uint32_t chunk = e / per, r0 = e - chunk * per;
+    const uint32_t t = r0 / (uint32_t)(rs * 256), rem = r0 - t * (uint32_t)(rs * 256);
+    const uint32_t co = rem >> 4, cc = chunk * 16 + (rem & 15);
+    if (co >= (uint32_t)a.cout || cc >= (uint32_t)a.cin || (cc < (uint32_t)a.c1s && cc >= (uint32_t)a.c1))
+        return;
+    const uint32_t ci = cc < (uint32_t)a.c1s ? cc : a.c1 + (cc - a.c1s);
+    dw[((int64_t)co * 27 + t) * a.cin_real + ci] = v;
 }
 
 // Packed weight element idx of wp[coutp][kpad] (k = tap * cin + stored
@@ -1741,7 +1752,8 @@ WgradPlan wgrad_plan(const ConvGeom& g, int relu) {
         p.rows = p.groups;
         p.wwidth = (int64_t)p.chunks * blk_floats;
         p.bwidth = g.coutp;
-        finish_plan(&p);
+        p.slices = false;  // one pass (k_brick_partials_sum)
+        p.scratch_floats = p.part_floats;
         return p;
     }
     p.rs = g.coutp >= 64 ? 4 : g.coutp >= 32 ? 2 : 1;
@@ -1828,18 +1840,12 @@ hipError_t conv_backward_weight(const ConvGeom& g, const __bf16* x1, const __bf1
         }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        WgradArgs b;
-        int64_t rows = 0;
-        e = sum_slices(p, a, &b, &rows, s);
-        if (e != hipSuccess) return e;
-        const int64_t nred = (int64_t)27 * g.coutp * 16 * p.chunks + g.cout;
-        if (nred * 8 >= ((int64_t)1 << 31)) return hipErrorInvalidValue;  // 32-bit lane index
-        if (rows >= kRedManyRows)
-            hipLaunchKernelGGL(k_wgrad_brick_reduce<8>, dim3(ceil_div(nred * 8, 256)), dim3(256), 0,
-                               s, b, p.chunks, (int)rows, p.rs, dw, db);
-        else
-            hipLaunchKernelGGL(k_wgrad_brick_reduce<1>, dim3(ceil_div(nred, 256)), dim3(256), 0, s,
-                               b, p.chunks, (int)rows, p.rs, dw, db);
+        const int64_t W = (int64_t)27 * g.coutp * 16 * p.chunks;
+        const int64_t nblk = ceil_div(W, kPsEntries) + ceil_div(g.cout, kPsEntries);
+        if (W >= ((int64_t)1 << 31) || nblk * kPsEntries >= ((int64_t)1 << 31))
+            return hipErrorInvalidValue;  // 32-bit entry index
+        hipLaunchKernelGGL(k_brick_partials_sum, dim3((unsigned)nblk), dim3(kPsEntries * kPsLanes), 0, s,
+                           a, p.chunks, p.groups, p.rs, dw, db);
         return hipGetLastError();
     }
     const dim3 grid(p.kt, p.ct, p.nz);
