@@ -789,6 +789,119 @@ __global__ void __launch_bounds__(64 * kWtWaves) k_wgrad_tr(WgradArgs a, int64_t
     }
 }
 
+// Weight gradient on grids of 8 cells (the bottleneck layers), by the
+// transposing LDS reads of k_wgrad_tr: a block takes one sample, one
+// 16-channel input group and 32 output channels, copies the sample's
+// 10 x 10 x 10 input halo (rows padded to 12 voxels) and the 32 channels of
+// its output gradient (rows of 8 voxels padded to 544 bytes) into LDS, and
+// nine waves (wave w the taps with dz = w / 3 - 1, dy = w % 3 - 1) walk the
+// 16 k steps of 32 voxels (plane s / 2, rows 4 (s % 2) + q for lane group q).
+// Partials per (sample, input group): the layout k_brick_partials_sum adds up
+// (samples as its rows).
+constexpr int kWsHaloRow = 12;                       // voxels per padded halo row
+constexpr int kWsHaloItems = 2 * kWsHaloRow * 10 * 10;  // 2400
+constexpr int kWsHaloBuf = 38 * 64;                  // whole waves
+constexpr int kWsDyRow = 34;                         // 16-byte items per output-gradient row
+constexpr int kWsDyItems = 64 * kWsDyRow;            // 2176 = 34 waves
+constexpr int kWsCopies = (kWsHaloBuf + kWsDyItems) / 64 / kWtWaves;  // 8 per wave
+
+__global__ void __launch_bounds__(64 * kWtWaves) k_wgrad_small(WgradArgs a) {
+    static_assert((kWsHaloBuf + kWsDyItems) / 64 == kWsCopies * kWtWaves, "uniform copies");
+    __shared__ __attribute__((aligned(16))) __bf16 set[(kWsHaloBuf + kWsDyItems) * 8];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r = lane & 15, q = lane >> 4;
+    const int chunk = blockIdx.x, smp = blockIdx.y, cp = blockIdx.z;
+    const int c0 = chunk * 16;
+    const int rsg = a.coutp / 16;  // output-channel tiles of the layer
+    const int wv = __builtin_amdgcn_readfirstlane(wave);
+    const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<__bf16*>(a.x1 + (int64_t)smp * 512 * a.c1s), (short)0, 512 * a.c1s * 2, 0x00020000);
+    const __amdgpu_buffer_rsrc_t rd = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<__bf16*>(a.dy + (int64_t)smp * 512 * a.ys), (short)0, 512 * a.ys * 2, 0x00020000);
+#pragma unroll
+    for (int j = 0; j < kWsCopies; ++j) {
+        const int tb = (j * kWtWaves + wv) * 64;
+        const int t0 = tb + lane;
+        uint32_t off;
+        __amdgpu_buffer_rsrc_t rsrc;
+        if (tb < kWsHaloBuf) {
+            // halo item t: slot t / 2 of 12 x 10 x 10, channel half t % 2
+            const int half = t0 & 1, hv = t0 >> 1;
+            const int hx = hv % kWsHaloRow, hy = (hv / kWsHaloRow) % 10, hz = hv / (10 * kWsHaloRow);
+            const int xx = hx - 1, yy = hy - 1, zz = hz - 1;
+            const bool ok = t0 < kWsHaloItems && hx < 10 && c0 + half * 8 < a.cin && (unsigned)xx < 8u &&
+                            (unsigned)yy < 8u && (unsigned)zz < 8u;
+            const uint32_t vox = ((uint32_t)zz << 6) + ((uint32_t)yy << 3) + (uint32_t)xx;
+            off = ((vox * (uint32_t)a.c1s + (uint32_t)(c0 + half * 8)) * 2u) | ((uint32_t)!ok << 31);
+            rsrc = rx;
+        } else {
+            // output-gradient item t: row t / 34 (8 z + y), voxel and 8 channels of item t % 34
+            const int t = t0 - kWsHaloBuf;
+            const int row = t / kWsDyRow, it = t - row * kWsDyRow;
+            const int px = it >> 2, c8 = it & 3;
+            const int co = cp * 32 + c8 * 8;
+            const bool ok = it < 32 && co < a.ys;
+            const uint32_t vox = ((uint32_t)row << 3) + (uint32_t)(px & 7);
+            off = ((vox * (uint32_t)a.ys + (uint32_t)co) * 2u) | ((uint32_t)!ok << 31);
+            rsrc = rd;
+        }
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc, (lds_void_ptr)&set[tb * 8], 16, off, 0, 0, 0);
+    }
+    __builtin_amdgcn_s_waitcnt((7 << 4) | (15 << 8));  // vmcnt 0: this wave's copies landed
+    __syncthreads();
+    floatx4 acc[3][2], accb[2];
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+        accb[m] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int d = 0; d < 3; ++d) acc[d][m] = floatx4{0.f, 0.f, 0.f, 0.f};
+    }
+    const bool bias_wave = chunk == 0 && wave == 0;
+    const int e = r >> 2, ac = r & 3;
+    const int dzw = wave / 3, dyw = wave % 3;
+    const uint32_t laneA = (uint32_t)(kWsHaloBuf * 16 + (q * kWsDyRow + e * 4) * 16 + ac * 8);
+    const uint32_t laneB = (uint32_t)(((q + dyw) * kWsHaloRow + dzw * 10 * kWsHaloRow + e) * 32 + ac * 8);
+    const char* sb = (const char*)set;
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+        const int ra = ((s >> 1) * 8 + 4 * (s & 1)) * kWsDyRow * 16;  // the step's first row
+        const int vb = ((s >> 1) * 10 + 4 * (s & 1)) * kWsHaloRow;   // halo slot of its first cell
+        bf16x8 av[2];
+#pragma unroll
+        for (int m = 0; m < 2; ++m) av[m] = tr_fragment(sb, laneA + ra + m * 32, laneA + ra + 4 * 64 + m * 32);
+        if (bias_wave) {
+#pragma unroll
+            for (int m = 0; m < 2; ++m)
+                accb[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[m], ones_frag(), accb[m], 0, 0, 0);
+        }
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx) {
+            const bf16x8 bv = tr_fragment(sb, laneB + (vb + dx) * 32, laneB + (vb + dx + 4) * 32);
+#pragma unroll
+            for (int m = 0; m < 2; ++m)
+                acc[dx][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[m], bv, acc[dx][m], 0, 0, 0);
+        }
+    }
+    const int chunks = gridDim.x;
+    float* pb = a.part + ((int64_t)smp * chunks + chunk) * (27 * rsg * 256);
+#pragma unroll
+    for (int dx = 0; dx < 3; ++dx) {
+        const int t = wave * 3 + dx;
+#pragma unroll
+        for (int m = 0; m < 2; ++m)
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                pb[((t * rsg + cp * 2 + m) * 16 + q * 4 + k) * 16 + r] = acc[dx][m][k];
+    }
+    if (bias_wave && r == 0) {
+        float* bb = a.part + a.bias_off + (int64_t)smp * a.coutp + cp * 32;
+#pragma unroll
+        for (int m = 0; m < 2; ++m)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) bb[m * 16 + q * 4 + k] = accb[m][k];
+    }
+}
+
 // Sum of the brick kernels' partials over the brick ranges in one pass, into
 // dw[co][tap][ci] (zero padding channels dropped) and db.  A block takes 32
 // entries (consecutive in a partial row) and 8 row lanes: lane j adds rows
@@ -1677,6 +1790,7 @@ namespace {
 // >= 16) or the tiled kernel, its grid, and the floats of partial sums it
 // writes.
 struct WgradPlan {
+    bool small;          // 8-cell grids: k_wgrad_small, one block per (group, sample, 32 channels)
     bool brick;
     int rs, cs;
     int chunks, groups;  // brick: channel groups x brick ranges
@@ -1731,6 +1845,22 @@ WgradPlan wgrad_plan(const ConvGeom& g, int relu) {
     // (8 input channels, the network's first layer, takes a channel group
     // of 16 whose upper half loads zeros; only k_wgrad_tr is checked for
     // that, so 64 output channels need 16.)
+    p.small = !relu && g.lg == 3 && g.taps == 27 && g.c2 == 0 && g.cin % 16 == 0 &&
+              g.coutp % 32 == 0;
+    if (p.small) {
+        p.rs = g.coutp / 16;
+        p.chunks = g.cin / 16;
+        p.groups = g.n;  // partial rows: one per sample
+        const int64_t blk_floats = (int64_t)27 * g.coutp * 16;
+        p.bias_off = (int64_t)g.n * p.chunks * blk_floats;
+        p.part_floats = p.bias_off + (int64_t)g.n * g.coutp;
+        p.rows = g.n;
+        p.wwidth = (int64_t)p.chunks * blk_floats;
+        p.bwidth = g.coutp;
+        p.slices = false;
+        p.scratch_floats = p.part_floats;
+        return p;
+    }
     p.brick = !relu && g.lg >= 4 && g.taps == 27 &&
               (g.c2 == 0 || g.c1s % 16 == 0) &&
               ((g.cin >= 8 && (g.coutp == 16 || g.coutp == 32)) || (g.cin >= 16 && g.coutp == 64));
@@ -1831,6 +1961,17 @@ hipError_t conv_backward_weight(const ConvGeom& g, const __bf16* x1, const __bf1
     a.relu = relu;
     a.cin_real = g.c1 + g.c2;
     a.vchunk = p.vchunk;
+    if (p.small) {
+        hipLaunchKernelGGL(k_wgrad_small, dim3(p.chunks, g.n, g.coutp / 32), dim3(64 * kWtWaves), 0,
+                           s, a);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        const int64_t W = (int64_t)27 * g.coutp * 16 * p.chunks;
+        const int64_t nblk = ceil_div(W, kPsEntries) + ceil_div(g.cout, kPsEntries);
+        hipLaunchKernelGGL(k_brick_partials_sum, dim3((unsigned)nblk), dim3(kPsEntries * kPsLanes), 0, s,
+                           a, p.chunks, p.groups, p.rs, dw, db);
+        return hipGetLastError();
+    }
     if (p.brick) {
         const dim3 grid(p.chunks, p.groups);
         switch (p.rs) {
