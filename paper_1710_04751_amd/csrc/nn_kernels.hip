@@ -631,7 +631,6 @@ constexpr int kWtHaloRow = 20;                 // voxels per LDS halo row (18 + 
 constexpr int kWtHaloItems = 2 * kWtHaloRow * 6 * 6;  // 16-byte items, padding included
 constexpr int kWtHaloBuf = 23 * 64;            // whole waves of items
 typedef short shortx4 __attribute__((ext_vector_type(4)));
-typedef short shortx8 __attribute__((ext_vector_type(8)));
 typedef __attribute__((address_space(3))) shortx4* lds_shortx4_ptr;
 
 __device__ __forceinline__ bf16x8 tr_fragment(const char* lds, uint32_t byte0, uint32_t byte1) {
