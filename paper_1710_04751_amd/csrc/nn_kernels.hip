@@ -1140,6 +1140,26 @@ __global__ void __launch_bounds__(256) k_head_forward(int n, int lg, const __bf1
     }
 }
 
+// Sum over the 64 lanes of a wave with DPP lane moves (no LDS): pairs and
+// quads by quad permutes, rows of 16 by rotations by 4 and 8, then row 0's
+// sum into row 1 and row 2's into row 3 by the lane-15 broadcast, and row
+// 1's into rows 2 and 3 by the lane-31 broadcast.  Lane 63 receives the
+// total, summed in the same order every time.  Rows left out of a move add 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_moved(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xF, false));
+}
+
+__device__ __forceinline__ float wave_sum_in_last_lane(float v) {
+    v += dpp_moved<0xB1, 0xF>(v);   // quad_perm [1, 0, 3, 2]
+    v += dpp_moved<0x4E, 0xF>(v);   // quad_perm [2, 3, 0, 1]
+    v += dpp_moved<0x124, 0xF>(v);  // row_ror 4
+    v += dpp_moved<0x128, 0xF>(v);  // row_ror 8
+    v += dpp_moved<0x142, 0xA>(v);  // row_bcast 15 (rows 1 and 3)
+    v += dpp_moved<0x143, 0xC>(v);  // row_bcast 31 (rows 2 and 3)
+    return v;
+}
+
 // Loss and the whole backward step of the head in one pass: per voxel the
 // output gradient d = 2 (out - t) / count (t = target times its scale), the
 // input gradient dx[ci] = sum_co w[co][ci] d[co] (0 where the ReLU output x
@@ -1200,14 +1220,12 @@ __global__ void __launch_bounds__(256) k_head_backward(
             g[kHeadOut * kHeadIn + c] += d[c];
         }
     }
-    // the wave's 64 lanes by an xor butterfly, then the 4 waves in order
+    // the wave's 64 lanes by DPP moves, then the 4 waves in order
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int j = 0; j < kHeadGrad; ++j) {
-        float val = g[j];
-#pragma unroll
-        for (int m = 32; m > 0; m >>= 1) val += __shfl_xor(val, m, 64);
-        if (lane == 0) gred[wave][j] = val;
+        const float val = wave_sum_in_last_lane(g[j]);
+        if (lane == 63) gred[wave][j] = val;
     }
     lred[threadIdx.x] = lsum;
     __syncthreads();

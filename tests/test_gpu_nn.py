@@ -341,3 +341,36 @@ def test_gradient_on_the_full_grid(net_mod, N):
     assert not bad, bad
     bad = {k: v[0] for k, v in elem.items() if not v[0] <= 0}
     assert not bad, bad
+
+
+def test_gradient_of_a_repeated_batch(net_mod, N):
+    """Nine copies of one 64^3 sample against that sample alone: the loss
+    is a mean over the batch, so both calls have the same loss and the same
+    gradient.  At nine samples each thread of the head's backward pass takes
+    an odd number of voxel passes (the pass pairs end on a single voxel),
+    and the weight gradients sum over nine times as many voxels.  The loss
+    agrees to 1e-6 (each sample's forward pass is the same arithmetic, the
+    FP64 loss sums are grouped differently); the gradients differ by the
+    BF16 rounding of gradient tensors scaled by 1/9, so each layer's
+    relative L2 difference stays below 2e-2, as against the oracle."""
+    log("case: nn gradient, grid 64, batch 9 of one sample against batch 1")
+    g = 64
+    theta = params(N, 19)
+    rng = np.random.default_rng(20)
+    targets = torch.from_numpy(
+        (0.02 * rng.standard_normal((1, 4, g, g, g))).astype(np.float32)).cuda()
+    tscale = [20.0, 20.0, 20.0, 1.0]
+    res = {}
+    for n in (1, 9):
+        net = net_mod.WarmStartNet(g, n, target_scale=tscale)
+        net.set_params(torch.from_numpy(theta.astype(np.float32)))
+        loss, grad = net.gradient([4.1] * n, targets, [0] * n)
+        res[n] = (loss, to_np(grad).astype(np.float64))
+        net.close()
+    (l1, g1), (l9, g9) = res[1], res[9]
+    rel = per_layer_rel(N, g9, g1)
+    log(f"loss {l9:.9e} vs {l1:.9e}; " +
+        ", ".join(f"{k} {v[0]:.1e}" for k, v in rel.items()))
+    assert abs(l9 - l1) <= 1e-6 * l1
+    bad = {k: v[0] for k, v in rel.items() if not v[0] < 2e-2}
+    assert not bad, bad
