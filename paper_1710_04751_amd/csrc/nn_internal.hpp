@@ -85,8 +85,6 @@ hipError_t upsample_backward(int n, int lg, int c, const __bf16* dcat, int ctot,
 // log10_ra is a host array of n <= kMaxBatch values (passed by value).
 hipError_t make_inputs(int n, int lg, const float* log10_ra, __bf16* x, hipStream_t s);
 
-hipError_t reduce_sum(const double* partial, int n, double* out, hipStream_t s);
-
 // The 1 x 1 x 1 head (16 BF16 input channels -> 4 FP32 outputs) on the
 // vector units with the FP32 master weights w[co][ci] and bias b[co]:
 // out[n][4][v] (channel-first) = (w x + b) * scale4[c] (scale4 NULL: 1).

@@ -903,11 +903,14 @@ __global__ void __launch_bounds__(64 * kWtWaves) k_wgrad_small(WgradArgs a) {
 
 // Sum of the brick kernels' partials over the brick ranges in one pass, into
 // dw[co][tap][ci] (zero padding channels dropped) and db.  A block takes 32
-// entries (consecutive in a partial row) and 8 row lanes: lane j adds rows
-// j, j + 8, ... in order, then a fixed tree adds the 8 lane sums, so every
-// sum has one fixed order.  Blocks past the weight entries take the bias.
-constexpr int kPsEntries = 32, kPsLanes = 8;
+// entries (consecutive in a partial row, 128 bytes) and L row lanes: lane j
+// adds rows j, j + L, ... in order, then a fixed tree adds the L lane sums,
+// so every sum has one fixed order.  Blocks past the weight entries take the
+// bias.  L = 32 for tables of many rows that give few blocks (fewer than two
+// per CU, each summing a long serial chain), else 8.
+constexpr int kPsEntries = 32, kPsTallRows = 256, kPsFewBlocks = 512;
 
+template <int kPsLanes>
 __global__ void __launch_bounds__(kPsEntries * kPsLanes)
 k_brick_partials_sum(WgradArgs a, int chunks, int rows, int rs, float* dw, float* db) {
     __shared__ float red[kPsLanes][kPsEntries + 1];
@@ -1240,35 +1243,39 @@ __global__ void __launch_bounds__(256) k_head_backward(
     if (threadIdx.x == 0) lpart[blockIdx.x] = lred[0];
 }
 
-// out[j] = sum over rows r of in[r][j] (rows x width), one block per column:
-// thread t adds rows t, t + 256, ... in order, then a fixed tree.
-__global__ void __launch_bounds__(256) k_column_sums(const float* __restrict__ in, int rows,
-                                                     int width, float* __restrict__ out) {
-    __shared__ float red[256];
-    const int j = blockIdx.x;
-    float acc = 0.f;
-    for (int r = threadIdx.x; r < rows; r += 256) acc += in[(int64_t)r * width + j];
-    red[threadIdx.x] = acc;
+// The head's block sums in one launch.  Blocks j < width: out[j] = sum over
+// rows r of in[r][j] (rows x width, FP32); the last block: loss = sum of the
+// rows FP64 partials lp.  Thread t adds rows t, t + 256, ... in order, then a
+// fixed tree adds the 256 thread sums.
+template <typename T>
+__device__ __forceinline__ T block_tree_sum(T* red, T v) {
+    red[threadIdx.x] = v;
     __syncthreads();
     for (int m = 128; m > 0; m >>= 1) {
         if ((int)threadIdx.x < m) red[threadIdx.x] += red[threadIdx.x + m];
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[j] = red[0];
+    return red[0];
 }
 
-__global__ void __launch_bounds__(1024) k_reduce(const double* __restrict__ p, int n,
-                                                 double* __restrict__ out) {
-    __shared__ double red[1024];
-    double acc = 0.0;
-    for (int i = threadIdx.x; i < n; i += 1024) acc += p[i];
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    for (int w = 512; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
+__global__ void __launch_bounds__(256) k_head_sums(const float* __restrict__ in, int rows,
+                                                   int width, float* __restrict__ out,
+                                                   const double* __restrict__ lp,
+                                                   double* __restrict__ loss) {
+    __shared__ float redf[256];
+    __shared__ double redd[256];
+    const int j = blockIdx.x;
+    if (j < width) {
+        float acc = 0.f;
+        for (int r = threadIdx.x; r < rows; r += 256) acc += in[(int64_t)r * width + j];
+        const float t = block_tree_sum(redf, acc);
+        if (threadIdx.x == 0) out[j] = t;
+    } else {
+        double acc = 0.0;
+        for (int r = threadIdx.x; r < rows; r += 256) acc += lp[r];
+        const double t = block_tree_sum(redd, acc);
+        if (threadIdx.x == 0) loss[0] = t;
     }
-    if (threadIdx.x == 0) out[0] = red[0];
 }
 
 __global__ void k_adam(int64_t count, float* __restrict__ th, float* __restrict__ m,
@@ -1951,6 +1958,23 @@ int64_t wgrad_scratch_floats(const ConvGeom& g) {
     return std::max(wgrad_plan(g, 0).scratch_floats, wgrad_plan(g, 1).scratch_floats);
 }
 
+// One pass over a brick or 8-cell partial table (rows x W weight entries,
+// then the bias rows).
+hipError_t launch_partials_sum(const WgradArgs& a, int chunks, int rows, int rs, float* dw,
+                               float* db, hipStream_t s) {
+    const int64_t W = (int64_t)27 * rs * 16 * 16 * chunks;
+    const int64_t nblk = ceil_div(W, kPsEntries) + ceil_div(a.cout, kPsEntries);
+    if (W >= ((int64_t)1 << 31) || nblk * kPsEntries >= ((int64_t)1 << 31))
+        return hipErrorInvalidValue;  // 32-bit entry index
+    if (rows >= kPsTallRows && nblk < kPsFewBlocks)
+        hipLaunchKernelGGL(k_brick_partials_sum<32>, dim3((unsigned)nblk), dim3(kPsEntries * 32),
+                           0, s, a, chunks, rows, rs, dw, db);
+    else
+        hipLaunchKernelGGL(k_brick_partials_sum<8>, dim3((unsigned)nblk), dim3(kPsEntries * 8), 0,
+                           s, a, chunks, rows, rs, dw, db);
+    return hipGetLastError();
+}
+
 hipError_t conv_backward_weight(const ConvGeom& g, const __bf16* x1, const __bf16* x2,
                                 const __bf16* dy, const __bf16* y, int relu, float* dw,
                                 float* db, float* scratch, hipStream_t s) {
@@ -1983,11 +2007,7 @@ hipError_t conv_backward_weight(const ConvGeom& g, const __bf16* x1, const __bf1
                            s, a);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        const int64_t W = (int64_t)27 * g.coutp * 16 * p.chunks;
-        const int64_t nblk = ceil_div(W, kPsEntries) + ceil_div(g.cout, kPsEntries);
-        hipLaunchKernelGGL(k_brick_partials_sum, dim3((unsigned)nblk), dim3(kPsEntries * kPsLanes), 0, s,
-                           a, p.chunks, p.groups, p.rs, dw, db);
-        return hipGetLastError();
+        return launch_partials_sum(a, p.chunks, p.groups, p.rs, dw, db, s);
     }
     if (p.brick) {
         const dim3 grid(p.chunks, p.groups);
@@ -1998,13 +2018,7 @@ hipError_t conv_backward_weight(const ConvGeom& g, const __bf16* x1, const __bf1
         }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        const int64_t W = (int64_t)27 * g.coutp * 16 * p.chunks;
-        const int64_t nblk = ceil_div(W, kPsEntries) + ceil_div(g.cout, kPsEntries);
-        if (W >= ((int64_t)1 << 31) || nblk * kPsEntries >= ((int64_t)1 << 31))
-            return hipErrorInvalidValue;  // 32-bit entry index
-        hipLaunchKernelGGL(k_brick_partials_sum, dim3((unsigned)nblk), dim3(kPsEntries * kPsLanes), 0, s,
-                           a, p.chunks, p.groups, p.rs, dw, db);
-        return hipGetLastError();
+        return launch_partials_sum(a, p.chunks, p.groups, p.rs, dw, db, s);
     }
     const dim3 grid(p.kt, p.ct, p.nz);
     switch (p.rs) {
@@ -2064,11 +2078,6 @@ hipError_t make_inputs(int n, int lg, const float* log10_ra, __bf16* x, hipStrea
     return hipGetLastError();
 }
 
-hipError_t reduce_sum(const double* partial, int n, double* out, hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, s, partial, n, out);
-    return hipGetLastError();
-}
-
 bool head_geometry(const ConvGeom& g) {
     return g.taps == 1 && g.c1 == kHeadIn && g.c1s == kHeadIn && g.c2 == 0 && g.cout == kHeadOut;
 }
@@ -2110,11 +2119,9 @@ hipError_t head_backward(const ConvGeom& g, const float* out, const float* targe
                        stride, ts, x, w, chunk, dx, lpartial, scratch);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_column_sums, dim3(kHeadGrad), dim3(256), 0, s, (const float*)scratch, nb,
-                       kHeadGrad, grad);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    return reduce_sum(lpartial, nb, loss, s);
+    hipLaunchKernelGGL(k_head_sums, dim3(kHeadGrad + 1), dim3(256), 0, s, (const float*)scratch,
+                       nb, kHeadGrad, grad, (const double*)lpartial, loss);
+    return hipGetLastError();
 }
 
 hipError_t adam_update(int64_t count, float* theta, float* m, float* v, const float* g, int t,
