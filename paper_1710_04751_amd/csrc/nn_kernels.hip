@@ -27,6 +27,7 @@
 namespace lbmnn {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) void* lds_void_ptr;  // LDS destination of direct loads
 
@@ -973,22 +974,54 @@ __device__ __forceinline__ float pack_wt_elem(const PackLayer& L, int64_t idx,
     return w[((int64_t)co * L.taps + (L.taps - 1 - t)) * L.cin_real + cir];
 }
 
+// The transposed copy is written in tiles of 16 input channels x 64 k
+// entries through LDS: the master weights are read along the input channels
+// (16 consecutive floats per k entry) and wt is written along k (8 bytes per
+// lane, 128 bytes per channel row), instead of one gather per element at the
+// stride of a whole output channel.
+constexpr int kWtTileCi = 16, kWtTileK = 64;
+
 // Every layer's packed and transposed weights in one launch.  Segment 2l is
-// layer l's wp, segment 2l + 1 its wt; each block serves one segment (the
-// first whose cumulative block count exceeds blockIdx.x), so the table is
-// read with block-uniform indices.
+// layer l's wp (8 elements per thread), segment 2l + 1 its wt (one tile per
+// block); each block serves one segment (the first whose cumulative block
+// count exceeds blockIdx.x), so the table is read with block-uniform indices.
 __global__ void __launch_bounds__(256) k_pack_all(PackTable t, const float* __restrict__ theta) {
+    __shared__ float tile[kWtTileK][kWtTileCi + 1];
     int seg = 0;
     while ((int64_t)blockIdx.x >= t.blk[seg]) ++seg;
     const int64_t first = seg ? t.blk[seg - 1] : 0;
-    const int64_t i = ((int64_t)blockIdx.x - first) * 256 + threadIdx.x;
+    const int64_t b = (int64_t)blockIdx.x - first;
     const PackLayer& L = t.l[seg >> 1];
     const float* w = theta + L.woff;
-    if (seg & 1) {
-        if (i < (int64_t)L.cinp * L.kpad_t) L.wt[i] = (__bf16)pack_wt_elem(L, i, w);
-    } else {
-        if (i < (int64_t)L.coutp * L.kpad) L.wp[i] = (__bf16)pack_w_elem(L, i, w);
+    if (!(seg & 1)) {
+        // 8 consecutive k entries per thread (one tap: cin is a multiple of 8), 16 bytes
+        const int64_t i = (b * 256 + threadIdx.x) * 8;
+        if (i >= (int64_t)L.coutp * L.kpad) return;
+        bf16x8 o;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) o[u] = (__bf16)pack_w_elem(L, i + u, w);
+        *(bf16x8*)(L.wp + i) = o;
+        return;
     }
+    const int nkt = (L.kpad_t + kWtTileK - 1) / kWtTileK;
+    const int ci0 = (int)(b / nkt) * kWtTileCi, k0 = (int)(b % nkt) * kWtTileK;
+    {
+        // 4 lanes per k entry, 4 consecutive input channels each
+        const int kk = threadIdx.x >> 2, c4 = (threadIdx.x & 3) * 4;
+        const int k = k0 + kk;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            tile[kk][c4 + u] = k < L.kpad_t ? pack_wt_elem(L, (int64_t)(ci0 + c4 + u) * L.kpad_t + k, w)
+                                            : 0.f;
+    }
+    __syncthreads();
+    // 16 lanes per input channel, 4 consecutive k entries (8 bytes) each
+    const int cl = threadIdx.x >> 4, k4 = (threadIdx.x & 15) * 4;
+    if (k0 + k4 >= L.kpad_t) return;  // kpad_t is a multiple of 4: whole groups
+    bf16x4 o;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) o[u] = (__bf16)tile[k4 + u][cl];
+    *(bf16x4*)(L.wt + (int64_t)(ci0 + cl) * L.kpad_t + k0 + k4) = o;
 }
 
 __device__ __forceinline__ int64_t fine_index(int s, int z, int y, int x, int lg) {
@@ -1739,9 +1772,11 @@ hipError_t pack_weights(int layers, const ConvGeom* g, const float* theta, const
         L.cinp = g[l].cinp;
         L.kpad_t = g[l].kpad_t;
         L.ys = g[l].ys;
-        blocks += ceil_div((int64_t)L.coutp * L.kpad, 256);
+        blocks += ceil_div((int64_t)L.coutp * L.kpad, 256 * 8);
         t.blk[2 * l] = blocks;
-        blocks += ceil_div((int64_t)L.cinp * L.kpad_t, 256);
+        // (kpad is a multiple of 8, cinp of kWtTileCi, kpad_t of 4)
+        if (L.kpad % 8 || L.cinp % kWtTileCi || L.kpad_t % 4) return hipErrorInvalidValue;
+        blocks += (int64_t)(L.cinp / kWtTileCi) * ceil_div((int64_t)L.kpad_t, kWtTileK);
         t.blk[2 * l + 1] = blocks;
     }
     hipLaunchKernelGGL(k_pack_all, dim3((unsigned)blocks), dim3(256), 0, s, t, theta);
