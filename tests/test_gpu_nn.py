@@ -374,3 +374,32 @@ def test_gradient_of_a_repeated_batch(net_mod, N):
     assert abs(l9 - l1) <= 1e-6 * l1
     bad = {k: v[0] for k, v in rel.items() if not v[0] < 2e-2}
     assert not bad, bad
+
+
+def test_packed_weights_follow_adam(net_mod, N):
+    """A training step re-packs the updated weights into their two BF16
+    copies (the packed rows of the forward convolutions and the transposed
+    ones of the input gradients).  After three steps, a second network given
+    the same parameters (which packs them on their own) must compute the
+    same output, loss and gradient, bit for bit."""
+    log("case: nn packed copies after Adam, grid 16")
+    rng = np.random.default_rng(21)
+    targets = torch.from_numpy(
+        (0.1 * rng.standard_normal((2, 4, GRID, GRID, GRID))).astype(np.float32)).cuda()
+    a = net_mod.WarmStartNet(GRID, 2, lr=1e-2)
+    a.set_params(torch.from_numpy(params(N, 22).astype(np.float32)))
+    for _ in range(3):
+        a.train_step(LRA, targets, [1, 0])
+    b = net_mod.WarmStartNet(GRID, 2)
+    b.set_params(a.get_params())
+    res = []
+    for net in (a, b):
+        out = to_np(net.forward(LRA))
+        loss, g = net.gradient(LRA, targets, [0, 1])
+        res.append((out, loss, to_np(g)))
+        net.close()
+    (oa, la, ga), (ob, lb, gb) = res
+    log(f"output max diff {np.abs(oa - ob).max():.1e}, loss {la:.9e} vs {lb:.9e}")
+    assert np.array_equal(oa, ob)
+    assert la == lb
+    assert np.array_equal(ga, gb)
