@@ -297,8 +297,9 @@ lbm_status loss_and_backward(lbm_nn* nn, int n, const float* log10_ra, const flo
     lbm_status st = forward(nn, n, log10_ra);
     if (st != LBM_OK) return st;
     const int h = kLayers - 1;
+    // (every entry of grad is written once below, by the head's sums and each
+    // layer's weight-gradient reduction: no clearing)
     float* grad = nn->at<float>(L.grad);
-    NN_TRY(fill_zero_f32(grad, nn->P, nn->stream), "zero grad");
     NN_TRY(head_backward(nn->geom(h, n), nn->at<float>(L.act[h]), targets, idx, stride,
                          nn->cfg.target_scale, nn->at<__bf16>(L.act[h - 1]),
                          nn->at<float>(L.theta) + nn->off[h], nn->at<__bf16>(L.dact[h - 1]),

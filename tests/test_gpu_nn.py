@@ -403,3 +403,34 @@ def test_packed_weights_follow_adam(net_mod, N):
     assert np.array_equal(oa, ob)
     assert la == lb
     assert np.array_equal(ga, gb)
+
+
+@pytest.mark.parametrize("grid", [16, 64])
+def test_every_gradient_entry_is_written(net_mod, N, grid):
+    """The gradient buffer is not cleared between calls: the head's sums and
+    every layer's weight-gradient reduction write each entry once.  A call
+    after one with other targets must therefore give, bit for bit, what a
+    fresh network gives (an entry left unwritten would keep the first
+    call's value; both networks stay open, so the second cannot reuse the
+    first's memory).  Grid 16 reaches the tiled weight-gradient kernel (4^3
+    and 2^3 levels) and the 8-cell one, grid 64 the brick ones at every
+    level but the 8-cell bottleneck."""
+    log(f"case: nn gradient entries all written, grid {grid}")
+    rng = np.random.default_rng(23)
+    t1, t2 = [torch.from_numpy((0.1 * rng.standard_normal((1, 4, grid, grid, grid)))
+                               .astype(np.float32)).cuda() for _ in range(2)]
+    theta = torch.from_numpy(params(N, 24).astype(np.float32))
+    lra = [3.9]
+    a = net_mod.WarmStartNet(grid, 1)
+    b = net_mod.WarmStartNet(grid, 1)
+    a.set_params(theta)
+    b.set_params(theta)
+    a.gradient(lra, t1, [0])
+    la, ga = a.gradient(lra, t2, [0])
+    lb, gb = b.gradient(lra, t2, [0])
+    ga, gb = to_np(ga), to_np(gb)
+    a.close()
+    b.close()
+    log(f"loss {la:.9e} vs {lb:.9e}; entries differing {int((ga != gb).sum())} of {ga.size}")
+    assert la == lb
+    assert np.array_equal(ga, gb)
