@@ -620,17 +620,20 @@ __global__ void __launch_bounds__(256, 2) k_wgrad_brick(WgradArgs a, int64_t bri
 // pieces addressed by lanes a, a + 4, a + 8, a + 12.  So when lane L of a
 // group addresses voxel k0 + L / 4, channels 4 (L % 4) .. + 3, lane n gets
 // voxels k0 .. k0 + 3 of channel n: two such reads give an operand fragment.
-// Nine waves, wave w the three taps with dz = w / 3 - 1, dy = w % 3 - 1; a
-// lane's LDS addresses are a register plus a compile-time offset.  Lane groups
-// q and q ^ 1 of a k step take neighbouring rows, and the LDS rows are padded
-// so that their reads fall in opposite halves of the banks (a row of the halo
-// or of a one-group output gradient holds 20 voxels, 640 bytes; of a
-// two-group output gradient 1056 bytes).  Blocks walk a range of bricks
-// (partial sums as k_wgrad_brick).
+// Nine waves, wave w the three taps with dz = w / 3 - 1, dy = w % 3 - 1.  Lane
+// groups q and q ^ 1 of a k step take neighbouring rows, and the LDS rows are
+// padded so that their reads fall in opposite halves of the banks (a row of
+// the halo or of a one-group output gradient holds 20 voxels, 640 bytes; of a
+// two-group output gradient 1056 bytes).  A block walks a range of bricks in
+// z order within each (x, y) column; the halo is a ring of 8 plane slots
+// (input plane z in slot z mod 8), so a brick that follows its z neighbour
+// keeps the two planes they share and copies only its 4 new ones.  Partial
+// sums as k_wgrad_brick.
 constexpr int kWtWaves = 9;
 constexpr int kWtHaloRow = 20;                 // voxels per LDS halo row (18 + 2 padding)
-constexpr int kWtHaloItems = 2 * kWtHaloRow * 6 * 6;  // 16-byte items, padding included
-constexpr int kWtHaloBuf = 23 * 64;            // whole waves of items
+constexpr int kWtPlaneItems = 256;             // 16-byte items per plane slot: 6 rows, padding
+constexpr int kWtRing = 8;                     // plane slots
+constexpr int kWtHaloBuf = kWtRing * kWtPlaneItems;
 typedef short shortx4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) shortx4* lds_shortx4_ptr;
 
@@ -645,12 +648,10 @@ __global__ void __launch_bounds__(64 * kWtWaves) k_wgrad_tr(WgradArgs a, int64_t
     constexpr int kDyRow = RS == 1 ? 40 : 66;   // 16-byte items per output-gradient row (padded)
     constexpr int kDyItems = 16 * kDyRow;       // 4 planes x 4 rows
     constexpr int kDyBuf = (kDyItems + 63) / 64 * 64;
-    // The LDS set: the halo (items 0 ..), the output gradient (from
-    // kWtHaloBuf) and zero padding, every wave issuing kCopies copies.
-    constexpr int kCopies = ((kWtHaloBuf + kDyBuf) / 64 + kWtWaves - 1) / kWtWaves;  // per wave
-    constexpr int kSetItems = kCopies * kWtWaves * 64;
-    constexpr int kDyByte = kWtHaloBuf * 16;  // byte offset of the output gradient in the set
-    __shared__ __attribute__((aligned(16))) __bf16 set[kSetItems * 8];
+    constexpr int kDyCopies = kDyBuf / 64;
+    constexpr int kDyByte = kWtHaloBuf * 16;  // byte offset of the output gradient in LDS
+    constexpr int kMaxCopies = 6 * kWtPlaneItems / 64 + kDyCopies;  // a brick with a new halo
+    __shared__ __attribute__((aligned(16))) __bf16 set[(kWtHaloBuf + kDyBuf) * 8];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r = lane & 15, q = lane >> 4;
     const int lg = a.lg, G = 1 << lg;
@@ -675,8 +676,8 @@ __global__ void __launch_bounds__(64 * kWtWaves) k_wgrad_tr(WgradArgs a, int64_t
     const uint32_t laneA =
         (uint32_t)(kDyByte + ((q & 1) * kDyRow + (8 * (q >> 1) + e) * 2 * RS) * 16 + ac * 8);
     const int dzw = wave / 3, dyw = wave % 3;  // this wave's taps: dz + 1, dy + 1
-    const uint32_t laneB = (uint32_t)((((q & 1) + dyw) * kWtHaloRow + dzw * 6 * kWtHaloRow +
-                                       8 * (q >> 1) + e) * 32 + ac * 8);
+    // within a plane slot (the slot's offset is added per brick)
+    const uint32_t laneB = (uint32_t)((((q & 1) + dyw) * kWtHaloRow + 8 * (q >> 1) + e) * 32 + ac * 8);
     const int h = lg - 1;
     const bool lo = c0 < a.c1s;  // the group's channels lie in x1 (else x2; c1s is then a multiple of 16)
     const int chans = lo ? a.c1s : a.c2;
@@ -684,14 +685,27 @@ __global__ void __launch_bounds__(64 * kWtWaves) k_wgrad_tr(WgradArgs a, int64_t
     const int64_t vs = (int64_t)1 << (3 * hl);
     const int cloc = lo ? c0 : c0 - a.c1s;
     const int wv = __builtin_amdgcn_readfirstlane(wave);
-    auto issue = [&](int64_t b, __bf16* dst) __attribute__((always_inline)) {
+    // brick b: z fastest, then x, y, sample
+    auto brick = [&](int64_t b, int& x0, int& y0, int& z0, int& smp) __attribute__((always_inline)) {
         uint32_t bb = (uint32_t)b;
-        const int x0 = (int)(bb % (uint32_t)nbx) * 16;
+        z0 = (int)(bb % (uint32_t)nbz) * 4;
+        bb /= (uint32_t)nbz;
+        x0 = (int)(bb % (uint32_t)nbx) * 16;
         bb /= (uint32_t)nbx;
-        const int y0 = (int)(bb % (uint32_t)nby) * 4;
-        bb /= (uint32_t)nby;
-        const int z0 = (int)(bb % (uint32_t)nbz) * 4;
-        const int smp = (int)(bb / (uint32_t)nbz);
+        y0 = (int)(bb % (uint32_t)nby) * 4;
+        smp = (int)(bb / (uint32_t)nby);
+    };
+    // The copies of brick b: the halo planes z0 - 1 .. z0 + 4 when the brick
+    // starts a run (the block's first, or the first of its column), else
+    // z0 + 1 .. z0 + 4 (the other two are in the ring from the brick before);
+    // then the output gradient.  Copy j goes to wave j % 9.
+    auto issue = [&](int64_t b) __attribute__((always_inline)) {
+        int x0, y0, z0, smp;
+        brick(b, x0, y0, z0, smp);
+        const bool fresh = b == b0 || z0 == 0;
+        const int zfirst = fresh ? z0 - 1 : z0 + 1;
+        const int nh = (fresh ? 6 : 4) * (kWtPlaneItems / 64);  // halo copies
+        const int ncopies = nh + kDyCopies;
         // range-checked buffer resources: positions outside the grid, channel
         // halves past the input channels, output channels past ys and padding
         // items read zeros
@@ -701,32 +715,35 @@ __global__ void __launch_bounds__(64 * kWtWaves) k_wgrad_tr(WgradArgs a, int64_t
         const __amdgpu_buffer_rsrc_t rd = __builtin_amdgcn_make_buffer_rsrc(
             const_cast<__bf16*>(a.dy + ((int64_t)smp << (3 * lg)) * a.ys), (short)0,
             (int)(uint32_t)(((int64_t)1 << (3 * lg)) * a.ys * 2), 0x00020000);
-        // copy j of wave w: items (j kWtWaves + w) 64 .. + 63 of the set (the
-        // lane's item decode is redone per brick rather than held in registers)
+        // (the lane's item decode is redone per brick rather than held in registers)
         int ln = lane;
         __asm__ volatile("" : "+v"(ln));
 #pragma unroll
-        for (int j = 0; j < kCopies; ++j) {
-            const int tb = (j * kWtWaves + wv) * 64;
-            if (tb < kWtHaloBuf) {
-                // halo item t: slot t / 2 of 20 x 6 x 6, channel half t % 2
-                const int t = tb + ln;
+        for (int i = 0; i < (kMaxCopies + kWtWaves - 1) / kWtWaves; ++i) {
+            const int j = i * kWtWaves + wv;
+            if (j >= ncopies) break;
+            if (j < nh) {
+                // halo plane zz = zfirst + j / 4 into slot zz mod 8; item t of
+                // the plane: slot t / 2 of 20 x 6 (t >= 240 pads), channel half t % 2
+                const int zz = zfirst + (j >> 2);
+                const int t = (j & 3) * 64 + ln;
                 const int half = t & 1, hv = t >> 1;
-                const int hx = hv % kWtHaloRow, hy = (hv / kWtHaloRow) % 6, hz = hv / (6 * kWtHaloRow);
-                const int xx = x0 + hx - 1, yy = y0 + hy - 1, zz = z0 + hz - 1;
-                const bool ok = t < kWtHaloItems && hx < 18 && c0 + half * 8 < a.cin &&
+                const int hx = hv % kWtHaloRow, hy = hv / kWtHaloRow;
+                const int xx = x0 + hx - 1, yy = y0 + hy - 1;
+                const bool ok = hy < 6 && hx < 18 && c0 + half * 8 < a.cin &&
                                 (unsigned)xx < (unsigned)G && (unsigned)yy < (unsigned)G &&
                                 (unsigned)zz < (unsigned)G;
                 const uint32_t vox = ((uint32_t)(zz >> sh) << (2 * hl)) +
                                      ((uint32_t)(yy >> sh) << hl) + (uint32_t)(xx >> sh);
                 const uint32_t off = ((vox * (uint32_t)chans + (uint32_t)(cloc + half * 8)) * 2u) |
                                      ((uint32_t)!ok << 31);
-                __builtin_amdgcn_raw_ptr_buffer_load_lds(rx, (lds_void_ptr)&dst[tb * 8], 16, off, 0, 0, 0);
+                const int dst = (zz & (kWtRing - 1)) * kWtPlaneItems + (j & 3) * 64;
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(rx, (lds_void_ptr)&set[dst * 8], 16, off, 0, 0, 0);
             } else {
                 // output-gradient item t: row t / kDyRow (4 plane + row), voxel
                 // and 8 channels of item t % kDyRow (the last items of a row
                 // pad); past the output gradient, padding
-                const int t = tb - kWtHaloBuf + ln;
+                const int t = (j - nh) * 64 + ln;
                 const int row = t / kDyRow, it = t - row * kDyRow;
                 const int px = it / (2 * RS), c8 = it % (2 * RS);
                 const uint32_t vox = ((uint32_t)(z0 + ((row >> 2) & 3)) << (2 * lg)) +
@@ -734,17 +751,25 @@ __global__ void __launch_bounds__(64 * kWtWaves) k_wgrad_tr(WgradArgs a, int64_t
                 const bool ok = t < kDyItems && px < 16 && c8 * 8 < a.ys;
                 const uint32_t off = ((vox * (uint32_t)a.ys + (uint32_t)(c8 * 8)) * 2u) |
                                      ((uint32_t)!ok << 31);
-                __builtin_amdgcn_raw_ptr_buffer_load_lds(rd, (lds_void_ptr)&dst[tb * 8], 16, off, 0, 0, 0);
+                const int dst = kWtHaloBuf + (j - nh) * 64;
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(rd, (lds_void_ptr)&set[dst * 8], 16, off, 0, 0, 0);
             }
         }
     };
-    auto products = [&](const __bf16* src) __attribute__((always_inline)) {
-        const char* sb = (const char*)src;
-        // k step s: plane s / 2, rows 2 (s % 2) + {0, 1}
+    // products of brick b: k step s reads halo plane z0 - 1 + s / 2 + dz + 1
+    auto products = [&](int64_t b) __attribute__((always_inline)) {
+        const char* sb = (const char*)set;
+        const int z0 = (int)((uint32_t)b % (uint32_t)nbz) * 4;
+        uint32_t bp[4];  // the lane's base in the slot of the plane of steps 2 p, 2 p + 1
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            bp[p] = laneB + (uint32_t)(((z0 - 1 + dzw + p) & (kWtRing - 1)) * kWtPlaneItems * 16);
+            __asm__ volatile("" : "+v"(bp[p]));
+        }
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
             const int ra = ((s >> 1) * 4 + 2 * (s & 1)) * kDyRow * 16;  // the step's first row
-            const int vb = ((s >> 1) * 6 + 2 * (s & 1)) * kWtHaloRow;  // halo slot of its first cell
+            const int vb = 2 * (s & 1) * kWtHaloRow;  // slot of the step's first cell in its plane
             bf16x8 av[RS];
 #pragma unroll
             for (int m = 0; m < RS; ++m)
@@ -756,7 +781,8 @@ __global__ void __launch_bounds__(64 * kWtWaves) k_wgrad_tr(WgradArgs a, int64_t
             }
 #pragma unroll
             for (int dx = 0; dx < 3; ++dx) {
-                const bf16x8 bv = tr_fragment(sb, laneB + (vb + dx) * 32, laneB + (vb + dx + 4) * 32);
+                const uint32_t base = bp[s >> 1];
+                const bf16x8 bv = tr_fragment(sb, base + (vb + dx) * 32, base + (vb + dx + 4) * 32);
 #pragma unroll
                 for (int m = 0; m < RS; ++m)
                     acc[dx][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[m], bv, acc[dx][m], 0, 0, 0);
@@ -764,10 +790,10 @@ __global__ void __launch_bounds__(64 * kWtWaves) k_wgrad_tr(WgradArgs a, int64_t
         }
     };
     for (int64_t b = b0; b < b1; ++b) {
-        issue(b, set);
+        issue(b);
         __builtin_amdgcn_s_waitcnt((7 << 4) | (15 << 8));  // vmcnt 0: this wave's copies landed
         __syncthreads();
-        products(set);
+        products(b);
         __syncthreads();
     }
     const int64_t blk = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
