@@ -655,10 +655,18 @@ __global__ void __launch_bounds__(64 * kWtWaves) k_wgrad_tr(WgradArgs a, int64_t
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r = lane & 15, q = lane >> 4;
     const int lg = a.lg, G = 1 << lg;
-    const int c0 = blockIdx.x * 16;
+    // XCD-grouped order: the dispatcher deals consecutive blocks to the 8 XCDs
+    // in turn, so logical block (lin mod 8) (total / 8) + lin / 8 puts runs of
+    // consecutive (range, channel group) pairs on one XCD: the channel groups
+    // of a range share its output gradient, neighbouring ranges their halo
+    // rows, in that XCD's L2
+    const uint32_t total = gridDim.x * gridDim.y, lin = blockIdx.y * gridDim.x + blockIdx.x;
+    const uint32_t lblk = total % 8 ? lin : (lin % 8) * (total / 8) + lin / 8;
+    const int chunk = (int)(lblk % gridDim.x), grp = (int)(lblk / gridDim.x);
+    const int c0 = chunk * 16;
     const int nbx = G >> 4, nby = G >> 2, nbz = G >> 2;
     const int64_t nbricks = (int64_t)a.n * nbz * nby * nbx;
-    const int64_t b0 = (int64_t)blockIdx.y * bricks_per_block;
+    const int64_t b0 = (int64_t)grp * bricks_per_block;
     const int64_t b1 = b0 + bricks_per_block < nbricks ? b0 + bricks_per_block : nbricks;
     floatx4 acc[3][RS];
 #pragma unroll
@@ -668,7 +676,7 @@ __global__ void __launch_bounds__(64 * kWtWaves) k_wgrad_tr(WgradArgs a, int64_t
     floatx4 accb[RS];
 #pragma unroll
     for (int m = 0; m < RS; ++m) accb[m] = floatx4{0.f, 0.f, 0.f, 0.f};
-    const bool bias_wave = blockIdx.x == 0 && wave == 0;
+    const bool bias_wave = chunk == 0 && wave == 0;
     // k value 8 q + 4 h + e of k step s (h: which of the two reads, e = r / 4)
     // is the brick voxel (plane s / 2, row 2 (s % 2) + q % 2, cell 8 (q / 2) +
     // 4 h + e); the lane reads channels 4 (r % 4) .. + 3 of it
@@ -796,7 +804,7 @@ __global__ void __launch_bounds__(64 * kWtWaves) k_wgrad_tr(WgradArgs a, int64_t
         products(b);
         __syncthreads();
     }
-    const int64_t blk = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+    const int64_t blk = (int64_t)grp * gridDim.x + chunk;
     float* pb = a.part + blk * (27 * RS * 16 * 16);
 #pragma unroll
     for (int dx = 0; dx < 3; ++dx) {
@@ -807,7 +815,7 @@ __global__ void __launch_bounds__(64 * kWtWaves) k_wgrad_tr(WgradArgs a, int64_t
             for (int k = 0; k < 4; ++k) pb[((t * RS + m) * 16 + q * 4 + k) * 16 + r] = acc[dx][m][k];
     }
     if (bias_wave && r == 0) {
-        float* bb = a.part + a.bias_off + (int64_t)blockIdx.y * (RS * 16);
+        float* bb = a.part + a.bias_off + (int64_t)grp * (RS * 16);
 #pragma unroll
         for (int m = 0; m < RS; ++m)
 #pragma unroll
