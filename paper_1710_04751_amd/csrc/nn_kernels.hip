@@ -937,41 +937,49 @@ __global__ void __launch_bounds__(64 * kWtWaves) k_wgrad_small(WgradArgs a) {
 }
 
 // Sum of the brick kernels' partials over the brick ranges in one pass, into
-// dw[co][tap][ci] (zero padding channels dropped) and db.  A block takes 32
-// entries (consecutive in a partial row, 128 bytes) and L row lanes: lane j
-// adds rows j, j + L, ... in order, then a fixed tree adds the L lane sums,
-// so every sum has one fixed order.  Blocks past the weight entries take the
-// bias.  L = 32 for tables of many rows that give few blocks (fewer than two
-// per CU, each summing a long serial chain), else 8.
-constexpr int kPsEntries = 32, kPsTallRows = 256, kPsFewBlocks = 512;
+// dw[co][tap][ci] (zero padding channels dropped) and db.  A block takes E
+// entries (consecutive in a partial row) and L row lanes: lane j adds rows j,
+// j + L, ... in order, then a fixed tree adds the L lane sums, so every sum
+// has one fixed order.  Blocks past the weight entries take the bias.  Tables
+// of few rows take L = 1 (256 entries a block, each thread its entry's rows
+// in order, several loads in flight), tall ones that give fewer than two
+// blocks per CU L = 32 (32 entries, 128 bytes of a row), the rest L = 8.
+constexpr int kPsShortRows = 32, kPsTallRows = 256, kPsFewBlocks = 512;
 
-template <int kPsLanes>
-__global__ void __launch_bounds__(kPsEntries * kPsLanes)
+template <int kPsLanes, int kEnt>
+__global__ void __launch_bounds__(kEnt * kPsLanes)
 k_brick_partials_sum(WgradArgs a, int chunks, int rows, int rs, float* dw, float* db) {
-    __shared__ float red[kPsLanes][kPsEntries + 1];
     const uint32_t per = (uint32_t)(27 * rs * 16 * 16);  // entries of one channel group
     const uint32_t W = per * (uint32_t)chunks;           // weight entries of a row
-    const uint32_t nbw = (W + kPsEntries - 1) / kPsEntries;
-    const int el = threadIdx.x % kPsEntries, j = threadIdx.x / kPsEntries;
+    const uint32_t nbw = (W + kEnt - 1) / kEnt;
+    const int el = threadIdx.x % kEnt, j = threadIdx.x / kEnt;
     const bool bias = blockIdx.x >= nbw;
-    const uint32_t e = (bias ? blockIdx.x - nbw : blockIdx.x) * kPsEntries + el;
+    const uint32_t e = (bias ? blockIdx.x - nbw : blockIdx.x) * kEnt + el;
     const bool valid = bias ? e < (uint32_t)a.cout : e < W;
     const float* base = bias ? a.part + a.bias_off : a.part;
     const uint32_t stride = bias ? (uint32_t)(rs * 16) : W;
-    float sum = 0.f;
-    if (valid) {
+    float v = 0.f;
+    if constexpr (kPsLanes == 1) {
+        if (!valid) return;
+#pragma unroll 8
+        for (int g = 0; g < rows; ++g) v += base[(int64_t)g * stride + e];
+    } else {
+        __shared__ float red[kPsLanes][kEnt + 1];
+        float sum = 0.f;
+        if (valid) {
 #pragma unroll 4
-        for (int g = j; g < rows; g += kPsLanes) sum += base[(int64_t)g * stride + e];
-    }
-    red[j][el] = sum;
-    __syncthreads();
-#pragma unroll
-    for (int h = kPsLanes / 2; h > 0; h >>= 1) {
-        if (j < h) red[j][el] += red[j + h][el];
+            for (int g = j; g < rows; g += kPsLanes) sum += base[(int64_t)g * stride + e];
+        }
+        red[j][el] = sum;
         __syncthreads();
+#pragma unroll
+        for (int h = kPsLanes / 2; h > 0; h >>= 1) {
+            if (j < h) red[j][el] += red[j + h][el];
+            __syncthreads();
+        }
+        if (j != 0 || !valid) return;
+        v = red[0][el];
     }
-    if (j != 0 || !valid) return;
-    const float v = red[0][el];
     if (bias) {
         db[e] = v;
         return;
@@ -2032,14 +2040,17 @@ int64_t wgrad_scratch_floats(const ConvGeom& g) {
 hipError_t launch_partials_sum(const WgradArgs& a, int chunks, int rows, int rs, float* dw,
                                float* db, hipStream_t s) {
     const int64_t W = (int64_t)27 * rs * 16 * 16 * chunks;
-    const int64_t nblk = ceil_div(W, kPsEntries) + ceil_div(a.cout, kPsEntries);
-    if (W >= ((int64_t)1 << 31) || nblk * kPsEntries >= ((int64_t)1 << 31))
+    auto blocks = [&](int ent) { return ceil_div(W, ent) + ceil_div(a.cout, ent); };
+    if (W >= ((int64_t)1 << 31) || blocks(32) * 32 >= ((int64_t)1 << 31))
         return hipErrorInvalidValue;  // 32-bit entry index
-    if (rows >= kPsTallRows && nblk < kPsFewBlocks)
-        hipLaunchKernelGGL(k_brick_partials_sum<32>, dim3((unsigned)nblk), dim3(kPsEntries * 32),
-                           0, s, a, chunks, rows, rs, dw, db);
+    if (rows <= kPsShortRows)
+        hipLaunchKernelGGL((k_brick_partials_sum<1, 256>), dim3((unsigned)blocks(256)), dim3(256), 0,
+                           s, a, chunks, rows, rs, dw, db);
+    else if (rows >= kPsTallRows && blocks(32) < kPsFewBlocks)
+        hipLaunchKernelGGL((k_brick_partials_sum<32, 32>), dim3((unsigned)blocks(32)), dim3(1024), 0,
+                           s, a, chunks, rows, rs, dw, db);
     else
-        hipLaunchKernelGGL(k_brick_partials_sum<8>, dim3((unsigned)nblk), dim3(kPsEntries * 8), 0,
+        hipLaunchKernelGGL((k_brick_partials_sum<8, 32>), dim3((unsigned)blocks(32)), dim3(256), 0,
                            s, a, chunks, rows, rs, dw, db);
     return hipGetLastError();
 }
