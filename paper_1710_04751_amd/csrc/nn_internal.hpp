@@ -91,7 +91,8 @@ hipError_t make_inputs(int n, int lg, const float* log10_ra, __bf16* x, hipStrea
 bool head_geometry(const ConvGeom& g);
 hipError_t head_forward(const ConvGeom& g, const __bf16* x, const float* w, const float* b,
                         const float* scale4, float* out, hipStream_t s);
-// Loss and backward step of the head in one pass over the voxels: against
+// Loss and backward step of the head in one pass over the voxels, its output
+// out = w x + b computed on the way (as head_forward computes it): against
 // targets[idx[i]] (channel-first, stride floats apart, times tscale4), the
 // output gradient 2 (out - t) / count, the input gradient dx[n][v][16]
 // (BF16, 0 where x <= 0), the weight and bias gradients (grad: w[4][16] then
@@ -101,10 +102,10 @@ hipError_t head_forward(const ConvGeom& g, const __bf16* x, const float* w, cons
 constexpr int kHeadBlocks = 1024;
 int head_backward_blocks(const ConvGeom& g);
 int64_t head_scratch_floats(const ConvGeom& g);
-hipError_t head_backward(const ConvGeom& g, const float* out, const float* targets,
-                         const int32_t* idx, int64_t stride, const float* tscale4,
-                         const __bf16* x, const float* w, __bf16* dx, float* grad,
-                         float* scratch, double* lpartial, double* loss, hipStream_t s);
+hipError_t head_backward(const ConvGeom& g, const float* targets, const int32_t* idx,
+                         int64_t stride, const float* tscale4, const __bf16* x, const float* w,
+                         const float* b, __bf16* dx, float* grad, float* scratch,
+                         double* lpartial, double* loss, hipStream_t s);
 
 hipError_t adam_update(int64_t count, float* theta, float* m, float* v, const float* g, int t,
                        float lr, float beta1, float beta2, float eps, hipStream_t s);

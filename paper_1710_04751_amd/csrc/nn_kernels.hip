@@ -1239,7 +1239,9 @@ __device__ __forceinline__ float wave_sum_in_last_lane(float v) {
 }
 
 // Loss and the whole backward step of the head in one pass: per voxel the
-// output gradient d = 2 (out - t) / count (t = target times its scale), the
+// head's output out = b + w x (the FMA sequence of k_head_forward, so the
+// same values), the output gradient d = 2 (out - t) / count (t = target
+// times its scale), the
 // input gradient dx[ci] = sum_co w[co][ci] d[co] (0 where the ReLU output x
 // <= 0; written as BF16), and the contributions d[co] x[ci] and d[co] to the
 // weight and bias gradients.  Block b takes voxels [b chunk, (b + 1) chunk);
@@ -1247,8 +1249,8 @@ __device__ __forceinline__ float wave_sum_in_last_lane(float v) {
 // are added over the block in a fixed order and written to lpart[b] and
 // gpart[b][kHeadGrad].
 __global__ void __launch_bounds__(256) k_head_backward(
-    int n, int lg, const float* __restrict__ out, const float* __restrict__ tg, SampleInts idx,
-    int64_t stride, float4 ts, const __bf16* __restrict__ x, const float* __restrict__ w,
+    int n, int lg, const float* __restrict__ tg, SampleInts idx, int64_t stride, float4 ts,
+    const __bf16* __restrict__ x, const float* __restrict__ w, const float* __restrict__ b,
     int64_t chunk, __bf16* __restrict__ dx, double* __restrict__ lpart,
     float* __restrict__ gpart) {
     __shared__ float gred[4][kHeadGrad];
@@ -1266,17 +1268,19 @@ __global__ void __launch_bounds__(256) k_head_backward(
     for (int64_t v = v0 + threadIdx.x; v < v1; v += blockDim.x) {
         const int s = (int)(v >> (3 * lg));
         const int64_t vin = v & (V - 1);
+        float xf[kHeadIn];
+        load_head_input(x, v, xf);
         float d[kHeadOut];
 #pragma unroll
         for (int c = 0; c < kHeadOut; ++c) {
-            const float ov = out[((int64_t)s * kHeadOut + c) * V + vin];
+            float ov = b[c];
+#pragma unroll
+            for (int i = 0; i < kHeadIn; ++i) ov = fmaf(w[c * kHeadIn + i], xf[i], ov);
             const float tv = tg[(int64_t)idx.v[s] * stride + c * V + vin] * tsc[c];
             const double e = (double)ov - (double)tv;
             lsum += e * e;
             d[c] = (float)e * inv;
         }
-        float xf[kHeadIn];
-        load_head_input(x, v, xf);
         bf16x8 lo, hi;
 #pragma unroll
         for (int i = 0; i < kHeadIn; ++i) {
@@ -2182,12 +2186,12 @@ int64_t head_scratch_floats(const ConvGeom& g) {
     return (int64_t)head_backward_blocks(g) * kHeadGrad;
 }
 
-hipError_t head_backward(const ConvGeom& g, const float* out, const float* targets,
-                         const int32_t* idx, int64_t stride, const float* tscale4,
-                         const __bf16* x, const float* w, __bf16* dx, float* grad,
-                         float* scratch, double* lpartial, double* loss, hipStream_t s) {
-    if (!head_geometry(g) || g.n < 1 || g.n > kMaxBatch || !out || !targets || !idx || !x ||
-        !w || !dx || !grad || !scratch || !lpartial || !loss)
+hipError_t head_backward(const ConvGeom& g, const float* targets, const int32_t* idx,
+                         int64_t stride, const float* tscale4, const __bf16* x, const float* w,
+                         const float* b, __bf16* dx, float* grad, float* scratch,
+                         double* lpartial, double* loss, hipStream_t s) {
+    if (!head_geometry(g) || g.n < 1 || g.n > kMaxBatch || !targets || !idx || !x || !w || !b ||
+        !dx || !grad || !scratch || !lpartial || !loss)
         return hipErrorInvalidValue;
     SampleInts ix;
     for (int i = 0; i < kMaxBatch; ++i) ix.v[i] = i < g.n ? idx[i] : 0;
@@ -2195,8 +2199,8 @@ hipError_t head_backward(const ConvGeom& g, const float* out, const float* targe
     const int nb = head_backward_blocks(g);
     const int64_t chunk = (int64_t)ceil_div(M, (int64_t)nb * 256) * 256;
     const float4 ts = make_float4(tscale4[0], tscale4[1], tscale4[2], tscale4[3]);
-    hipLaunchKernelGGL(k_head_backward, dim3(nb), dim3(256), 0, s, g.n, g.lg, out, targets, ix,
-                       stride, ts, x, w, chunk, dx, lpartial, scratch);
+    hipLaunchKernelGGL(k_head_backward, dim3(nb), dim3(256), 0, s, g.n, g.lg, targets, ix, stride,
+                       ts, x, w, b, chunk, dx, lpartial, scratch);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_head_sums, dim3(kHeadGrad + 1), dim3(256), 0, s, (const float*)scratch,

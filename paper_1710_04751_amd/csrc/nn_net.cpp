@@ -199,21 +199,17 @@ void layer_inputs(const lbm_nn* nn, int l, const __bf16** x1, const __bf16** x2)
     }
 }
 
-// Forward pass; the head writes its unscaled FP32 output into act[head].
+// Forward pass up to the head's input act[head - 1].  The head runs where
+// its output is used: into the caller's buffer (lbm_nn_forward), inside the
+// loss and backward step, or into act[head] when that is asked for.
 lbm_status forward(lbm_nn* nn, int n, const float* log10_ra) {
     const Layout& L = nn->lay;
     hipStream_t s = nn->stream;
     NN_TRY(make_inputs(n, nn->lg0, log10_ra, nn->at<__bf16>(L.in), s), "inputs");
-    for (int l = 0; l < kLayers; ++l) {
+    for (int l = 0; l < kLayers - 1; ++l) {
         const ConvGeom g = nn->geom(l, n);
         const __bf16 *x1, *x2;
         layer_inputs(nn, l, &x1, &x2);
-        if (l == kLayers - 1) {
-            NN_TRY(head_forward(g, x1, nn->at<float>(L.theta) + nn->off[l], bias_of(nn, l),
-                                nullptr, nn->at<float>(L.act[l]), s),
-                   "head forward");
-            break;
-        }
         NN_TRY(conv_forward(g, x1, x2, nn->at<__bf16>(L.wp[l]), bias_of(nn, l), kDefs[l].relu,
                             nn->at<__bf16>(L.act[l]), nn->at<float>(L.wpart), L.wpart_floats, s),
                "conv forward");
@@ -300,10 +296,10 @@ lbm_status loss_and_backward(lbm_nn* nn, int n, const float* log10_ra, const flo
     // (every entry of grad is written once below, by the head's sums and each
     // layer's weight-gradient reduction: no clearing)
     float* grad = nn->at<float>(L.grad);
-    NN_TRY(head_backward(nn->geom(h, n), nn->at<float>(L.act[h]), targets, idx, stride,
-                         nn->cfg.target_scale, nn->at<__bf16>(L.act[h - 1]),
-                         nn->at<float>(L.theta) + nn->off[h], nn->at<__bf16>(L.dact[h - 1]),
-                         grad + nn->off[h], nn->at<float>(L.wpart), nn->at<double>(L.partial),
+    NN_TRY(head_backward(nn->geom(h, n), targets, idx, stride, nn->cfg.target_scale,
+                         nn->at<__bf16>(L.act[h - 1]), nn->at<float>(L.theta) + nn->off[h],
+                         bias_of(nn, h), nn->at<__bf16>(L.dact[h - 1]), grad + nn->off[h],
+                         nn->at<float>(L.wpart), nn->at<double>(L.partial),
                          nn->at<double>(L.loss), nn->stream),
            "loss and head backward");
     return backward(nn, n);
@@ -424,7 +420,7 @@ lbm_status lbm_nn_forward(lbm_nn* nn, int32_t n, const float* log10_ra, float* o
     if (!out) return lbm::fail(LBM_ERR_ARG, "null output");
     st = forward(nn, n, log10_ra);
     if (st != LBM_OK) return st;
-    // the head once more, into the caller's buffer with the scale
+    // the head, into the caller's buffer with the scale
     const int h = kLayers - 1;
     NN_TRY(head_forward(nn->geom(h, n), nn->at<__bf16>(nn->lay.act[h - 1]),
                         nn->at<float>(nn->lay.theta) + nn->off[h], bias_of(nn, h), out_scale, out,
@@ -483,6 +479,11 @@ lbm_status lbm_nn_activation(lbm_nn* nn, int32_t layer, int32_t n, float* out) {
     if (nn->last_n < 1) return lbm::fail(LBM_ERR_STATE, "no forward pass yet");
     if (n != nn->last_n) return lbm::fail(LBM_ERR_ARG, "n differs from the last forward pass");
     if (layer == kLayers - 1) {
+        // the head's unscaled output, from its input of the last forward pass
+        NN_TRY(head_forward(nn->geom(layer, n), nn->at<__bf16>(nn->lay.act[layer - 1]),
+                            nn->at<float>(nn->lay.theta) + nn->off[layer], bias_of(nn, layer),
+                            nullptr, nn->at<float>(nn->lay.act[layer]), nn->stream),
+               "head forward");
         NN_TRY(cf_to_cl(nn->at<float>(nn->lay.act[layer]), n, nn->cells(layer, 1), 4, out,
                         nn->stream),
                "activation");
