@@ -108,6 +108,8 @@ lbm_status lbm_nn_set_lr(lbm_nn* nn, float lr);
 /* Output of layer `layer` (0..15 in the order above; 15 is the head,
  * before out_scale) of the last forward pass as FP32 (device), channels-
  * last [n][g][g][g][c] on that layer's grid g; for checking the kernels.
+ * The head's output is computed on this call from its input of that pass
+ * with the current parameters (after lbm_nn_train_step: the updated ones).
  * n must equal the sample count of that pass (LBM_ERR_ARG otherwise). */
 lbm_status lbm_nn_activation(lbm_nn* nn, int32_t layer, int32_t n, float* out);
 
