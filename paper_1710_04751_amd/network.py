@@ -118,7 +118,8 @@ class WarmStartNet:
 
     def activation(self, layer, n):
         """Output of a layer of the last forward pass (n samples), FP32
-        channels-last [n][g][g][g][c] on the layer's grid."""
+        channels-last [n][g][g][g][c] on the layer's grid (the head's from
+        its input of that pass with the current parameters)."""
         level, c = LAYER_OUTPUTS[layer]
         g = self.grid >> level
         out = torch.empty(n, g, g, g, c, dtype=torch.float32, device=self.device)
